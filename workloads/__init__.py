@@ -1,0 +1,86 @@
+"""Seeded synthetic inputs shared by the oracle and the HIP path.
+
+This module only draws random numbers and fixes workload parameters.  It
+holds none of the method's arithmetic (no contraction, no canonicalisation,
+no fit): each side turns these raw inputs into MPS/MPO objects with its own
+code.  Complex Gaussian entries are (N(0,1) + i N(0,1)) / sqrt(2).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def cgauss(rng: np.random.Generator, shape) -> np.ndarray:
+    """Complex Gaussian array, unit variance per entry."""
+    re = rng.standard_normal(shape)
+    im = rng.standard_normal(shape)
+    return (re + 1j * im) / np.sqrt(2.0)
+
+
+def hermitian_stack(seed: int, w: int, D: int) -> np.ndarray:
+    """w Hermitian D x D blocks (G + G^H) / (2 sqrt(D)), complex Gaussian G."""
+    rng = np.random.default_rng(seed)
+    g = cgauss(rng, (w, D, D))
+    return (g + np.conj(np.transpose(g, (0, 2, 1)))) / (2.0 * np.sqrt(D))
+
+
+def unit_vector(seed: int, shape) -> np.ndarray:
+    """Complex Gaussian tensor scaled to unit Frobenius norm."""
+    rng = np.random.default_rng(seed)
+    x = cgauss(rng, shape)
+    return x / np.linalg.norm(x)
+
+
+def random_site_tensors(seed: int, chi, d: int):
+    """Raw complex Gaussian site tensors [chi[j-1], d, chi[j]] for j = 1..N.
+
+    Not canonical; the consumer orthonormalises them with its own code.
+    """
+    rng = np.random.default_rng(seed)
+    return [cgauss(rng, (chi[j], d, chi[j + 1])) for j in range(len(chi) - 1)]
+
+
+def full_rank_bonds(N: int, d: int, cap: int | None = None):
+    """Bond dimensions chi_0..chi_N = min(d^j, d^(N-j)[, cap])."""
+    chi = [min(d ** j, d ** (N - j)) for j in range(N + 1)]
+    if cap is not None:
+        chi = [min(c, cap) for c in chi]
+    return chi
+
+
+# ---------------------------------------------------------------------------
+# Workload parameters (spin-1/2 chains, d = 2).
+# ---------------------------------------------------------------------------
+
+ISING_N10 = dict(  # long-range transverse Ising quench, exact MPO, 1TDVP
+    N=10, d=2, J=1.0, h=1.0, alpha=3.0, dt=0.01, steps=100, chi_cap=32)
+
+HEFF_MICRO = dict(  # two-site effective-Hamiltonian microbenchmark
+    D=(128, 256, 512, 1024), d=2, w=10, alpha=0.75, K=4, fit_rmax=100,
+    seed_L=6127, seed_R=7127, seed_theta=8127)
+
+XXX_N64 = dict(  # 2TDVP sweep, 1/r^2 Heisenberg, fitted with K=6 exponentials
+    N=64, d=2, alpha=2.0, K=6, dt=0.05, steps=40, w_max=1e-8, eps=1e-12,
+    chi_max=512, centre=32)
+
+XY_N201 = dict(  # batched uneven segments, long-range XY
+    N=201, d=2, alpha=1.5, K=6, dt=0.01, segments=[11] + [6] * 30 + [10],
+    chi_lo=64, chi_hi=1024, seed_chi=201, seed_state=202)
+
+ISING_N32_GRAD = dict(  # differentiation workload
+    N=32, d=2, J=1.0, h=1.0, alpha=2.0, K=8, chi_cap=128, dt=0.05, steps=20,
+    seed_state=32, site=16, checkpoint_every=5, fd_step=1e-6)
+
+
+def heff_micro_inputs(D: int, w: int = 10, d: int = 2):
+    """Environments and state for the two-site microbenchmark at bond D.
+
+    Returns (Lk, Rk, theta) with Lk[k] and Rk[k] Hermitian D x D blocks,
+    theta[D, d, d, D] of unit norm.  Lk[k] is indexed [bra, ket] and Rk[k]
+    [ket, bra]; both are Hermitian so the distinction only matters for the
+    layout adapters of each side.
+    """
+    Lk = hermitian_stack(HEFF_MICRO["seed_L"] + D, w, D)
+    Rk = hermitian_stack(HEFF_MICRO["seed_R"] + D, w, D)
+    theta = unit_vector(HEFF_MICRO["seed_theta"] + D, (D, d, d, D))
+    return Lk, Rk, theta
