@@ -1,0 +1,236 @@
+/*
+ * tdvp.h -- C ABI of the MI355X (gfx950) TDVP library.
+ *
+ * Time evolution of matrix product states (MPS) under long-range matrix
+ * product operator (MPO) Hamiltonians by the time-dependent variational
+ * principle, after Secular et al., "Parallel time-dependent variational
+ * principle algorithm for matrix product states" (arXiv:1912.06127).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Sites are 1-based in the documentation and 0-based in `site` arguments.
+ *  - Complex numbers are interleaved (re, im): complex64 = 2 x float,
+ *    complex128 = 2 x double, the layout of torch.complex64/complex128.
+ *  - All arrays are row-major, last index fastest:
+ *      MPS site tensor   A[a][s][b]        [chi_l][d][chi_r]      (Sec. II A)
+ *      two-site state    Theta[a][s1][s2][b]                      (Sec. III A)
+ *      bond matrix       C[a][b]           [chi_l][chi_r]
+ *      MPO site tensor   W[k][l][s'][s]    [w_l][w_r][d][d], s' output (Sec. II C)
+ *      left environment  L[k][a'][a]       [w][chi_bra][chi_ket]  = beta_j[a',k,a]
+ *      right environment R[l][b][b']       [w][chi_ket][chi_bra]  = gamma_j[b',l,b]
+ *  - Every call returns an int status (TDVP_OK = 0).  No call aborts or
+ *    throws across the ABI; a failing call stores a message readable with
+ *    tdvp_last_error(ctx).  Kernel faults are asynchronous and surface at
+ *    the next synchronising call (tdvp_ctx_sync, any host read-back).
+ *  - Raw-pointer calls (apply_heff, env_update) take device pointers owned
+ *    by the caller, enqueue work on the context stream and return without
+ *    synchronising; they neither free nor retain the pointers.
+ *  - Handles (tdvp_ctx, tdvp_mps, tdvp_mpo) are opaque and owned by the
+ *    library until the matching *_destroy call.  A context is used by one
+ *    host thread at a time.
+ */
+#ifndef TDVP_H
+#define TDVP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum tdvp_status {
+    TDVP_OK = 0,
+    TDVP_E_ARG = 1,      /* null pointer, bad enum, negative size */
+    TDVP_E_SHAPE = 2,    /* inconsistent tensor dimensions */
+    TDVP_E_DTYPE = 3,    /* unsupported dtype */
+    TDVP_E_NOMEM = 4,    /* device or host allocation failed */
+    TDVP_E_HIP = 5,      /* HIP runtime or kernel error */
+    TDVP_E_NOCONV = 6,   /* Krylov did not converge (strict mode only) */
+    TDVP_E_NUMERIC = 7,  /* NaN or Inf met */
+    TDVP_E_STATE = 8,    /* object in a state that does not allow the call */
+    TDVP_E_SOLVER = 9    /* dense solver (QR/SVD) reported failure */
+};
+
+typedef enum { TDVP_C64 = 0, TDVP_C128 = 1 } tdvp_dtype;
+
+typedef struct tdvp_ctx_s* tdvp_ctx;
+typedef struct tdvp_mps_s* tdvp_mps;
+typedef struct tdvp_mpo_s* tdvp_mpo;
+
+/* Optional device allocator.  alloc returns a device pointer of at least
+ * `bytes` bytes usable on `stream`, or NULL; free releases it.  With NULL
+ * callbacks the library calls hipMalloc/hipFree itself. */
+typedef void* (*tdvp_alloc_fn)(size_t bytes, void* stream, void* user);
+typedef void (*tdvp_free_fn)(void* ptr, size_t bytes, void* stream, void* user);
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context on HIP device `device` that enqueues all work on
+ * `hip_stream` (a hipStream_t; NULL = the default stream). */
+int tdvp_ctx_create(int device, void* hip_stream, tdvp_alloc_fn alloc_fn,
+                    tdvp_free_fn free_fn, void* user, tdvp_ctx* out);
+int tdvp_ctx_destroy(tdvp_ctx ctx);
+/* Message of the last failing call on this context ("" if none).  The
+ * string stays valid until the next call on the context. */
+const char* tdvp_last_error(tdvp_ctx ctx);
+/* Wait for all work on the context stream; reports asynchronous errors. */
+int tdvp_ctx_sync(tdvp_ctx ctx);
+/* Library version string, e.g. "tdvp-gfx950 0.1". */
+const char* tdvp_version(void);
+
+/* -------------------------------------------------------------------- MPO */
+
+/* Long-range spin-chain Hamiltonian (Sec. II C, Sec. IV):
+ *   H = sum_{i<j} f(j-i) sum_a g_a A_a(i) B_a(j) + h sum_i X(i).
+ * With K > 0, f(r) = Re sum_k c_k lambda_k^r (sum of exponentials,
+ * Sec. II C): bond dimension m = n_terms K + 2.  With K = 0 every distance
+ * r = 1..N-1 has its own chain of bond states and coupling[r-1] = f(r)
+ * (exact MPO, bond dimension n_terms (N-1) + 2).
+ * Operators are d x d complex128 matrices, host memory, [s'][s]. */
+typedef struct {
+    int N;                  /* number of sites, >= 2 */
+    int d;                  /* local dimension */
+    int n_terms;            /* number of long-range terms n_H */
+    const double* g;        /* [n_terms] real prefactors g_a */
+    const double* A_ops;    /* [n_terms][d][d] complex128 */
+    const double* B_ops;    /* [n_terms][d][d] complex128 */
+    int K;                  /* exponentials per term; 0 = exact MPO */
+    const double* c;        /* [K] complex128 weights c_k (K > 0) */
+    const double* lambda;   /* [K] complex128 decay factors lambda_k (K > 0) */
+    const double* coupling; /* [N-1] real f(1..N-1) (K = 0) */
+    const double* onsite;   /* [d][d] complex128 X, or NULL */
+    double h;               /* field strength multiplying X */
+} tdvp_mpo_spec;
+
+int mpo_longrange(tdvp_ctx ctx, const tdvp_mpo_spec* spec, tdvp_mpo* out);
+/* MPO from explicit tensors: w[0..N] bond dimensions (w[0] = w[N] = 1),
+ * W_host the concatenation of the N site tensors [w_j][w_{j+1}][d][d]
+ * complex128 (host). */
+int mpo_from_tensors(tdvp_ctx ctx, int N, int d, const int* w, const double* W_host,
+                     tdvp_mpo* out);
+int mpo_get_info(tdvp_mpo mpo, int* N, int* d, int* w /* [N+1], nullable */);
+int mpo_get_tensor(tdvp_mpo mpo, int site, double* W_host);
+int mpo_destroy(tdvp_mpo mpo);
+
+/* -------------------------------------------------------------------- MPS */
+
+/* MPS with bond dimensions chi[0..N] (chi[0] = chi[N] = 1, chi[j-1] <=
+ * d chi[j]) in right-canonical form with the orthogonality centre on
+ * site 1 (Eqs. mixed-mps1/2).  basis_state[N] (entries in 0..d-1) gives a
+ * product state padded to chi by unit vectors: row 0 of every site holds
+ * the product state, the remaining rows are the unit vectors e_(s,b) in
+ * lexicographic order.  basis_state = NULL gives a random state from
+ * `seed` (complex Gaussian entries, then right-orthonormalised). */
+int mps_init(tdvp_ctx ctx, int N, int d, const int* chi, const int* basis_state,
+             uint64_t seed, tdvp_mps* out);
+int mps_get_info(tdvp_mps mps, int* N, int* d, int* chi /* [N+1], nullable */);
+/* Copy site tensor `site` (0-based) to host as complex128. */
+int mps_get_tensor(tdvp_mps mps, int site, double* host);
+/* Replace site tensor `site` by host complex128 data of shape
+ * [chil][d][chir]; chil/chir must match the neighbours' bonds once all
+ * sets are done.  Invalidates cached environments.  The caller is
+ * responsible for the canonical form that tdvp*_step assumes (sites 2..N
+ * right-orthonormal); mps_right_canonicalize restores it. */
+int mps_set_tensor(tdvp_mps mps, int site, const double* host, int chil, int chir);
+/* Right-orthonormalise sites N..2 by successive LQ decompositions; the
+ * norm stays in site 1. */
+int mps_right_canonicalize(tdvp_ctx ctx, tdvp_mps mps);
+int mps_destroy(tdvp_mps mps);
+
+/* ------------------------------------------------------------- time steps */
+
+typedef struct {
+    tdvp_dtype compute;  /* TDVP_C64: H_eff and environment contractions in
+                            complex FP32 on MFMA (FP32 accumulation), Lanczos,
+                            QR/SVD in FP64.  TDVP_C128: everything FP64. */
+    int krylov_max;      /* maximum Krylov dimension (paper: 8) */
+    double krylov_tol;   /* a-posteriori error tolerance (paper: 1e-6) */
+    int chi_max;         /* maximum bond dimension (2TDVP) */
+    double w_max;        /* maximum discarded weight per SVD, Eq. (discweight) */
+    double eps_rel;      /* relative singular-value cut eps (Sec. III D) */
+    int multiplet_guard; /* 1: never cut inside a degenerate multiplet */
+    int strict;          /* 1: Krylov non-convergence returns TDVP_E_NOCONV */
+    int gemm_form;       /* 0 = default (3M for FP32, 4M for FP64), 3 = 3M, 4 = 4M */
+} tdvp_opts;
+
+typedef struct {
+    double w_step;       /* discarded weight of this step */
+    double w_total;      /* cumulative discarded weight of this MPS */
+    double seconds;      /* host wall time of the call */
+    double flops;        /* algorithmic flops of H_eff and environment work */
+    int chi_peak;        /* largest bond dimension after the step */
+    int matvecs;         /* number of H_eff applications */
+    int krylov_max_used; /* largest Krylov dimension used */
+    int flags;           /* bit 0: a Krylov run hit krylov_max unconverged */
+} tdvp_stats;
+
+/* Fill opts with defaults: C128, krylov_max 40, tol 1e-13, chi_max
+ * 1<<30, w_max 0, eps_rel 0, guard on, strict off, gemm_form 0. */
+int tdvp_opts_default(tdvp_opts* opts);
+
+/* One symmetric one-site TDVP step of size dt (Sec. II D, Eq. proj1site):
+ * forward one-site and backward zero-site updates in a left-to-right and a
+ * right-to-left sweep, the last site evolved once by the full dt.  Bond
+ * dimensions stay fixed.  The MPS must be right-canonical with the centre
+ * on site 1, and is left so. */
+int tdvp1_step(tdvp_ctx ctx, tdvp_mps mps, tdvp_mpo mpo, double dt,
+               const tdvp_opts* opts, tdvp_stats* stats);
+/* One symmetric two-site TDVP step (Sec. II D, Eq. proj2site; Sec. III A):
+ * forward two-site and backward one-site updates, truncated SVD splits
+ * with w_max, chi_max and eps_rel (Sec. III C, III D), the right-most pair
+ * evolved once by the full dt.  Same canonical-form contract as tdvp1_step. */
+int tdvp2_step(tdvp_ctx ctx, tdvp_mps mps, tdvp_mpo mpo, double dt,
+               const tdvp_opts* opts, tdvp_stats* stats);
+
+/* ------------------------------------------------------ raw-pointer kernels */
+
+/* Effective Hamiltonian applied to a local state (Sec. III A, Fig. update;
+ * cost Eq. eqnscaling):
+ *   nsite = 2: out[a'][s1'][s2'][b'] = sum L[k][a'][a] W1[k][l][s1'][s1]
+ *              W2[l][n][s2'][s2] R[n][b][b'] theta[a][s1][s2][b]
+ *              (W1: [wl][wm][d][d], W2: [wm][wr][d][d], L: [wl][chil][chil],
+ *               R: [wr][chir][chir])
+ *   nsite = 1: out[a'][s'][b'] = sum L[k][a'][a] W1[k][l][s'][s] R[l][b][b'] theta[a][s][b]
+ *              (W1: [wl][wr][d][d]; W2 unused, wm ignored)
+ *   nsite = 0: out[a'][b'] = sum_k L[k][a'][a] C[a][b] R[k][b][b'] (bond
+ *              evolution of Eq. proj1site; wl = wr; W1, W2 unused, d ignored)
+ * All device pointers; every tensor has `dtype` (TDVP_C64 computes in FP32
+ * on MFMA with FP32 accumulation, TDVP_C128 in FP64).  W1/W2 are device
+ * copies of the MPO tensors.  `out` must not alias any input. */
+int apply_heff(tdvp_ctx ctx, int nsite, tdvp_dtype dtype, int chil, int chir, int d,
+               int wl, int wm, int wr, const void* L, const void* W1, const void* W2,
+               const void* R, const void* theta, void* out);
+
+/* Environment update (Sec. III A, left-environment figure):
+ *   dir = +1: out[l][b'][b] = sum conj(A[a'][s'][b']) env[k][a'][a] W[k][l][s'][s] A[a][s][b]
+ *             (env = L_j [wl][chil][chil], out = L_{j+1} [wr][chir][chir])
+ *   dir = -1: out[k][a][a'] = sum A[a][s][b] W[k][l][s'][s] env[l][b][b'] conj(A[a'][s'][b'])
+ *             (env = R_j [wr][chir][chir], out = R_{j-1} [wl][chil][chil])
+ * A is [chil][d][chir]; all device pointers of `dtype`. */
+int env_update(tdvp_ctx ctx, int dir, tdvp_dtype dtype, int chil, int chir, int d,
+               int wl, int wr, const void* env_in, const void* A, const void* W,
+               void* env_out);
+
+/* ------------------------------------------------------------ observables */
+
+/* <psi|O_i|psi>/<psi|psi> for n (site, O) pairs; sites 0-based, ops
+ * [n][d][d] complex128 host, out [n] complex128 host (Sec. IV). */
+int expect(tdvp_ctx ctx, tdvp_mps mps, int n, const int* sites, const double* ops,
+           double* out);
+/* <psi|O_i O_j|psi>/<psi|psi> for n pairs (equal-time correlator,
+ * Eq. IsingCorrelation without the disconnected part). */
+int expect2(tdvp_ctx ctx, tdvp_mps mps, int n, const int* i, const int* j, const double* Oi,
+            const double* Oj, double* out);
+/* <psi|H|psi>/<psi|psi> with H the MPO; out is complex128 (2 doubles). */
+int energy(tdvp_ctx ctx, tdvp_mps mps, tdvp_mpo mpo, double* out);
+/* <psi|psi> (real). */
+int norm2(tdvp_ctx ctx, tdvp_mps mps, double* out);
+/* <bra|ket> as complex128; infidelity (Sec. IV) follows from it. */
+int overlap(tdvp_ctx ctx, tdvp_mps bra, tdvp_mps ket, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TDVP_H */

@@ -1,0 +1,410 @@
+"""Python binding of the gfx950 TDVP library (argument marshalling only).
+
+Every computation happens in libtdvp.so on the GPU; this module converts
+torch tensors and numpy arrays into pointers and sizes, checks status codes
+and turns them into exceptions.  torch supplies device memory (through the
+caching allocator, handed to the library as allocation callbacks) and the
+stream.
+"""
+from __future__ import annotations
+
+import atexit
+import ctypes as C
+import weakref
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import TDVP_C64, TDVP_C128, MpoSpec, Opts, Stats
+
+
+class TDVPError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_lib.STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _check(ctx_handle, rc: int):
+    if rc != 0:
+        lib = _lib.load()
+        msg = lib.tdvp_last_error(ctx_handle).decode() if ctx_handle else ""
+        raise TDVPError(rc, msg)
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _iptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_int))
+
+
+def _c128(x) -> np.ndarray:
+    """Host complex128 array as contiguous interleaved doubles."""
+    return np.ascontiguousarray(np.asarray(x, dtype=np.complex128)).view(np.float64)
+
+
+_LIVE_CONTEXTS = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all_contexts():
+    # Library objects must be destroyed before their context, and before
+    # torch (whose allocator backs them) is torn down at interpreter exit.
+    for c in list(_LIVE_CONTEXTS):
+        c.close()
+
+
+class Context:
+    """Device, stream and allocator for library calls.
+
+    With ``torch_allocator=True`` the library's device memory comes from
+    torch's caching allocator on the context stream.  Closing the context
+    first closes every MPS and MPO created on it.
+    """
+
+    def __init__(self, device: int = 0, stream: torch.cuda.Stream | None = None,
+                 torch_allocator: bool = True):
+        lib = _lib.load()
+        self._children = weakref.WeakSet()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device available")
+        self.device = device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        self._sizes = {}
+        if torch_allocator:
+            dev = device
+
+            def _alloc(nbytes, stream_ptr, user):
+                try:
+                    return torch.cuda.caching_allocator_alloc(int(nbytes), dev, int(stream_ptr or 0))
+                except Exception:
+                    return None
+
+            def _free(ptr, nbytes, stream_ptr, user):
+                if ptr:
+                    torch.cuda.caching_allocator_delete(int(ptr))
+
+            self._alloc = _lib.ALLOC_FN(_alloc)
+            self._free = _lib.FREE_FN(_free)
+        else:
+            self._alloc = _lib.ALLOC_FN()
+            self._free = _lib.FREE_FN()
+        h = C.c_void_p()
+        rc = lib.tdvp_ctx_create(device, C.c_void_p(self.stream.cuda_stream), self._alloc, self._free,
+                                 None, C.byref(h))
+        if rc != 0:
+            raise TDVPError(rc, "tdvp_ctx_create failed")
+        self.handle = h
+        _LIVE_CONTEXTS.add(self)
+
+    def _adopt(self, obj):
+        if not self.handle:
+            raise RuntimeError("context is closed")
+        self._children.add(obj)
+
+    def sync(self):
+        _check(self.handle, _lib.load().tdvp_ctx_sync(self.handle))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            for child in list(self._children):
+                child.close()
+            _lib.load().tdvp_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.complex64:
+        return TDVP_C64
+    if t.dtype == torch.complex128:
+        return TDVP_C128
+    raise TypeError(f"expected complex64 or complex128, got {t.dtype}")
+
+
+def _dev(t: torch.Tensor, dtype) -> C.c_void_p:
+    if not t.is_cuda or not t.is_contiguous() or t.dtype != dtype:
+        raise ValueError("tensor must be a contiguous device tensor of the common dtype")
+    return C.c_void_p(t.data_ptr())
+
+
+def apply_heff(ctx: Context, L, R, theta, W1=None, W2=None, out=None) -> torch.Tensor:
+    """H_eff theta for a zero-, one- or two-site local state.
+
+    L [wl][chil][chil], R [wr][chir][chir]; theta [chil][chir] (zero-site),
+    [chil][d][chir] (one-site, W1 [wl][wr][d][d]) or [chil][d][d][chir]
+    (two-site, W1 [wl][wm][d][d], W2 [wm][wr][d][d]).
+    """
+    nsite = theta.dim() - 2
+    dt = theta.dtype
+    wl, chil = L.shape[0], L.shape[1]
+    wr, chir = R.shape[0], R.shape[1]
+    d = theta.shape[1] if nsite >= 1 else 1
+    wm = W1.shape[1] if nsite == 2 else wl
+    if out is None:
+        out = torch.empty_like(theta)
+    ptr = lambda t: _dev(t, dt) if t is not None else C.c_void_p()
+    rc = _lib.load().apply_heff(ctx.handle, nsite, _dtype_code(theta), chil, chir, d, wl, wm, wr,
+                                ptr(L), ptr(W1), ptr(W2), ptr(R), ptr(theta), ptr(out))
+    _check(ctx.handle, rc)
+    return out
+
+
+def env_update(ctx: Context, direction: int, env, A, W, out=None) -> torch.Tensor:
+    """Left (direction=+1) or right (-1) environment update with site tensor A [chil][d][chir]."""
+    dt = A.dtype
+    chil, d, chir = A.shape
+    wl, wr = W.shape[0], W.shape[1]
+    if out is None:
+        shape = (wr, chir, chir) if direction == 1 else (wl, chil, chil)
+        out = torch.empty(shape, dtype=dt, device=A.device)
+    rc = _lib.load().env_update(ctx.handle, direction, _dtype_code(A), chil, chir, d, wl, wr,
+                                _dev(env, dt), _dev(A, dt), _dev(W, dt), _dev(out, dt))
+    _check(ctx.handle, rc)
+    return out
+
+
+class MPO:
+    """Long-range Hamiltonian MPO held by the library (Sec. II C)."""
+
+    def __init__(self, ctx: Context, handle):
+        self.ctx = ctx
+        self.handle = handle
+        ctx._adopt(self)
+        lib = _lib.load()
+        N, d = C.c_int(), C.c_int()
+        _check(ctx.handle, lib.mpo_get_info(handle, C.byref(N), C.byref(d), None))
+        self.N, self.d = N.value, d.value
+        w = np.zeros(self.N + 1, dtype=np.int32)
+        _check(ctx.handle, lib.mpo_get_info(handle, None, None, _iptr(w)))
+        self.w = [int(x) for x in w]
+
+    @classmethod
+    def longrange(cls, ctx: Context, N: int, pairs, *, c=None, lam=None, coupling=None,
+                  onsite=None, h: float = 0.0):
+        """sum_{i<j} f(j-i) sum_a g_a A_a(i) B_a(j) + h sum X(i).
+
+        pairs: list of (g_a, A_a, B_a).  Either (c, lam) for f(r) = Re sum
+        c_k lam_k^r, or coupling = [f(1), ..., f(N-1)] for the exact MPO.
+        """
+        d = np.asarray(pairs[0][1]).shape[0] if pairs else np.asarray(onsite).shape[0]
+        g = np.array([p[0] for p in pairs], dtype=np.float64)
+        Aops = _c128(np.array([p[1] for p in pairs]).reshape(-1, d, d)) if pairs else np.zeros(2)
+        Bops = _c128(np.array([p[2] for p in pairs]).reshape(-1, d, d)) if pairs else np.zeros(2)
+        spec = MpoSpec()
+        spec.N, spec.d, spec.n_terms = N, d, len(pairs)
+        spec.g, spec.A_ops, spec.B_ops = _dptr(g), _dptr(Aops), _dptr(Bops)
+        keep = [g, Aops, Bops]
+        if c is not None:
+            cc, ll = _c128(c), _c128(lam)
+            keep += [cc, ll]
+            spec.K, spec.c, spec.lam = len(np.atleast_1d(c)), _dptr(cc), _dptr(ll)
+        else:
+            cp = np.ascontiguousarray(coupling, dtype=np.float64)
+            keep.append(cp)
+            spec.K, spec.coupling = 0, _dptr(cp)
+        if onsite is not None:
+            on = _c128(onsite)
+            keep.append(on)
+            spec.onsite, spec.h = _dptr(on), float(h)
+        h_ = C.c_void_p()
+        _check(ctx.handle, _lib.load().mpo_longrange(ctx.handle, C.byref(spec), C.byref(h_)))
+        return cls(ctx, h_)
+
+    @classmethod
+    def from_tensors(cls, ctx: Context, Ws):
+        N = len(Ws)
+        d = Ws[0].shape[2]
+        w = np.array([1] + [W.shape[1] for W in Ws], dtype=np.int32)
+        flat = np.concatenate([_c128(W).reshape(-1) for W in Ws])
+        h_ = C.c_void_p()
+        _check(ctx.handle, _lib.load().mpo_from_tensors(ctx.handle, N, d, _iptr(w), _dptr(flat), C.byref(h_)))
+        return cls(ctx, h_)
+
+    def tensor(self, site: int) -> np.ndarray:
+        shape = (self.w[site], self.w[site + 1], self.d, self.d)
+        out = np.zeros(shape, dtype=np.complex128)
+        _check(self.ctx.handle, _lib.load().mpo_get_tensor(self.handle, site, _dptr(out.view(np.float64))))
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            if self.ctx.handle:  # otherwise the context already released it
+                _lib.load().mpo_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class MPS:
+    """MPS held by the library in right-canonical form, centre on site 1."""
+
+    def __init__(self, ctx: Context, handle):
+        self.ctx = ctx
+        self.handle = handle
+        ctx._adopt(self)
+        N, d = C.c_int(), C.c_int()
+        _check(ctx.handle, _lib.load().mps_get_info(handle, C.byref(N), C.byref(d), None))
+        self.N, self.d = N.value, d.value
+
+    @classmethod
+    def init(cls, ctx: Context, N: int, d: int, chi, basis_state=None, seed: int = 0):
+        chi = np.ascontiguousarray(chi, dtype=np.int32)
+        bs = None if basis_state is None else np.ascontiguousarray(basis_state, dtype=np.int32)
+        h_ = C.c_void_p()
+        rc = _lib.load().mps_init(ctx.handle, N, d, _iptr(chi), None if bs is None else _iptr(bs),
+                                  C.c_uint64(seed), C.byref(h_))
+        _check(ctx.handle, rc)
+        return cls(ctx, h_)
+
+    @classmethod
+    def from_tensors(cls, ctx: Context, tensors):
+        """MPS with the given host tensors [chi_l][d][chi_r] (taken as they are)."""
+        N = len(tensors)
+        d = tensors[0].shape[1]
+        chi = [1] + [T.shape[2] for T in tensors]
+        m = cls.init(ctx, N, d, [1] * (N + 1), basis_state=[0] * N)
+        for j, T in enumerate(tensors):
+            m.set_tensor(j, T)
+        assert m.chi == chi
+        return m
+
+    @property
+    def chi(self):
+        c = np.zeros(self.N + 1, dtype=np.int32)
+        _check(self.ctx.handle, _lib.load().mps_get_info(self.handle, None, None, _iptr(c)))
+        return [int(x) for x in c]
+
+    def tensor(self, site: int) -> np.ndarray:
+        chi = self.chi
+        out = np.zeros((chi[site], self.d, chi[site + 1]), dtype=np.complex128)
+        _check(self.ctx.handle, _lib.load().mps_get_tensor(self.handle, site, _dptr(out.view(np.float64))))
+        return out
+
+    def tensors(self):
+        return [self.tensor(j) for j in range(self.N)]
+
+    def set_tensor(self, site: int, T):
+        T = _c128(T)
+        chil, _, chir = np.asarray(T).view(np.complex128).shape
+        _check(self.ctx.handle, _lib.load().mps_set_tensor(self.handle, site, _dptr(T), chil, chir))
+
+    def right_canonicalize(self):
+        _check(self.ctx.handle, _lib.load().mps_right_canonicalize(self.ctx.handle, self.handle))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            if self.ctx.handle:
+                _lib.load().mps_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class TDVPOptions:
+    compute: str = "c128"       # "c64": FP32 MFMA contractions, FP64 Lanczos/QR/SVD
+    krylov_max: int = 40
+    krylov_tol: float = 1e-13
+    chi_max: int = 1 << 30
+    w_max: float = 0.0
+    eps_rel: float = 0.0
+    multiplet_guard: bool = True
+    strict: bool = False
+    gemm_form: int = 0
+
+    def to_c(self) -> Opts:
+        o = Opts()
+        o.compute = TDVP_C64 if self.compute == "c64" else TDVP_C128
+        o.krylov_max = self.krylov_max
+        o.krylov_tol = self.krylov_tol
+        o.chi_max = self.chi_max
+        o.w_max = self.w_max
+        o.eps_rel = self.eps_rel
+        o.multiplet_guard = int(self.multiplet_guard)
+        o.strict = int(self.strict)
+        o.gemm_form = self.gemm_form
+        return o
+
+
+def tdvp1_step(ctx: Context, mps: MPS, mpo: MPO, dt: float, opts: TDVPOptions | None = None) -> dict:
+    o = (opts or TDVPOptions()).to_c()
+    st = Stats()
+    _check(ctx.handle, _lib.load().tdvp1_step(ctx.handle, mps.handle, mpo.handle, float(dt), C.byref(o), C.byref(st)))
+    return st.as_dict()
+
+
+def tdvp2_step(ctx: Context, mps: MPS, mpo: MPO, dt: float, opts: TDVPOptions | None = None) -> dict:
+    o = (opts or TDVPOptions()).to_c()
+    st = Stats()
+    _check(ctx.handle, _lib.load().tdvp2_step(ctx.handle, mps.handle, mpo.handle, float(dt), C.byref(o), C.byref(st)))
+    return st.as_dict()
+
+
+def expect(ctx: Context, mps: MPS, sites, ops) -> np.ndarray:
+    sites = np.ascontiguousarray(sites, dtype=np.int32)
+    n = len(sites)
+    ops = np.asarray(ops, dtype=np.complex128)
+    if ops.ndim == 2:
+        ops = np.broadcast_to(ops, (n,) + ops.shape)
+    ops = _c128(ops)
+    out = np.zeros(n, dtype=np.complex128)
+    _check(ctx.handle, _lib.load().expect(ctx.handle, mps.handle, n, _iptr(sites), _dptr(ops),
+                                          _dptr(out.view(np.float64))))
+    return out
+
+
+def expect2(ctx: Context, mps: MPS, i, j, Oi, Oj) -> np.ndarray:
+    i = np.ascontiguousarray(np.atleast_1d(i), dtype=np.int32)
+    j = np.ascontiguousarray(np.atleast_1d(j), dtype=np.int32)
+    n = len(i)
+    Oi = np.asarray(Oi, dtype=np.complex128)
+    Oj = np.asarray(Oj, dtype=np.complex128)
+    if Oi.ndim == 2:
+        Oi = np.broadcast_to(Oi, (n,) + Oi.shape)
+    if Oj.ndim == 2:
+        Oj = np.broadcast_to(Oj, (n,) + Oj.shape)
+    Oi, Oj = _c128(Oi), _c128(Oj)
+    out = np.zeros(n, dtype=np.complex128)
+    _check(ctx.handle, _lib.load().expect2(ctx.handle, mps.handle, n, _iptr(i), _iptr(j), _dptr(Oi),
+                                           _dptr(Oj), _dptr(out.view(np.float64))))
+    return out
+
+
+def energy(ctx: Context, mps: MPS, mpo: MPO) -> complex:
+    out = np.zeros(2)
+    _check(ctx.handle, _lib.load().energy(ctx.handle, mps.handle, mpo.handle, _dptr(out)))
+    return complex(out[0], out[1])
+
+
+def norm2(ctx: Context, mps: MPS) -> float:
+    out = np.zeros(1)
+    _check(ctx.handle, _lib.load().norm2(ctx.handle, mps.handle, _dptr(out)))
+    return float(out[0])
+
+
+def overlap(ctx: Context, bra: MPS, ket: MPS) -> complex:
+    out = np.zeros(2)
+    _check(ctx.handle, _lib.load().overlap(ctx.handle, bra.handle, ket.handle, _dptr(out)))
+    return complex(out[0], out[1])
+
+
+def infidelity(ctx: Context, a: MPS, b: MPS) -> float:
+    """1 - |<a|b>| / sqrt(<a|a><b|b>) (Sec. IV)."""
+    return 1.0 - abs(overlap(ctx, a, b)) / np.sqrt(norm2(ctx, a) * norm2(ctx, b))

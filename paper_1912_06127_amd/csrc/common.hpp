@@ -1,0 +1,187 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/tdvp.h"
+
+namespace tdvp {
+
+// ------------------------------------------------------------------ errors
+
+struct Error : std::runtime_error {
+    int status;
+    Error(int s, const std::string& m) : std::runtime_error(m), status(s) {}
+};
+
+#define TDVP_CHECK_HIP(expr)                                                          \
+    do {                                                                              \
+        hipError_t e_ = (expr);                                                       \
+        if (e_ != hipSuccess)                                                         \
+            throw ::tdvp::Error(TDVP_E_HIP, std::string(#expr) + ": " +               \
+                                                hipGetErrorString(e_));               \
+    } while (0)
+
+#define TDVP_REQUIRE(cond, status, msg)                                              \
+    do {                                                                              \
+        if (!(cond)) throw ::tdvp::Error((status), (msg));                            \
+    } while (0)
+
+// ------------------------------------------------------------------- dtypes
+
+enum class Dt : int { C64 = 0, C128 = 1 };
+inline size_t elem_bytes(Dt d) { return d == Dt::C64 ? 8 : 16; }
+inline Dt to_dt(int v) {
+    TDVP_REQUIRE(v == TDVP_C64 || v == TDVP_C128, TDVP_E_DTYPE, "dtype must be TDVP_C64 or TDVP_C128");
+    return v == TDVP_C64 ? Dt::C64 : Dt::C128;
+}
+
+struct cd {  // host complex double
+    double re, im;
+};
+
+// ------------------------------------------------------------------ context
+
+struct Buffer {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace tdvp
+
+struct tdvp_ctx_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    tdvp_alloc_fn alloc_fn = nullptr;
+    tdvp_free_fn free_fn = nullptr;
+    void* user = nullptr;
+    rocblas_handle blas = nullptr;
+    std::string err;
+    std::map<std::string, tdvp::Buffer> work;  // grow-only named workspaces
+
+    void* dev_alloc(size_t bytes);
+    void dev_free(void* p, size_t bytes);
+    // Named workspace of at least `bytes` bytes; contents not preserved on growth.
+    void* workspace(const std::string& name, size_t bytes);
+    void release_all();
+};
+
+namespace tdvp {
+
+// RAII device allocation through the context allocator.
+struct DevMem {
+    tdvp_ctx ctx = nullptr;
+    void* ptr = nullptr;
+    size_t bytes = 0;
+    DevMem() = default;
+    DevMem(tdvp_ctx c, size_t b) : ctx(c), bytes(b) { ptr = b ? c->dev_alloc(b) : nullptr; }
+    DevMem(const DevMem&) = delete;
+    DevMem& operator=(const DevMem&) = delete;
+    DevMem(DevMem&& o) noexcept { *this = std::move(o); }
+    DevMem& operator=(DevMem&& o) noexcept {
+        reset();
+        ctx = o.ctx; ptr = o.ptr; bytes = o.bytes;
+        o.ptr = nullptr; o.bytes = 0;
+        return *this;
+    }
+    ~DevMem() { reset(); }
+    void reset() {
+        if (ptr && ctx) ctx->dev_free(ptr, bytes);
+        ptr = nullptr; bytes = 0;
+    }
+    template <class T> T* as() const { return static_cast<T*>(ptr); }
+};
+
+// ------------------------------------------------------------ kernel entry
+
+// Operand of the complex GEMM.  For the A operand the "outer" index is m,
+// for B it is n.  kcontig: element (outer, k) at p[outer*ld + k], otherwise
+// at p[k*ld + outer].  conj: use the complex conjugate of the stored value.
+struct GemmOperand {
+    const void* p = nullptr;
+    Dt dt = Dt::C64;
+    int64_t ld = 0;
+    int64_t stride = 0;  // batch stride in elements
+    bool kcontig = true;
+    bool conj = false;
+};
+
+// C[z][m][n] = sum_k op(A)[z][m][k] op(B)[z][k][n], C stored row-major with ldc.
+struct GemmDesc {
+    int M = 0, N = 0, K = 0, batch = 1;
+    GemmOperand A, B;
+    void* C = nullptr;
+    Dt cdt = Dt::C64;
+    int64_t ldc = 0, strideC = 0;
+};
+
+// fp64: FP64 MFMA, else FP32 MFMA.  form: 3 (Gauss 3-real-product) or 4.
+void cgemm(const GemmDesc& g, bool fp64, int form, hipStream_t s);
+
+// Sparse local-operator stage.  For every grid point (p, q):
+//   out[n][s'](p, q) = sum_{k,s} M[(n,s'),(k,s)] in[k][s](p, q)
+// with in offset  k*ik + s*is + p*ip + q  and out offset n*on + s'*os + p*op + q.
+// M is given in CSR form by output row r = n*D + s'; col = k*D + s.
+struct WStageDesc {
+    const void* in = nullptr; Dt in_dt = Dt::C64;
+    void* out = nullptr; Dt out_dt = Dt::C64;
+    int P = 0, Q = 0, D = 1, w_in = 1, w_out = 1;
+    int64_t ik = 0, is = 0, ip = 0, on = 0, os = 0, op = 0;
+    const int* row_ptr = nullptr;  // device [w_out*D + 1]
+    const int* col = nullptr;      // device [nnz]
+    const void* val = nullptr;     // device [nnz] complex of the compute dtype
+    bool fp64 = false;
+};
+void wstage(const WStageDesc& w, hipStream_t s);
+
+// ----------------------------------------------- FP64 vector kernels (c128)
+// All pointers device; n complex elements.
+// partial dot products of vectors V[0..nv) (stride vstride) with w,
+// reduced into out[nv] (complex) = sum conj(V[j][i]) w[i].
+void vdot_multi(tdvp_ctx ctx, const double2* V, int64_t vstride, int nv, const double2* w,
+                int64_t n, double2* out);
+// w -= sum_j coef[j] V[j]   (coef device complex[nv])
+void axpy_multi(const double2* V, int64_t vstride, int nv, const double2* coef, double2* w,
+                int64_t n, hipStream_t s);
+// w -= Re(alpha_dev[0]) * vk + beta * vkm1 (vkm1 may be null)
+void lanczos_3term(double2* w, const double2* vk, const double2* vkm1, const double2* alpha_dev,
+                   double beta, int64_t n, hipStream_t s);
+// out = scale * in
+void scale_copy(double2* out, const double2* in, double scale, int64_t n, hipStream_t s);
+// out = sum_j coef[j] V[j]
+void combine(double2* out, const double2* V, int64_t vstride, int nv, const double2* coef,
+             int64_t n, hipStream_t s);
+// strided 2-D copy of complex128: dst[r*ldd + c] = src[r*lds + c] for c < cols;
+// mask: 0 none, 1 zero where c < r (keep upper), 2 zero where c > r (keep lower)
+void copy2d(double2* dst, int64_t ldd, const double2* src, int64_t lds, int rows, int cols,
+            int mask, hipStream_t s);
+// rows of V (row-major [rows][cols]) multiplied by real sv[r]
+void scale_rows(double2* V, int64_t ld, const double* sv, int rows, int cols, hipStream_t s);
+// columns of U (row-major [rows][cols]) multiplied by real sv[c]
+void scale_cols(double2* U, int64_t ld, const double* sv, int rows, int cols, hipStream_t s);
+// c128 <-> c64 conversion
+void convert(void* dst, Dt ddt, const void* src, Dt sdt, int64_t n, hipStream_t s);
+// any NaN/Inf in n complex128 values -> flag[0] = 1 (flag must be zeroed)
+void nan_check(const double2* x, int64_t n, int* flag, hipStream_t s);
+
+}  // namespace tdvp
+
+namespace tdvp {
+// MPO-stage operator kinds (rows <- cols):
+//   0 zero-site identity (w x w), 1 one-site / left environment (l,s')<-(k,s),
+//   2 two-site (n,s1's2')<-(k,s1s2), 3 right environment (k,s')<-(l,s).
+void mop_build(int kind, const void* W1, Dt w1dt, const void* W2, Dt w2dt, int wl, int wm, int wr,
+               int d, int rows, int cols, double2* dense, int* row_ptr, int* col, void* val,
+               bool val_fp64, hipStream_t s);
+// out[0] = sum_{i,j} X[i][j] Y[j][i] for n x n complex128 matrices.
+void trace_xyT(tdvp_ctx ctx, const double2* X, const double2* Y, int n, double2* out);
+}  // namespace tdvp

@@ -1,0 +1,125 @@
+// Host-side objects and algorithms of the library.
+#pragma once
+
+#include "common.hpp"
+
+#include <functional>
+
+namespace tdvp {
+
+// Run `body`, translating exceptions into a status code and a message on ctx.
+int guarded(tdvp_ctx ctx, const std::function<void()>& body);
+
+// ------------------------------------------------------ MPO stage operator
+// CSR form of the sparse operator between the two GEMMs of a contraction.
+struct Mop {
+    const int* row_ptr = nullptr;
+    const int* col = nullptr;
+    const void* val = nullptr;
+    int rows = 0, cols = 0;
+    bool fp64 = false;
+    DevMem own_rp, own_col, own_val;  // storage when the operator is cached
+};
+// kind: see mop_build.  W1/W2 device tensors of dtype w_dt.  own = true
+// keeps the operator in memory owned by m; otherwise context workspaces
+// (valid until the next mop_make without ownership) are used.
+void mop_make(tdvp_ctx ctx, Mop& m, int kind, const void* W1, const void* W2, Dt w_dt, int wl,
+              int wm, int wr, int d, bool fp64, bool own);
+
+// ------------------------------------------------------------ contractions
+// y = H_eff x for nsite = 0, 1, 2 (Sec. III A).  Env layouts L[wl][chil][chil],
+// R[wr][chir][chir]; x, y of shape [chil][D][chir] with D = d^nsite (1 for
+// nsite = 0).  L and R have dtype env_dt, x has x_dt, y has y_dt.
+struct HeffArgs {
+    int nsite, chil, chir, d, wl, wr;
+    const void* L;
+    const void* R;
+    Dt env_dt;
+    const Mop* mop;
+    bool fp64;
+    int form;
+};
+void heff_apply(tdvp_ctx ctx, const HeffArgs& a, const void* x, Dt x_dt, void* y, Dt y_dt);
+double heff_flops(int nsite, int chil, int chir, int d, int wl, int wr);
+
+// Left environment update with separate bra and ket tensors (Sec. III A):
+// out[l][b'][b] = sum conj(Abra[a'][s'][b']) L[k][a'][a] W[k][l][s'][s] Aket[a][s][b]
+// Abra [chil_b][d][chir_b], Aket [chil][d][chir] (complex128), L [wl][chil_b][chil],
+// out [wr][chir_b][chir].  mop: kind 1 for W.
+struct EnvArgs {
+    int chil, chir, chil_b, chir_b, d, wl, wr;
+    const void* Abra;
+    const void* Aket;
+    Dt a_dt;
+    const Mop* mop;
+    bool fp64;
+    int form;
+};
+void env_left(tdvp_ctx ctx, const EnvArgs& a, const void* L, Dt l_dt, void* out, Dt out_dt);
+// Right update: out[k][a][a'] = sum Aket[a][s][b] W[k][l][s'][s] R[l][b][b'] conj(Abra[a'][s'][b'])
+// R [wr][chir][chir_b], out [wl][chil][chil_b].  mop: kind 3 for W.
+void env_right(tdvp_ctx ctx, const EnvArgs& a, const void* R, Dt r_dt, void* out, Dt out_dt);
+double env_flops(int chil, int chir, int d, int wl, int wr);
+
+// ------------------------------------------------------------- Lanczos
+// Linear operator on complex128 device vectors.
+using MatVec = std::function<void(const double2* x, double2* y)>;
+struct KrylovInfo {
+    int k = 0;
+    int matvecs = 0;
+    bool converged = true;
+};
+// theta <- exp(-i tau H) theta with H Hermitian (Sec. III A, Lanczos).
+KrylovInfo expm_krylov(tdvp_ctx ctx, const MatVec& op, double2* theta, int64_t n, double tau,
+                       int kmax, double tol);
+// eigen-decomposition of a symmetric tridiagonal k x k matrix (host):
+// evals[k], evecs row-major [k][k] with columns the eigenvectors.
+void tridiag_eigen(const std::vector<double>& alpha, const std::vector<double>& beta,
+                   std::vector<double>& evals, std::vector<double>& evecs);
+
+// ------------------------------------------------------------- solvers
+// Row-major QR: M [rows][cols] = Q [rows][k] R [k][cols], k = min(rows, cols).
+void qr_rowmajor(tdvp_ctx ctx, const double2* M, int rows, int cols, double2* Q, double2* R);
+// Row-major LQ: M [rows][cols] = L [rows][k] Q [k][cols].
+void lq_rowmajor(tdvp_ctx ctx, const double2* M, int rows, int cols, double2* L, double2* Q);
+// Row-major thin SVD: M = U [rows][k] diag(S) Vh [k][cols]; S on host and device.
+struct SvdResult {
+    double2* U;   // row-major [rows][k]  (workspace)
+    double2* Vh;  // row-major [k][cols]  (workspace)
+    double* S_dev;
+    std::vector<double> S;
+    int k;
+};
+SvdResult svd_rowmajor(tdvp_ctx ctx, const double2* M, int rows, int cols);
+// Row-major complex128 product C [m][n] = A [m][k] B [k][n] (FP64 MFMA).
+void zgemm_rowmajor(tdvp_ctx ctx, const double2* A, const double2* B, double2* C, int m, int k, int n);
+
+}  // namespace tdvp
+
+// ------------------------------------------------------------------ objects
+
+struct tdvp_mpo_s {
+    tdvp_ctx ctx = nullptr;
+    int N = 0, d = 0;
+    std::vector<int> w;                           // [N+1]
+    std::vector<std::vector<double>> host;        // c128 interleaved per site
+    std::vector<tdvp::DevMem> dev128, dev64;      // device copies
+    std::map<std::tuple<int, int, bool>, std::unique_ptr<tdvp::Mop>> mops;  // (kind, site, fp64)
+    const tdvp::Mop& mop(int kind, int site, bool fp64);
+    const void* W(int site, tdvp::Dt dt);
+};
+
+struct tdvp_mps_s {
+    tdvp_ctx ctx = nullptr;
+    int N = 0, d = 0;
+    std::vector<int> chi;                 // [N+1]
+    std::vector<tdvp::DevMem> A;          // c128 site tensors
+    double w_total = 0.0;
+    // cached environments for (mpo, dtype)
+    const tdvp_mpo_s* env_mpo = nullptr;
+    tdvp::Dt env_dt = tdvp::Dt::C128;
+    bool env_valid = false;
+    std::vector<tdvp::DevMem> L, R;       // L[j]: [w_j][chi_j][chi_j], R[j]: [w_{j+1}][chi_{j+1}][chi_{j+1}]
+    size_t tensor_elems(int j) const { return (size_t)chi[j] * d * chi[j + 1]; }
+    void set_tensor_dev(int j, int chil, int chir);  // (re)allocate site j storage
+};

@@ -1,0 +1,449 @@
+// Memory-bound kernels of the TDVP path: the sparse MPO stage between the
+// two GEMMs of H_eff and of the environment updates, the FP64 vector
+// operations of Lanczos, and small reshaping helpers around the dense
+// solvers.
+#include "common.hpp"
+
+namespace tdvp {
+namespace {
+
+constexpr int kVecThreads = 256;
+constexpr int kDotBlocks = 512;  // fixed partial-sum count -> deterministic sums
+
+template <typename T> struct cplx;
+template <> struct cplx<float> { using t = float2; };
+template <> struct cplx<double> { using t = double2; };
+
+template <typename T>
+__device__ inline void ld(const void* p, int c128, int64_t i, T& re, T& im) {
+    if (c128) {
+        double2 v = reinterpret_cast<const double2*>(p)[i];
+        re = (T)v.x;
+        im = (T)v.y;
+    } else {
+        float2 v = reinterpret_cast<const float2*>(p)[i];
+        re = (T)v.x;
+        im = (T)v.y;
+    }
+}
+
+template <typename T>
+__device__ inline void st(void* p, int c128, int64_t i, T re, T im) {
+    if (c128) reinterpret_cast<double2*>(p)[i] = make_double2((double)re, (double)im);
+    else reinterpret_cast<float2*>(p)[i] = make_float2((float)re, (float)im);
+}
+
+// ---------------------------------------------------------------- MPO stage
+// One thread per grid point (p, q).  The w_in*D input values of the point
+// are staged in a thread-private LDS column, then each output row is a
+// short sparse dot product with the MPO entries (read with uniform
+// addresses).  Loads and stores are coalesced along q.
+struct WParams {
+    const void* in; int in128;
+    void* out; int out128;
+    int P, Q, D, nin, nout;
+    int64_t ik, is, ip, on, os, op;
+    const int* row_ptr;
+    const int* col;
+    const void* val;
+};
+
+template <typename T>
+__global__ void wstage_kernel(WParams w) {
+    using C = typename cplx<T>::t;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C* xin = reinterpret_cast<C*>(smem_raw);  // [nin][blockDim.x]
+    const int nt = blockDim.x;
+    const int q = blockIdx.x * nt + threadIdx.x;
+    const int p = blockIdx.y;
+    if (q >= w.Q) return;  // no barrier below: each thread uses only its column
+    const int64_t pin = (int64_t)p * w.ip + q;
+    for (int c = 0; c < w.nin; ++c) {
+        const int k = c / w.D, s = c % w.D;
+        T re, im;
+        ld<T>(w.in, w.in128, pin + k * w.ik + s * w.is, re, im);
+        xin[c * nt + threadIdx.x] = C{re, im};
+    }
+    const C* val = reinterpret_cast<const C*>(w.val);
+    const int64_t pout = (int64_t)p * w.op + q;
+    for (int r = 0; r < w.nout; ++r) {
+        T ar = 0, ai = 0;
+        const int e1 = w.row_ptr[r + 1];
+        for (int e = w.row_ptr[r]; e < e1; ++e) {
+            const C v = val[e];
+            const C x = xin[w.col[e] * nt + threadIdx.x];
+            ar += v.x * x.x - v.y * x.y;
+            ai += v.x * x.y + v.y * x.x;
+        }
+        const int n = r / w.D, s = r % w.D;
+        st<T>(w.out, w.out128, pout + n * w.on + s * w.os, ar, ai);
+    }
+}
+
+// ------------------------------------------------------------ FP64 vectors
+
+__global__ void vdot_partial_kernel(const double2* V, int64_t vstride, int nv, const double2* w,
+                                    int64_t n, double2* partial) {
+    // partial[j][block] = sum over this block's grid-stride slice of conj(V[j][i]) w[i]
+    __shared__ double sre[kVecThreads], sim[kVecThreads];
+    for (int j = 0; j < nv; ++j) {
+        double re = 0.0, im = 0.0;
+        const double2* v = V + j * vstride;
+        for (int64_t i = (int64_t)blockIdx.x * kVecThreads + threadIdx.x; i < n;
+             i += (int64_t)gridDim.x * kVecThreads) {
+            const double2 a = v[i], b = w[i];
+            re += a.x * b.x + a.y * b.y;
+            im += a.x * b.y - a.y * b.x;
+        }
+        sre[threadIdx.x] = re;
+        sim[threadIdx.x] = im;
+        __syncthreads();
+        for (int h = kVecThreads / 2; h > 0; h >>= 1) {
+            if (threadIdx.x < h) {
+                sre[threadIdx.x] += sre[threadIdx.x + h];
+                sim[threadIdx.x] += sim[threadIdx.x + h];
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) partial[(int64_t)j * gridDim.x + blockIdx.x] = make_double2(sre[0], sim[0]);
+        __syncthreads();
+    }
+}
+
+__global__ void reduce_partial_kernel(const double2* partial, int nblocks, double2* out) {
+    // one block per vector j
+    __shared__ double sre[kVecThreads], sim[kVecThreads];
+    const int j = blockIdx.x;
+    double re = 0.0, im = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += kVecThreads) {
+        const double2 v = partial[(int64_t)j * nblocks + b];
+        re += v.x;
+        im += v.y;
+    }
+    sre[threadIdx.x] = re;
+    sim[threadIdx.x] = im;
+    __syncthreads();
+    for (int h = kVecThreads / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) {
+            sre[threadIdx.x] += sre[threadIdx.x + h];
+            sim[threadIdx.x] += sim[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[j] = make_double2(sre[0], sim[0]);
+}
+
+__global__ void axpy_multi_kernel(const double2* V, int64_t vstride, int nv, const double2* coef,
+                                  double2* w, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
+    if (i >= n) return;
+    double2 acc = w[i];
+    for (int j = 0; j < nv; ++j) {
+        const double2 c = coef[j], v = V[j * vstride + i];
+        acc.x -= c.x * v.x - c.y * v.y;
+        acc.y -= c.x * v.y + c.y * v.x;
+    }
+    w[i] = acc;
+}
+
+__global__ void lanczos_3term_kernel(double2* w, const double2* vk, const double2* vkm1,
+                                     const double2* alpha, double beta, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
+    if (i >= n) return;
+    const double a = alpha[0].x;
+    double2 x = w[i];
+    const double2 v = vk[i];
+    x.x -= a * v.x;
+    x.y -= a * v.y;
+    if (vkm1) {
+        const double2 u = vkm1[i];
+        x.x -= beta * u.x;
+        x.y -= beta * u.y;
+    }
+    w[i] = x;
+}
+
+__global__ void scale_copy_kernel(double2* out, const double2* in, double scale, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
+    if (i >= n) return;
+    const double2 v = in[i];
+    out[i] = make_double2(scale * v.x, scale * v.y);
+}
+
+__global__ void combine_kernel(double2* out, const double2* V, int64_t vstride, int nv,
+                               const double2* coef, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
+    if (i >= n) return;
+    double re = 0.0, im = 0.0;
+    for (int j = 0; j < nv; ++j) {
+        const double2 c = coef[j], v = V[j * vstride + i];
+        re += c.x * v.x - c.y * v.y;
+        im += c.x * v.y + c.y * v.x;
+    }
+    out[i] = make_double2(re, im);
+}
+
+__global__ void copy2d_kernel(double2* dst, int64_t ldd, const double2* src, int64_t lds, int rows,
+                              int cols, int mask) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    if (c >= cols || r >= rows) return;
+    double2 v = src[(int64_t)r * lds + c];
+    if ((mask == 1 && c < r) || (mask == 2 && c > r)) v = make_double2(0.0, 0.0);
+    dst[(int64_t)r * ldd + c] = v;
+}
+
+__global__ void scale_rows_kernel(double2* V, int64_t ld, const double* sv, int rows, int cols) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    if (c >= cols || r >= rows) return;
+    const double s = sv[r];
+    double2 v = V[(int64_t)r * ld + c];
+    V[(int64_t)r * ld + c] = make_double2(s * v.x, s * v.y);
+}
+
+__global__ void scale_cols_kernel(double2* U, int64_t ld, const double* sv, int rows, int cols) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    if (c >= cols || r >= rows) return;
+    const double s = sv[c];
+    double2 v = U[(int64_t)r * ld + c];
+    U[(int64_t)r * ld + c] = make_double2(s * v.x, s * v.y);
+}
+
+__global__ void convert_kernel(void* dst, int d128, const void* src, int s128, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
+    if (i >= n) return;
+    double re, im;
+    ld<double>(src, s128, i, re, im);
+    st<double>(dst, d128, i, re, im);
+}
+
+__global__ void nan_check_kernel(const double2* x, int64_t n, int* flag) {
+    const int64_t i = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
+    if (i >= n) return;
+    const double2 v = x[i];
+    if (!isfinite(v.x) || !isfinite(v.y)) atomicOr(flag, 1);
+}
+
+// --------------------------------------------- MPO stage operator (device)
+// Dense operator M[row][col] of the sparse MPO stage, built in FP64 from the
+// device MPO tensors (kind as in MopKind).
+__global__ void mop_dense_kernel(int kind, const void* W1, int w1_128, const void* W2, int w2_128,
+                                 int wl, int wm, int wr, int d, int rows, int cols, double2* M) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= rows * cols) return;
+    const int row = idx / cols, col = idx % cols;
+    double re = 0.0, im = 0.0;
+    if (kind == 0) {  // zero-site: identity on the MPO bond
+        re = (row == col) ? 1.0 : 0.0;
+    } else if (kind == 1) {  // (l, s') <- (k, s): W[k][l][s'][s]
+        const int l = row / d, sp = row % d, k = col / d, s = col % d;
+        ld<double>(W1, w1_128, (((int64_t)k * wr + l) * d + sp) * d + s, re, im);
+    } else if (kind == 3) {  // (k, s') <- (l, s): W[k][l][s'][s]
+        const int k = row / d, sp = row % d, l = col / d, s = col % d;
+        ld<double>(W1, w1_128, (((int64_t)k * wr + l) * d + sp) * d + s, re, im);
+    } else {  // kind 2: (n, s1' s2') <- (k, s1 s2): sum_l W1[k][l][s1'][s1] W2[l][n][s2'][s2]
+        const int dd = d * d;
+        const int n = row / dd, s1p = (row % dd) / d, s2p = row % d;
+        const int k = col / dd, s1 = (col % dd) / d, s2 = col % d;
+        for (int l = 0; l < wm; ++l) {
+            double ar, ai, br, bi;
+            ld<double>(W1, w1_128, (((int64_t)k * wm + l) * d + s1p) * d + s1, ar, ai);
+            ld<double>(W2, w2_128, (((int64_t)l * wr + n) * d + s2p) * d + s2, br, bi);
+            re += ar * br - ai * bi;
+            im += ar * bi + ai * br;
+        }
+    }
+    M[idx] = make_double2(re, im);
+}
+
+// Compress the dense operator to CSR (exact zeros dropped).  One block.
+__global__ void mop_csr_kernel(const double2* M, int rows, int cols, int* row_ptr, int* col,
+                               void* val, int val128) {
+    for (int r = threadIdx.x; r < rows; r += blockDim.x) {
+        int c = 0;
+        for (int j = 0; j < cols; ++j) {
+            const double2 v = M[(int64_t)r * cols + j];
+            c += (v.x != 0.0 || v.y != 0.0);
+        }
+        row_ptr[r + 1] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        row_ptr[0] = 0;
+        for (int r = 0; r < rows; ++r) row_ptr[r + 1] += row_ptr[r];
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < rows; r += blockDim.x) {
+        int e = row_ptr[r];
+        for (int j = 0; j < cols; ++j) {
+            const double2 v = M[(int64_t)r * cols + j];
+            if (v.x != 0.0 || v.y != 0.0) {
+                col[e] = j;
+                st<double>(val, val128, e, v.x, v.y);
+                ++e;
+            }
+        }
+    }
+}
+
+// out[block] = partial sums of X[i][j] * Y[j][i] (no conjugation)
+__global__ void trace_xyT_partial_kernel(const double2* X, const double2* Y, int n, double2* partial) {
+    __shared__ double sre[kVecThreads], sim[kVecThreads];
+    double re = 0.0, im = 0.0;
+    const int64_t nn = (int64_t)n * n;
+    for (int64_t t = (int64_t)blockIdx.x * kVecThreads + threadIdx.x; t < nn;
+         t += (int64_t)gridDim.x * kVecThreads) {
+        const int64_t i = t / n, j = t % n;
+        const double2 a = X[t], b = Y[j * n + i];
+        re += a.x * b.x - a.y * b.y;
+        im += a.x * b.y + a.y * b.x;
+    }
+    sre[threadIdx.x] = re;
+    sim[threadIdx.x] = im;
+    __syncthreads();
+    for (int h = kVecThreads / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) {
+            sre[threadIdx.x] += sre[threadIdx.x + h];
+            sim[threadIdx.x] += sim[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = make_double2(sre[0], sim[0]);
+}
+
+inline unsigned nblk(int64_t n) { return (unsigned)((n + kVecThreads - 1) / kVecThreads); }
+
+}  // namespace
+
+void wstage(const WStageDesc& d, hipStream_t s) {
+    if (d.P == 0 || d.Q == 0) return;
+    WParams w;
+    w.in = d.in;
+    w.in128 = d.in_dt == Dt::C128;
+    w.out = d.out;
+    w.out128 = d.out_dt == Dt::C128;
+    w.P = d.P;
+    w.Q = d.Q;
+    w.D = d.D;
+    w.nin = d.w_in * d.D;
+    w.nout = d.w_out * d.D;
+    w.ik = d.ik; w.is = d.is; w.ip = d.ip;
+    w.on = d.on; w.os = d.os; w.op = d.op;
+    w.row_ptr = d.row_ptr;
+    w.col = d.col;
+    w.val = d.val;
+    const size_t esz = d.fp64 ? sizeof(double2) : sizeof(float2);
+    int nt = 256;
+    while (nt > 64 && (size_t)nt * w.nin * esz > 48 * 1024) nt /= 2;
+    const size_t shmem = (size_t)nt * w.nin * esz;
+    TDVP_REQUIRE(shmem <= 160 * 1024, TDVP_E_SHAPE, "wstage: MPO bond dimension too large");
+    TDVP_REQUIRE(d.P <= 65535 * 1024, TDVP_E_SHAPE, "wstage: grid too large");
+    dim3 grid((d.Q + nt - 1) / nt, d.P);
+    if (d.fp64) hipLaunchKernelGGL(wstage_kernel<double>, grid, dim3(nt), shmem, s, w);
+    else hipLaunchKernelGGL(wstage_kernel<float>, grid, dim3(nt), shmem, s, w);
+    TDVP_CHECK_HIP(hipGetLastError());
+}
+
+void vdot_multi(tdvp_ctx ctx, const double2* V, int64_t vstride, int nv, const double2* w,
+                int64_t n, double2* out) {
+    if (nv <= 0) return;
+    double2* partial = static_cast<double2*>(
+        ctx->workspace("vdot_partial", sizeof(double2) * (size_t)kDotBlocks * nv));
+    int nb = (int)std::min<int64_t>(kDotBlocks, std::max<int64_t>(1, (n + kVecThreads - 1) / kVecThreads));
+    hipLaunchKernelGGL(vdot_partial_kernel, dim3(nb), dim3(kVecThreads), 0, ctx->stream, V, vstride,
+                       nv, w, n, partial);
+    hipLaunchKernelGGL(reduce_partial_kernel, dim3(nv), dim3(kVecThreads), 0, ctx->stream, partial,
+                       nb, out);
+    TDVP_CHECK_HIP(hipGetLastError());
+}
+
+void axpy_multi(const double2* V, int64_t vstride, int nv, const double2* coef, double2* w,
+                int64_t n, hipStream_t s) {
+    if (n == 0 || nv == 0) return;
+    hipLaunchKernelGGL(axpy_multi_kernel, dim3(nblk(n)), dim3(kVecThreads), 0, s, V, vstride, nv,
+                       coef, w, n);
+    TDVP_CHECK_HIP(hipGetLastError());
+}
+
+void lanczos_3term(double2* w, const double2* vk, const double2* vkm1, const double2* alpha_dev,
+                   double beta, int64_t n, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(lanczos_3term_kernel, dim3(nblk(n)), dim3(kVecThreads), 0, s, w, vk, vkm1,
+                       alpha_dev, beta, n);
+    TDVP_CHECK_HIP(hipGetLastError());
+}
+
+void scale_copy(double2* out, const double2* in, double scale, int64_t n, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(scale_copy_kernel, dim3(nblk(n)), dim3(kVecThreads), 0, s, out, in, scale, n);
+    TDVP_CHECK_HIP(hipGetLastError());
+}
+
+void combine(double2* out, const double2* V, int64_t vstride, int nv, const double2* coef,
+             int64_t n, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(combine_kernel, dim3(nblk(n)), dim3(kVecThreads), 0, s, out, V, vstride, nv,
+                       coef, n);
+    TDVP_CHECK_HIP(hipGetLastError());
+}
+
+void copy2d(double2* dst, int64_t ldd, const double2* src, int64_t lds, int rows, int cols,
+            int mask, hipStream_t s) {
+    if (rows == 0 || cols == 0) return;
+    TDVP_REQUIRE(rows <= 65535, TDVP_E_SHAPE, "copy2d: too many rows");
+    dim3 grid((cols + 127) / 128, rows);
+    hipLaunchKernelGGL(copy2d_kernel, grid, dim3(128), 0, s, dst, ldd, src, lds, rows, cols, mask);
+    TDVP_CHECK_HIP(hipGetLastError());
+}
+
+void scale_rows(double2* V, int64_t ld, const double* sv, int rows, int cols, hipStream_t s) {
+    if (rows == 0 || cols == 0) return;
+    dim3 grid((cols + 127) / 128, rows);
+    hipLaunchKernelGGL(scale_rows_kernel, grid, dim3(128), 0, s, V, ld, sv, rows, cols);
+    TDVP_CHECK_HIP(hipGetLastError());
+}
+
+void scale_cols(double2* U, int64_t ld, const double* sv, int rows, int cols, hipStream_t s) {
+    if (rows == 0 || cols == 0) return;
+    dim3 grid((cols + 127) / 128, rows);
+    hipLaunchKernelGGL(scale_cols_kernel, grid, dim3(128), 0, s, U, ld, sv, rows, cols);
+    TDVP_CHECK_HIP(hipGetLastError());
+}
+
+void convert(void* dst, Dt ddt, const void* src, Dt sdt, int64_t n, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(convert_kernel, dim3(nblk(n)), dim3(kVecThreads), 0, s, dst,
+                       (int)(ddt == Dt::C128), src, (int)(sdt == Dt::C128), n);
+    TDVP_CHECK_HIP(hipGetLastError());
+}
+
+void nan_check(const double2* x, int64_t n, int* flag, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(nan_check_kernel, dim3(nblk(n)), dim3(kVecThreads), 0, s, x, n, flag);
+    TDVP_CHECK_HIP(hipGetLastError());
+}
+
+void mop_build(int kind, const void* W1, Dt w1dt, const void* W2, Dt w2dt, int wl, int wm, int wr,
+               int d, int rows, int cols, double2* dense, int* row_ptr, int* col, void* val,
+               bool val_fp64, hipStream_t s) {
+    const int tot = rows * cols;
+    if (tot == 0) return;
+    hipLaunchKernelGGL(mop_dense_kernel, dim3((tot + 255) / 256), dim3(256), 0, s, kind, W1,
+                       (int)(w1dt == Dt::C128), W2, (int)(w2dt == Dt::C128), wl, wm, wr, d, rows,
+                       cols, dense);
+    hipLaunchKernelGGL(mop_csr_kernel, dim3(1), dim3(256), 0, s, dense, rows, cols, row_ptr, col,
+                       val, (int)val_fp64);
+    TDVP_CHECK_HIP(hipGetLastError());
+}
+
+void trace_xyT(tdvp_ctx ctx, const double2* X, const double2* Y, int n, double2* out) {
+    double2* partial = static_cast<double2*>(ctx->workspace("trace_partial", sizeof(double2) * kDotBlocks));
+    int nb = (int)std::min<int64_t>(kDotBlocks, std::max<int64_t>(1, ((int64_t)n * n + kVecThreads - 1) / kVecThreads));
+    hipLaunchKernelGGL(trace_xyT_partial_kernel, dim3(nb), dim3(kVecThreads), 0, ctx->stream, X, Y, n, partial);
+    hipLaunchKernelGGL(reduce_partial_kernel, dim3(1), dim3(kVecThreads), 0, ctx->stream, partial, nb, out);
+    TDVP_CHECK_HIP(hipGetLastError());
+}
+
+}  // namespace tdvp

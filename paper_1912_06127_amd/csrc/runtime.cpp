@@ -1,0 +1,134 @@
+// Context: device, stream, allocator, rocBLAS handle and named workspaces.
+#include "internal.hpp"
+
+#include <rocsolver/rocsolver.h>
+
+void* tdvp_ctx_s::dev_alloc(size_t bytes) {
+    if (bytes == 0) return nullptr;
+    void* p = nullptr;
+    if (alloc_fn) {
+        p = alloc_fn(bytes, (void*)stream, user);
+        if (!p) throw tdvp::Error(TDVP_E_NOMEM, "allocator callback returned NULL for " + std::to_string(bytes) + " bytes");
+    } else {
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess || !p)
+            throw tdvp::Error(TDVP_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
+    }
+    return p;
+}
+
+void tdvp_ctx_s::dev_free(void* p, size_t bytes) {
+    if (!p) return;
+    if (free_fn) free_fn(p, bytes, (void*)stream, user);
+    else (void)hipFree(p);
+}
+
+void* tdvp_ctx_s::workspace(const std::string& name, size_t bytes) {
+    tdvp::Buffer& b = work[name];
+    if (b.bytes < bytes) {
+        if (b.ptr) {
+            // the old buffer may still be read by queued kernels
+            TDVP_CHECK_HIP(hipStreamSynchronize(stream));
+            dev_free(b.ptr, b.bytes);
+            b.ptr = nullptr;
+            b.bytes = 0;
+        }
+        size_t cap = bytes + bytes / 4 + 256;
+        b.ptr = dev_alloc(cap);
+        b.bytes = cap;
+    }
+    return b.ptr;
+}
+
+void tdvp_ctx_s::release_all() {
+    for (auto& kv : work) dev_free(kv.second.ptr, kv.second.bytes);
+    work.clear();
+}
+
+namespace tdvp {
+
+int guarded(tdvp_ctx ctx, const std::function<void()>& body) {
+    try {
+        body();
+        if (ctx) ctx->err.clear();
+        return TDVP_OK;
+    } catch (const Error& e) {
+        if (ctx) ctx->err = e.what();
+        return e.status;
+    } catch (const std::bad_alloc&) {
+        if (ctx) ctx->err = "host allocation failed";
+        return TDVP_E_NOMEM;
+    } catch (const std::exception& e) {
+        if (ctx) ctx->err = e.what();
+        return TDVP_E_STATE;
+    } catch (...) {
+        if (ctx) ctx->err = "unknown error";
+        return TDVP_E_STATE;
+    }
+}
+
+}  // namespace tdvp
+
+extern "C" {
+
+const char* tdvp_version(void) { return "tdvp-gfx950 0.1"; }
+
+int tdvp_ctx_create(int device, void* hip_stream, tdvp_alloc_fn alloc_fn, tdvp_free_fn free_fn,
+                    void* user, tdvp_ctx* out) {
+    if (!out) return TDVP_E_ARG;
+    *out = nullptr;
+    if ((alloc_fn == nullptr) != (free_fn == nullptr)) return TDVP_E_ARG;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return TDVP_E_HIP;
+    if (device < 0 || device >= ndev) return TDVP_E_ARG;
+    auto* c = new (std::nothrow) tdvp_ctx_s();
+    if (!c) return TDVP_E_NOMEM;
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    c->alloc_fn = alloc_fn;
+    c->free_fn = free_fn;
+    c->user = user;
+    if (hipSetDevice(device) != hipSuccess) {
+        delete c;
+        return TDVP_E_HIP;
+    }
+    if (rocblas_create_handle(&c->blas) != rocblas_status_success) {
+        delete c;
+        return TDVP_E_HIP;
+    }
+    rocblas_set_stream(c->blas, c->stream);
+    *out = c;
+    return TDVP_OK;
+}
+
+int tdvp_ctx_destroy(tdvp_ctx ctx) {
+    if (!ctx) return TDVP_E_ARG;
+    (void)hipStreamSynchronize(ctx->stream);
+    ctx->release_all();
+    if (ctx->blas) rocblas_destroy_handle(ctx->blas);
+    delete ctx;
+    return TDVP_OK;
+}
+
+const char* tdvp_last_error(tdvp_ctx ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int tdvp_ctx_sync(tdvp_ctx ctx) {
+    if (!ctx) return TDVP_E_ARG;
+    return tdvp::guarded(ctx, [&] { TDVP_CHECK_HIP(hipStreamSynchronize(ctx->stream)); });
+}
+
+int tdvp_opts_default(tdvp_opts* o) {
+    if (!o) return TDVP_E_ARG;
+    o->compute = TDVP_C128;
+    o->krylov_max = 40;
+    o->krylov_tol = 1e-13;
+    o->chi_max = 1 << 30;
+    o->w_max = 0.0;
+    o->eps_rel = 0.0;
+    o->multiplet_guard = 1;
+    o->strict = 0;
+    o->gemm_form = 0;
+    return TDVP_OK;
+}
+
+}  // extern "C"

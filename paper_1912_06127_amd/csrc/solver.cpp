@@ -1,0 +1,84 @@
+// Dense FP64 gauge moves on the device (rocSOLVER): QR / LQ for one-site TDVP
+// and the thin SVD that re-splits two-site states (Sec. III A, Fig. postupdate).
+//
+// rocSOLVER is column-major.  A row-major matrix M [rows][cols] is the
+// column-major matrix M^T [cols][rows] in the same memory, so a row-major QR
+// is a column-major LQ and vice versa, and the SVD factors swap roles:
+//   M^T = U' S V'^H  =>  M = (V'^H)^T S U'^T,
+// i.e. the column-major V'^H buffer read row-major is U, and the
+// column-major U' buffer read row-major is V^H.  No transposition kernel is
+// needed.
+#include "internal.hpp"
+
+#include <rocsolver/rocsolver.h>
+
+namespace tdvp {
+
+namespace {
+
+void check_rs(rocblas_status st, const char* what) {
+    if (st != rocblas_status_success)
+        throw Error(TDVP_E_SOLVER, std::string(what) + " failed: " + rocblas_status_to_string(st));
+}
+
+rocblas_double_complex* rz(double2* p) { return reinterpret_cast<rocblas_double_complex*>(p); }
+
+}  // namespace
+
+void qr_rowmajor(tdvp_ctx ctx, const double2* M, int rows, int cols, double2* Q, double2* R) {
+    const int k = std::min(rows, cols);
+    double2* work = static_cast<double2*>(ctx->workspace("qr_work", sizeof(double2) * (size_t)rows * cols));
+    double2* tau = static_cast<double2*>(ctx->workspace("qr_tau", sizeof(double2) * (size_t)k));
+    TDVP_CHECK_HIP(hipMemcpyAsync(work, M, sizeof(double2) * (size_t)rows * cols, hipMemcpyDeviceToDevice, ctx->stream));
+    // column-major LQ of M^T (cols x rows, lda = cols)
+    check_rs(rocsolver_zgelqf(ctx->blas, cols, rows, rz(work), cols, rz(tau)), "zgelqf");
+    // R[c][i] = L^T: buffer rows c < k with row stride cols, keep i >= c
+    copy2d(R, cols, work, cols, k, cols, 1, ctx->stream);
+    check_rs(rocsolver_zunglq(ctx->blas, k, rows, k, rz(work), cols, rz(tau)), "zunglq");
+    // Q[i][c] = work[i*cols + c], c < k
+    copy2d(Q, k, work, cols, rows, k, 0, ctx->stream);
+}
+
+void lq_rowmajor(tdvp_ctx ctx, const double2* M, int rows, int cols, double2* L, double2* Q) {
+    const int k = std::min(rows, cols);
+    double2* work = static_cast<double2*>(ctx->workspace("qr_work", sizeof(double2) * (size_t)rows * cols));
+    double2* tau = static_cast<double2*>(ctx->workspace("qr_tau", sizeof(double2) * (size_t)k));
+    TDVP_CHECK_HIP(hipMemcpyAsync(work, M, sizeof(double2) * (size_t)rows * cols, hipMemcpyDeviceToDevice, ctx->stream));
+    // column-major QR of M^T (cols x rows, lda = cols)
+    check_rs(rocsolver_zgeqrf(ctx->blas, cols, rows, rz(work), cols, rz(tau)), "zgeqrf");
+    // L[a][c] = work[a*cols + c] for c <= a, c < k
+    copy2d(L, k, work, cols, rows, k, 2, ctx->stream);
+    check_rs(rocsolver_zungqr(ctx->blas, cols, k, k, rz(work), cols, rz(tau)), "zungqr");
+    // Q[c][j] = work[c*cols + j]
+    copy2d(Q, cols, work, cols, k, cols, 0, ctx->stream);
+}
+
+SvdResult svd_rowmajor(tdvp_ctx ctx, const double2* M, int rows, int cols) {
+    SvdResult r;
+    const int k = std::min(rows, cols);
+    r.k = k;
+    double2* work = static_cast<double2*>(ctx->workspace("svd_work", sizeof(double2) * (size_t)rows * cols));
+    double2* Ubuf = static_cast<double2*>(ctx->workspace("svd_U", sizeof(double2) * (size_t)cols * k));
+    double2* Vbuf = static_cast<double2*>(ctx->workspace("svd_V", sizeof(double2) * (size_t)k * rows));
+    double* S = static_cast<double*>(ctx->workspace("svd_S", sizeof(double) * (size_t)k));
+    double* E = static_cast<double*>(ctx->workspace("svd_E", sizeof(double) * (size_t)std::max(k, 1)));
+    int* dinfo = static_cast<int*>(ctx->workspace("svd_info", sizeof(int)));
+    TDVP_CHECK_HIP(hipMemcpyAsync(work, M, sizeof(double2) * (size_t)rows * cols, hipMemcpyDeviceToDevice, ctx->stream));
+    check_rs(rocsolver_zgesvd(ctx->blas, rocblas_svect_singular, rocblas_svect_singular, cols, rows,
+                              rz(work), cols, S, rz(Ubuf), cols, rz(Vbuf), k, E,
+                              rocblas_outofplace, dinfo),
+             "zgesvd");
+    int hinfo = 0;
+    r.S.resize(k);
+    TDVP_CHECK_HIP(hipMemcpyAsync(r.S.data(), S, sizeof(double) * k, hipMemcpyDeviceToHost, ctx->stream));
+    TDVP_CHECK_HIP(hipMemcpyAsync(&hinfo, dinfo, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    TDVP_CHECK_HIP(hipStreamSynchronize(ctx->stream));
+    TDVP_REQUIRE(hinfo == 0, TDVP_E_SOLVER, "zgesvd did not converge (info = " + std::to_string(hinfo) + ")");
+    for (double v : r.S) TDVP_REQUIRE(std::isfinite(v), TDVP_E_NUMERIC, "SVD: non-finite singular value");
+    r.U = Vbuf;   // row-major [rows][k]
+    r.Vh = Ubuf;  // row-major [k][cols]
+    r.S_dev = S;
+    return r;
+}
+
+}  // namespace tdvp

@@ -1,0 +1,62 @@
+"""Host-side checks of the C ABI: the library loads, exports what the header
+declares, and rejects bad arguments without touching a GPU."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1912_06127_amd as pkg
+from paper_1912_06127_amd import _lib
+from oracle import mpo as omp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "tdvp.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^(?:int|const char\*)\s+(\w+)\s*\(", text, flags=re.M)))
+
+
+def test_library_exports_every_header_function():
+    lib = _lib.load()
+    names = header_functions()
+    assert len(names) >= 25
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(_lib.SIGNATURES)
+
+
+def test_version_and_default_options():
+    lib = _lib.load()
+    assert lib.tdvp_version().startswith(b"tdvp-gfx950")
+    o = _lib.Opts()
+    assert lib.tdvp_opts_default(C.byref(o)) == 0
+    assert o.compute == _lib.TDVP_C128 and o.krylov_max == 40 and o.multiplet_guard == 1
+    assert lib.tdvp_opts_default(None) == 1
+
+
+def test_null_arguments_are_rejected():
+    lib = _lib.load()
+    assert lib.tdvp_ctx_destroy(None) == 1
+    assert lib.tdvp_ctx_sync(None) == 1
+    assert lib.apply_heff(None, 2, 0, 4, 4, 2, 3, 3, 3, None, None, None, None, None, None) == 1
+    assert lib.env_update(None, 1, 0, 4, 4, 2, 3, 3, None, None, None, None) == 1
+    assert lib.mps_destroy(None) == 1 and lib.mpo_destroy(None) == 1
+    assert lib.tdvp1_step(None, None, None, 0.1, None, None) == 1
+    assert lib.tdvp_last_error(None) == b"null context"
+    h = C.c_void_p()
+    assert lib.tdvp_ctx_create(0, None, _lib.ALLOC_FN(), _lib.FREE_FN(), None, None) == 1
+
+
+def test_package_fit_matches_oracle_fit():
+    # the package and the oracle implement the fit independently
+    for alpha, K, R in [(0.75, 4, 100), (2.0, 6, 63), (1.5, 6, 200)]:
+        c1, l1, e1 = pkg.fit.fit_power_law(alpha, K, R)
+        c2, l2, e2 = omp.fit_exponentials(1.0 / np.arange(1, R + 1) ** alpha, K)
+        g1 = pkg.fit.coupling_values(c1, l1, R)
+        g2 = omp.eval_exponentials(c2, l2, R)[1:]
+        assert np.max(np.abs(g1 - g2)) < 1e-10
+        assert abs(e1 - e2) < 1e-10

@@ -1,0 +1,185 @@
+"""Parity of the HIP effective-Hamiltonian and environment kernels with the
+FP64 oracle (Sec. III A, Fig. update; environments figure).
+
+Tolerances (norm-wise relative error of the whole output, or of the sampled
+outputs at full size): complex128 path 1e-12, complex64 path (FP32 MFMA, FP32
+accumulation) 1e-5.
+"""
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import env as oenv
+from oracle import heff as oheff
+from oracle import mpo as ompo
+from oracle import spin
+from tests.adapters import L_from_beta, R_from_gamma, rel_err
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"c64": 1e-5, "c128": 1e-12}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1912_06127_amd as pkg
+    c = pkg.Context(0)
+    yield c
+    c.sync()
+    c.close()
+
+
+def _t(x, dt):
+    import torch
+    tdt = torch.complex64 if dt == "c64" else torch.complex128
+    return torch.from_numpy(np.ascontiguousarray(x)).to(device="cuda", dtype=tdt)
+
+
+def _h(t):
+    return t.detach().to("cpu", dtype=__import__("torch").complex128).numpy()
+
+
+def random_case(seed, nsite, chil, chir, d, wl_, wm, wr):
+    rng = np.random.default_rng(seed)
+    beta = wl.cgauss(rng, (chil, wl_, chil))
+    gamma = wl.cgauss(rng, (chir, wr, chir))
+    if nsite == 2:
+        W1 = wl.cgauss(rng, (wl_, wm, d, d))
+        W2 = wl.cgauss(rng, (wm, wr, d, d))
+        theta = wl.cgauss(rng, (chil, d, d, chir))
+    elif nsite == 1:
+        W1 = wl.cgauss(rng, (wl_, wr, d, d))
+        W2 = None
+        theta = wl.cgauss(rng, (chil, d, chir))
+    else:
+        W1 = W2 = None
+        theta = wl.cgauss(rng, (chil, chir))
+    return beta, W1, W2, gamma, theta
+
+
+def oracle_heff(nsite, beta, W1, W2, gamma, theta):
+    if nsite == 2:
+        return oheff.apply_heff2(beta, W1, W2, gamma, theta)
+    if nsite == 1:
+        return oheff.apply_heff1(beta, W1, gamma, theta)
+    return oheff.apply_heff0(beta, gamma, theta)
+
+
+def run_gpu(ctx, dt, beta, W1, W2, gamma, theta):
+    import paper_1912_06127_amd as pkg
+    L = _t(L_from_beta(beta), dt)
+    R = _t(R_from_gamma(gamma), dt)
+    y = pkg.apply_heff(ctx, L, R, _t(theta, dt), None if W1 is None else _t(W1, dt),
+                       None if W2 is None else _t(W2, dt))
+    ctx.sync()
+    return _h(y)
+
+
+CASES = [
+    # nsite, chil, chir, d, wl, wm, wr
+    (2, 37, 45, 2, 5, 4, 6),
+    (2, 150, 130, 2, 7, 7, 7),
+    (2, 1, 1, 2, 1, 1, 1),
+    (2, 3, 2, 2, 3, 5, 1),
+    (1, 200, 170, 2, 11, 0, 9),
+    (1, 5, 7, 3, 4, 0, 3),
+    (1, 1, 2, 2, 1, 0, 5),
+    (0, 96, 96, 2, 8, 0, 8),
+    (0, 33, 17, 2, 3, 0, 3),
+]
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("case", CASES, ids=lambda c: "n%d_%dx%d_d%d_w%d.%d.%d" % c)
+def test_apply_heff_matches_oracle(ctx, dt, case):
+    nsite, chil, chir, d, wl_, wm, wr = case
+    print(f"apply_heff nsite={nsite} chil={chil} chir={chir} d={d} w={wl_},{wm},{wr} {dt}", flush=True)
+    beta, W1, W2, gamma, theta = random_case(hash(case) % 1000, *case)
+    ref = oracle_heff(nsite, beta, W1, W2, gamma, theta)
+    y = run_gpu(ctx, dt, beta, W1, W2, gamma, theta)
+    assert y.shape == ref.shape
+    assert rel_err(y, ref) <= TOL[dt]
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_apply_heff_multi_tile_shape(ctx, dt):
+    # 512-wide bond: the large-tile GEMM configuration of both precisions
+    print(f"apply_heff two-site D=512 w=10 {dt}", flush=True)
+    beta, W1, W2, gamma, theta = random_case(512, 2, 512, 512, 2, 10, 10, 10)
+    ref = oracle_heff(2, beta, W1, W2, gamma, theta)
+    y = run_gpu(ctx, dt, beta, W1, W2, gamma, theta)
+    assert rel_err(y, ref) <= TOL[dt]
+
+
+def xy_bulk_mpo(alpha=0.75, K=4, rmax=100):
+    fvals = 1.0 / np.arange(1, rmax + 1) ** alpha
+    c, lam, _ = ompo.fit_exponentials(fvals, K)
+    Ws = ompo.mpo_exponentials(6, c, lam, spin.xy_pairs())
+    return Ws[2]  # bulk tensor, w = 2K + 2
+
+
+@pytest.mark.parametrize("dt", ["c64", "c128"])
+def test_apply_heff_full_size_sampled(ctx, dt):
+    """Two-site microbenchmark input at D = 1024, w = 10: sampled rows y[a', :, :, b']."""
+    import paper_1912_06127_amd as pkg
+    D, w = 1024, 10
+    print(f"apply_heff full size D={D} {dt}", flush=True)
+    Lk, Rk, theta = wl.heff_micro_inputs(D, w)
+    W = xy_bulk_mpo()
+    assert W.shape[0] == w
+    y = pkg.apply_heff(ctx, _t(Lk, dt), _t(Rk, dt), _t(theta, dt), _t(W, dt), _t(W, dt))
+    ctx.sync()
+    yh = _h(y)
+    beta = np.transpose(Lk, (1, 0, 2))   # L[k][a'][a] -> beta[a', k, a]
+    gamma = np.transpose(Rk, (2, 0, 1))  # R[l][b][b'] -> gamma[b', l, b]
+    rng = np.random.default_rng(7)
+    num = den = 0.0
+    for a1, b1 in zip(rng.integers(0, D, 6), rng.integers(0, D, 6)):
+        ref = oheff.apply_heff2(beta[[a1]], W, W, gamma[[b1]], theta)[0, :, :, 0]
+        got = yh[a1, :, :, b1]
+        num += np.linalg.norm(got - ref) ** 2
+        den += np.linalg.norm(ref) ** 2
+    assert np.sqrt(num / den) <= TOL[dt]
+    assert np.all(np.isfinite(yh))
+
+
+ENV_CASES = [
+    # chil, chir, d, wl, wr
+    (40, 52, 2, 6, 5),
+    (130, 150, 2, 11, 11),
+    (1, 2, 2, 1, 11),
+    (7, 3, 3, 4, 2),
+]
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("direction", [1, -1])
+@pytest.mark.parametrize("case", ENV_CASES, ids=lambda c: "%dx%d_d%d_w%d.%d" % c)
+def test_env_update_matches_oracle(ctx, dt, direction, case):
+    import paper_1912_06127_amd as pkg
+    chil, chir, d, wl_, wr = case
+    print(f"env_update dir={direction} {case} {dt}", flush=True)
+    rng = np.random.default_rng(chil * 1000 + chir)
+    A = wl.cgauss(rng, (chil, d, chir))
+    W = wl.cgauss(rng, (wl_, wr, d, d))
+    if direction == 1:
+        beta = wl.cgauss(rng, (chil, wl_, chil))
+        ref = L_from_beta(oenv.update_left(beta, A, W))
+        out = pkg.env_update(ctx, 1, _t(L_from_beta(beta), dt), _t(A, dt), _t(W, dt))
+    else:
+        gamma = wl.cgauss(rng, (chir, wr, chir))
+        ref = R_from_gamma(oenv.update_right(gamma, A, W))
+        out = pkg.env_update(ctx, -1, _t(R_from_gamma(gamma), dt), _t(A, dt), _t(W, dt))
+    ctx.sync()
+    assert rel_err(_h(out), ref) <= TOL[dt]
+
+
+def test_apply_heff_rejects_bad_arguments(ctx):
+    import torch
+    import paper_1912_06127_amd as pkg
+    L = torch.zeros((3, 4, 4), dtype=torch.complex128, device="cuda")
+    R = torch.zeros((2, 4, 4), dtype=torch.complex128, device="cuda")
+    theta = torch.zeros((4, 4), dtype=torch.complex128, device="cuda")
+    with pytest.raises(pkg.TDVPError) as e:  # zero-site needs wl == wr
+        pkg.apply_heff(ctx, L, R, theta)
+    assert e.value.status == 2
