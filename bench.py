@@ -1,0 +1,274 @@
+#!/usr/bin/env python3
+"""Benchmark of the TDVP hot path on one MI355X.
+
+Workload: the two-site effective-Hamiltonian application H_eff Theta
+(L.W.W.R.Theta, Sec. III A, Eq. eqnscaling) at bond dimension D = 1024,
+d = 2, MPO bond w = 10 (long-range XY, alpha = 0.75, K = 4 exponentials per
+channel), environments Hermitian per MPO index with complex Gaussian entries,
+Theta a unit-norm complex Gaussian.  One step = one application.  The
+headline runs complex64 on FP32 MFMA (3M form, FP32 accumulation); the same
+line reports the complex128 (FP64 MFMA) path, the D = 128..1024 sweep, a
+2TDVP sweep timing, the roofline of the dominant kernel and the FP64 CPU
+oracle timed on the host cores.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_FP64_MFMA_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "heff_cgemm_f32_D1024_pmc.txt")
+GEMM_SOURCE = os.path.join(ROOT, "paper_1912_06127_amd", "csrc", "gemm.hip")
+
+
+def heff2_flops(D: int, w: int, d: int = 2) -> float:
+    """Algorithmic flops of one two-site application, 8 per complex MAC (Eq. eqnscaling)."""
+    return 16.0 * w * d * d * D ** 3 + 16.0 * w * w * d ** 3 * D ** 2
+
+
+def xy_bulk_tensor(pkg, ctx, alpha=0.75, K=4, rmax=100):
+    import numpy as np
+    c, lam, _ = pkg.fit.fit_power_law(alpha, K, rmax)
+    half = 0.5
+    sx = np.array(pkg.PAULI_X, dtype=np.complex128)
+    sy = np.array(pkg.PAULI_Y, dtype=np.complex128)
+    mpo = pkg.MPO.longrange(ctx, 6, [(half, sx, sx), (half, sy, sy)], c=c, lam=lam)
+    W = mpo.tensor(2)
+    mpo.close()
+    return W
+
+
+def gemm_source_hash() -> str:
+    return hashlib.sha256(open(GEMM_SOURCE, "rb").read()).hexdigest()[:16]
+
+
+def traffic_from_profiles(D: int):
+    """HBM bytes per launch of the dominant kernel from the committed PMC summary,
+    or None when the summary is missing or was taken on a different kernel source."""
+    if not os.path.exists(PMC_SUMMARY):
+        return None
+    text = open(PMC_SUMMARY).read()
+    m_hash = re.search(r"gemm_source_sha256_16:\s*([0-9a-f]+)", text)
+    m_bytes = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not (m_hash and m_bytes) or m_hash.group(1) != gemm_source_hash():
+        return None
+    return float(m_bytes.group(1))
+
+
+def time_heff(pkg, ctx, torch, tensors, steps, warmup, profile=False):
+    L, R, th, W = tensors
+    out = torch.empty_like(th)
+    for _ in range(warmup):
+        pkg.apply_heff(ctx, L, R, th, W, W, out=out)
+    torch.cuda.synchronize()
+    if profile:
+        ctx.profile(True)
+        ctx.profile_read()
+    stream = ctx.stream
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(steps):
+        pkg.apply_heff(ctx, L, R, th, W, W, out=out)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    prof = ctx.profile_read() if profile else {}
+    if profile:
+        ctx.profile(False)
+    return ev0.elapsed_time(ev1) / steps, prof, out
+
+
+def device_inputs(torch, wl, W, D, w, dtype):
+    Lk, Rk, theta = wl.heff_micro_inputs(D, w)
+    to = lambda x: torch.from_numpy(x).to(device="cuda", dtype=dtype)
+    return to(Lk), to(Rk), to(theta), to(W)
+
+
+def cpu_baseline(wl, W, D=512, reps=2):
+    """FP64 oracle einsum on the host cores for a bounded sample of the workload."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+    from oracle import heff as oheff
+    Lk, Rk, theta = wl.heff_micro_inputs(D, 10)
+    beta = np.transpose(Lk, (1, 0, 2))
+    gamma = np.transpose(Rk, (2, 0, 1))
+    oheff.apply_heff2(beta[:8], W, W, gamma[:8], theta[:8])  # warm the path search
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        oheff.apply_heff2(beta, W, W, gamma, theta)
+    dt = (time.perf_counter() - t0) / reps
+    threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    return {
+        "value": round(heff2_flops(D, 10) / dt * 1e-9, 3),
+        "unit": "GFLOP/s",
+        "cores": int(threads),
+        "kind": "oracle",
+        "sample": f"{reps} two-site H_eff applications at D={D}, w=10 (numpy einsum, complex128), "
+                  f"{dt:.2f} s each; host has {os.cpu_count()} logical CPUs",
+    }
+
+
+def sweep_timing(pkg, ctx, steps=2):
+    """2TDVP time steps on the N=64 1/r^2 XXX chain (K = 6, w = 20) at bond dimension 512."""
+    import numpy as np
+    N, cap = 64, 512
+    c, lam, _ = pkg.fit.fit_power_law(2.0, 6, N - 1)
+    sx, sy, sz = (np.array(p, dtype=np.complex128) for p in (pkg.PAULI_X, pkg.PAULI_Y, pkg.PAULI_Z))
+    mpo = pkg.MPO.longrange(ctx, N, [(0.25, sx, sx), (0.25, sy, sy), (0.25, sz, sz)], c=c, lam=lam)
+    chi = [min(2 ** min(j, N - j), cap) for j in range(N + 1)]
+    res = {}
+    for comp in ("c64", "c128"):
+        mps = pkg.MPS.init(ctx, N, 2, chi, seed=64)
+        opts = pkg.TDVPOptions(compute=comp, chi_max=cap, w_max=0.0, eps_rel=1e-12, krylov_max=40,
+                               krylov_tol=1e-10)
+        times, flops, mv = [], 0.0, 0
+        for _ in range(steps):
+            st = pkg.tdvp2_step(ctx, mps, mpo, 0.05, opts)
+            times.append(st["seconds"])
+            flops += st["flops"]
+            mv += st["matvecs"]
+        res[comp] = {"s_per_step": round(float(np.mean(times)), 4), "matvecs_per_step": mv / steps,
+                     "heff_env_gflops": round(flops / sum(times) * 1e-9, 1)}
+        mps.close()
+    mpo.close()
+    res["workload"] = "2TDVP step, N=64 XXX 1/r^2 (K=6, w=20), chi=min(2^j, 2^(N-j), 512), dt=0.05"
+    return res
+
+
+def copy_calibration(torch, gib=1):
+    """Plain device copy of known size, used to scale HBM byte counters."""
+    n = gib * (1 << 30) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_each_way": n * 4, "launches": 5}))
+
+
+def progress(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="headline kernel only (for profiling)")
+    ap.add_argument("--sweep-steps", type=int, default=0)
+    ap.add_argument("--copy-calibration", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "n_gpus_requested": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_1912_06127_amd as pkg
+    import workloads as wl
+
+    if args.copy_calibration:
+        copy_calibration(torch)
+        return
+
+    ctx = pkg.Context(0)
+    D, w = 1024, 10
+    W = xy_bulk_tensor(pkg, ctx)
+    assert W.shape == (w, w, 2, 2)
+    F = heff2_flops(D, w)
+
+    progress("inputs ready; timing complex64 D=1024")
+    x64 = device_inputs(torch, wl, W, D, w, torch.complex64)
+    ms64, prof64, _ = time_heff(pkg, ctx, torch, x64, args.steps, args.warmup, profile=True)
+    value = F / (ms64 * 1e-3) * 1e-9
+    del x64
+
+    # dominant kernel: the FP32 3M GEMM of both H_eff stages
+    kname = max(prof64, key=lambda k: prof64[k]["ms"])
+    kp = prof64[kname]
+    achieved = kp["flops"] / (kp["ms"] * 1e-3) * 1e-12
+    per_launch_flops = kp["flops"] / kp["count"]
+    per_launch_ms = kp["ms"] / kp["count"]
+    traffic = traffic_from_profiles(D)
+    roofline = {
+        "bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
+        "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 4), "traffic": traffic,
+        "kernel": kname, "launches": kp["count"], "avg_launch_us": round(per_launch_ms * 1e3, 1),
+        "algorithmic_flops_per_launch": per_launch_flops,
+        "mfma_executed_frac": round(0.75 * achieved / PEAK_FP32_MFMA_TFLOPS, 4),
+        "kernel_share_of_step": round(kp["ms"] / (ms64 * args.steps), 3),
+        "other_kernels_ms_per_step": {k: round(v["ms"] / args.steps, 4) for k, v in prof64.items() if k != kname},
+    }
+
+    line = {
+        "metric": "apply_heff GFLOP/s + TDVP sweep s/step, FP32-MFMA vs FP64, at <=1e-4 obs err",
+        "value": round(value, 1),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms64, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "apply_heff two-site, D=1024, d=2, w=10 (long-range XY alpha=0.75, K=4), "
+                               "complex64 on FP32 MFMA (3M)",
+                   "D": D, "d": 2, "w": w, "parallelism": "single GPU"},
+        "roofline": roofline,
+    }
+
+    if not args.no_extras:
+        progress(f"complex64 {value:.0f} GFLOP/s; timing complex128")
+        x128 = device_inputs(torch, wl, W, D, w, torch.complex128)
+        ms128, prof128, _ = time_heff(pkg, ctx, torch, x128, max(3, args.steps // 2), 1, profile=True)
+        del x128
+        k128 = max(prof128, key=lambda k: prof128[k]["ms"])
+        a128 = prof128[k128]["flops"] / (prof128[k128]["ms"] * 1e-3) * 1e-12
+        line["fp64"] = {"gflops": round(F / (ms128 * 1e-3) * 1e-9, 1), "ms_per_step": round(ms128, 4),
+                        "kernel": k128, "kernel_tflops": round(a128, 2),
+                        "kernel_frac_of_fp64_peak": round(a128 / PEAK_FP64_MFMA_TFLOPS, 4)}
+        line["speedup_fp32_vs_fp64"] = round(ms128 / ms64, 2)
+        progress("D sweep")
+        byD = {}
+        for Dx in (128, 256, 512):
+            r = {}
+            for name, dt in (("c64", torch.complex64), ("c128", torch.complex128)):
+                xs = device_inputs(torch, wl, W, Dx, w, dt)
+                msx, _, _ = time_heff(pkg, ctx, torch, xs, 10, 2)
+                r[name] = round(heff2_flops(Dx, w) / (msx * 1e-3) * 1e-9, 1)
+                del xs
+            byD[str(Dx)] = r
+        byD["1024"] = {"c64": line["value"], "c128": line["fp64"]["gflops"]}
+        line["gflops_by_D"] = byD
+        if args.sweep_steps > 0:
+            progress("2TDVP sweep timing")
+            line["sweep"] = sweep_timing(pkg, ctx, args.sweep_steps)
+
+    if not args.no_cpu_baseline:
+        progress("CPU oracle baseline")
+        line["cpu_baseline"] = cpu_baseline(wl, W)
+
+    ctx.close()
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -79,6 +79,17 @@ int tdvp_ctx_sync(tdvp_ctx ctx);
 /* Library version string, e.g. "tdvp-gfx950 0.1". */
 const char* tdvp_version(void);
 
+/* Kernel timing.  With profiling on, every kernel launch of the library is
+ * bracketed by a HIP event pair on the context stream (a few microseconds of
+ * overhead per launch).  tdvp_profile_read synchronises the stream, returns
+ * per-kernel totals accumulated since the previous read and clears them:
+ * names [max_entries][64] (NUL-terminated), ms = summed event time, flops /
+ * bytes = summed algorithmic work (8 real flops per complex multiply-add;
+ * compulsory operand bytes), count = launches; *n_out = entries written. */
+int tdvp_profile_enable(tdvp_ctx ctx, int on);
+int tdvp_profile_read(tdvp_ctx ctx, int max_entries, char* names, double* ms, double* flops,
+                      double* bytes, long* count, int* n_out);
+
 /* -------------------------------------------------------------------- MPO */
 
 /* Long-range spin-chain Hamiltonian (Sec. II C, Sec. IV):

@@ -79,6 +79,8 @@ SIGNATURES = {
     "energy": (_I, [_P, _P, _P, _PD]),
     "norm2": (_I, [_P, _P, _PD]),
     "overlap": (_I, [_P, _P, _P, _PD]),
+    "tdvp_profile_enable": (_I, [_P, _I]),
+    "tdvp_profile_read": (_I, [_P, _I, C.c_char_p, _PD, _PD, _PD, C.POINTER(C.c_long), _PI]),
 }
 
 

@@ -108,6 +108,27 @@ class Context:
     def sync(self):
         _check(self.handle, _lib.load().tdvp_ctx_sync(self.handle))
 
+    def profile(self, on: bool = True):
+        """Bracket every library kernel launch with HIP events."""
+        _check(self.handle, _lib.load().tdvp_profile_enable(self.handle, int(on)))
+
+    def profile_read(self) -> dict:
+        """{kernel: {ms, flops, bytes, count}} since the last read (synchronises)."""
+        n = 256
+        names = C.create_string_buffer(64 * n)
+        ms, fl, by = np.zeros(n), np.zeros(n), np.zeros(n)
+        cnt = np.zeros(n, dtype=np.int64)
+        nout = C.c_int()
+        rc = _lib.load().tdvp_profile_read(self.handle, n, names, _dptr(ms), _dptr(fl), _dptr(by),
+                                           cnt.ctypes.data_as(C.POINTER(C.c_long)), C.byref(nout))
+        _check(self.handle, rc)
+        out = {}
+        raw = names.raw
+        for i in range(nout.value):
+            name = raw[64 * i:64 * (i + 1)].split(b"\0", 1)[0].decode()
+            out[name] = {"ms": float(ms[i]), "flops": float(fl[i]), "bytes": float(by[i]), "count": int(cnt[i])}
+        return out
+
     def close(self):
         if getattr(self, "handle", None):
             for child in list(self._children):

@@ -58,6 +58,16 @@ struct Buffer {
 
 }  // namespace tdvp
 
+struct tdvp_prof_rec {
+    std::string name;
+    hipEvent_t start, stop;
+    double flops, bytes;
+};
+struct tdvp_prof_total {
+    double ms = 0.0, flops = 0.0, bytes = 0.0;
+    long count = 0;
+};
+
 struct tdvp_ctx_s {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -67,6 +77,9 @@ struct tdvp_ctx_s {
     rocblas_handle blas = nullptr;
     std::string err;
     std::map<std::string, tdvp::Buffer> work;  // grow-only named workspaces
+    bool prof_on = false;                       // HIP event pair around every launch
+    std::vector<tdvp_prof_rec> prof_pending;
+    std::map<std::string, tdvp_prof_total> prof_total;
 
     void* dev_alloc(size_t bytes);
     void dev_free(void* p, size_t bytes);
@@ -76,6 +89,15 @@ struct tdvp_ctx_s {
 };
 
 namespace tdvp {
+
+// Records a HIP event pair around the launches in its scope when the
+// context's profiler is on; `flops` and `bytes` are the algorithmic work.
+struct ProfScope {
+    tdvp_ctx ctx;
+    size_t idx = (size_t)-1;
+    ProfScope(tdvp_ctx c, const char* name, double flops, double bytes);
+    ~ProfScope();
+};
 
 // RAII device allocation through the context allocator.
 struct DevMem {
@@ -125,7 +147,7 @@ struct GemmDesc {
 };
 
 // fp64: FP64 MFMA, else FP32 MFMA.  form: 3 (Gauss 3-real-product) or 4.
-void cgemm(const GemmDesc& g, bool fp64, int form, hipStream_t s);
+void cgemm(tdvp_ctx ctx, const GemmDesc& g, bool fp64, int form);
 
 // Sparse local-operator stage.  For every grid point (p, q):
 //   out[n][s'](p, q) = sum_{k,s} M[(n,s'),(k,s)] in[k][s](p, q)
@@ -141,7 +163,7 @@ struct WStageDesc {
     const void* val = nullptr;     // device [nnz] complex of the compute dtype
     bool fp64 = false;
 };
-void wstage(const WStageDesc& w, hipStream_t s);
+void wstage(tdvp_ctx ctx, const WStageDesc& w);
 
 // ----------------------------------------------- FP64 vector kernels (c128)
 // All pointers device; n complex elements.

@@ -97,7 +97,7 @@ void heff_apply(tdvp_ctx ctx, const HeffArgs& a, const void* x, Dt x_dt, void* y
     g1.C = T1;
     g1.cdt = cdt;
     g1.ldc = D * chir;
-    cgemm(g1, a.fp64, a.form, ctx->stream);
+    cgemm(ctx, g1, a.fp64, a.form);
 
     // MPO stage: T3[a'][s'][n][b] = sum_{k,s} M[(n,s'),(k,s)] T1[k][a'][s][b]
     WStageDesc w;
@@ -120,7 +120,7 @@ void heff_apply(tdvp_ctx ctx, const HeffArgs& a, const void* x, Dt x_dt, void* y
     w.col = a.mop->col;
     w.val = a.mop->val;
     w.fp64 = a.fp64;
-    wstage(w, ctx->stream);
+    wstage(ctx, w);
 
     // Stage B: y[(a' s')][b'] = sum_{(n b)} T3[(a' s')][(n b)] R[(n b)][b']
     GemmDesc g2;
@@ -132,7 +132,7 @@ void heff_apply(tdvp_ctx ctx, const HeffArgs& a, const void* x, Dt x_dt, void* y
     g2.C = y;
     g2.cdt = y_dt;
     g2.ldc = chir;
-    cgemm(g2, a.fp64, a.form, ctx->stream);
+    cgemm(ctx, g2, a.fp64, a.form);
 }
 
 void env_left(tdvp_ctx ctx, const EnvArgs& a, const void* L, Dt l_dt, void* out, Dt out_dt) {
@@ -154,7 +154,7 @@ void env_left(tdvp_ctx ctx, const EnvArgs& a, const void* L, Dt l_dt, void* out,
     g1.C = X;
     g1.cdt = cdt;
     g1.ldc = d * chir;
-    cgemm(g1, a.fp64, a.form, ctx->stream);
+    cgemm(ctx, g1, a.fp64, a.form);
 
     // Y[l][a'][s'][b] = sum_{k,s} W[k][l][s'][s] X[k][a'][s][b]
     WStageDesc w;
@@ -177,7 +177,7 @@ void env_left(tdvp_ctx ctx, const EnvArgs& a, const void* L, Dt l_dt, void* out,
     w.col = a.mop->col;
     w.val = a.mop->val;
     w.fp64 = a.fp64;
-    wstage(w, ctx->stream);
+    wstage(ctx, w);
 
     // out[l][b'][b] = sum_{(a' s')} conj(Abra[(a' s')][b']) Y[l][(a' s')][b]
     GemmDesc g2;
@@ -191,7 +191,7 @@ void env_left(tdvp_ctx ctx, const EnvArgs& a, const void* L, Dt l_dt, void* out,
     g2.cdt = out_dt;
     g2.ldc = chir;
     g2.strideC = chirb * chir;
-    cgemm(g2, a.fp64, a.form, ctx->stream);
+    cgemm(ctx, g2, a.fp64, a.form);
 }
 
 void env_right(tdvp_ctx ctx, const EnvArgs& a, const void* R, Dt r_dt, void* out, Dt out_dt) {
@@ -215,7 +215,7 @@ void env_right(tdvp_ctx ctx, const EnvArgs& a, const void* R, Dt r_dt, void* out
     g1.cdt = cdt;
     g1.ldc = a.wr * chirb;
     g1.strideC = chirb;
-    cgemm(g1, a.fp64, a.form, ctx->stream);
+    cgemm(ctx, g1, a.fp64, a.form);
 
     // V[k][a][s'][b'] = sum_{l,s} W[k][l][s'][s] U[a][s][l][b']
     WStageDesc w;
@@ -238,7 +238,7 @@ void env_right(tdvp_ctx ctx, const EnvArgs& a, const void* R, Dt r_dt, void* out
     w.col = a.mop->col;
     w.val = a.mop->val;
     w.fp64 = a.fp64;
-    wstage(w, ctx->stream);
+    wstage(ctx, w);
 
     // out[(k a)][a'] = sum_{(s' b')} V[(k a)][(s' b')] conj(Abra[a'][(s' b')])
     GemmDesc g2;
@@ -250,7 +250,7 @@ void env_right(tdvp_ctx ctx, const EnvArgs& a, const void* R, Dt r_dt, void* out
     g2.C = out;
     g2.cdt = out_dt;
     g2.ldc = chilb;
-    cgemm(g2, a.fp64, a.form, ctx->stream);
+    cgemm(ctx, g2, a.fp64, a.form);
 }
 
 }  // namespace tdvp

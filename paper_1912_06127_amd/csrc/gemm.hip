@@ -24,6 +24,8 @@
 // by zero-filled staging and guarded stores.
 #include "common.hpp"
 
+#include <cstdio>
+
 namespace tdvp {
 namespace {
 
@@ -277,19 +279,26 @@ KOperand to_k(const GemmOperand& o) {
 }
 
 template <typename T, int WTM, int WTN, int BK, bool M3>
-void launch(KParams kp, int batch, hipStream_t s) {
+void launch(tdvp_ctx ctx, KParams kp, int batch) {
     constexpr int MT = Mfma<T>::MT;
     constexpr int BM = 2 * WTM * MT, BN = 2 * WTN * MT;
     kp.tiles_m = (kp.M + BM - 1) / BM;
     kp.tiles_n = (kp.N + BN - 1) / BN;
     dim3 grid(kp.tiles_m * kp.tiles_n, 1, batch);
-    hipLaunchKernelGGL((cgemm_kernel<T, WTM, WTN, BK, M3>), grid, dim3(256), 0, s, kp);
+    char name[64];
+    snprintf(name, sizeof(name), "cgemm_%s_%s_%dx%d", sizeof(T) == 4 ? "f32" : "f64", M3 ? "3m" : "4m", BM, BN);
+    const double flops = 8.0 * kp.M * (double)kp.N * kp.K * batch;
+    const double bytes = (double)batch * ((double)kp.M * kp.K * (kp.A.c128 ? 16 : 8) * (kp.A.stride ? 1 : 1.0 / batch) +
+                                          (double)kp.K * kp.N * (kp.B.c128 ? 16 : 8) * (kp.B.stride ? 1 : 1.0 / batch) +
+                                          (double)kp.M * kp.N * (kp.c128C ? 16 : 8));
+    ProfScope prof(ctx, name, flops, bytes);
+    hipLaunchKernelGGL((cgemm_kernel<T, WTM, WTN, BK, M3>), grid, dim3(256), 0, ctx->stream, kp);
     TDVP_CHECK_HIP(hipGetLastError());
 }
 
 }  // namespace
 
-void cgemm(const GemmDesc& g, bool fp64, int form, hipStream_t s) {
+void cgemm(tdvp_ctx ctx, const GemmDesc& g, bool fp64, int form) {
     TDVP_REQUIRE(g.M >= 0 && g.N >= 0 && g.K >= 0 && g.batch >= 1, TDVP_E_SHAPE, "cgemm: bad sizes");
     TDVP_REQUIRE(g.batch <= 65535, TDVP_E_SHAPE, "cgemm: batch too large");
     if (g.M == 0 || g.N == 0) return;
@@ -308,20 +317,20 @@ void cgemm(const GemmDesc& g, bool fp64, int form, hipStream_t s) {
     if (fp64) {
         const int64_t big_tiles = ((g.M + 127) / 128) * (int64_t)((g.N + 63) / 64) * g.batch;
         if (big_tiles >= 512) {
-            if (m3) launch<double, 4, 2, 8, true>(kp, g.batch, s);
-            else launch<double, 4, 2, 8, false>(kp, g.batch, s);
+            if (m3) launch<double, 4, 2, 8, true>(ctx, kp, g.batch);
+            else launch<double, 4, 2, 8, false>(ctx, kp, g.batch);
         } else {
-            if (m3) launch<double, 2, 1, 8, true>(kp, g.batch, s);
-            else launch<double, 2, 1, 8, false>(kp, g.batch, s);
+            if (m3) launch<double, 2, 1, 8, true>(ctx, kp, g.batch);
+            else launch<double, 2, 1, 8, false>(ctx, kp, g.batch);
         }
     } else {
         const int64_t big_tiles = ((g.M + 127) / 128) * (int64_t)((g.N + 127) / 128) * g.batch;
         if (big_tiles >= 512) {
-            if (m3) launch<float, 2, 2, 16, true>(kp, g.batch, s);
-            else launch<float, 2, 2, 16, false>(kp, g.batch, s);
+            if (m3) launch<float, 2, 2, 16, true>(ctx, kp, g.batch);
+            else launch<float, 2, 2, 16, false>(ctx, kp, g.batch);
         } else {
-            if (m3) launch<float, 1, 1, 16, true>(kp, g.batch, s);
-            else launch<float, 1, 1, 16, false>(kp, g.batch, s);
+            if (m3) launch<float, 1, 1, 16, true>(ctx, kp, g.batch);
+            else launch<float, 1, 1, 16, false>(ctx, kp, g.batch);
         }
     }
 }

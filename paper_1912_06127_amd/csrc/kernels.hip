@@ -317,7 +317,8 @@ inline unsigned nblk(int64_t n) { return (unsigned)((n + kVecThreads - 1) / kVec
 
 }  // namespace
 
-void wstage(const WStageDesc& d, hipStream_t s) {
+void wstage(tdvp_ctx ctx, const WStageDesc& d) {
+    hipStream_t s = ctx->stream;
     if (d.P == 0 || d.Q == 0) return;
     WParams w;
     w.in = d.in;
@@ -341,6 +342,9 @@ void wstage(const WStageDesc& d, hipStream_t s) {
     TDVP_REQUIRE(shmem <= 160 * 1024, TDVP_E_SHAPE, "wstage: MPO bond dimension too large");
     TDVP_REQUIRE(d.P <= 65535 * 1024, TDVP_E_SHAPE, "wstage: grid too large");
     dim3 grid((d.Q + nt - 1) / nt, d.P);
+    const double pts = (double)d.P * d.Q;
+    ProfScope prof(ctx, d.fp64 ? "wstage_f64" : "wstage_f32", 0.0,
+                   pts * (w.nin * elem_bytes(d.in_dt) + w.nout * elem_bytes(d.out_dt)));
     if (d.fp64) hipLaunchKernelGGL(wstage_kernel<double>, grid, dim3(nt), shmem, s, w);
     else hipLaunchKernelGGL(wstage_kernel<float>, grid, dim3(nt), shmem, s, w);
     TDVP_CHECK_HIP(hipGetLastError());

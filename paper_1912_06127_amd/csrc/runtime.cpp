@@ -132,3 +132,69 @@ int tdvp_opts_default(tdvp_opts* o) {
 }
 
 }  // extern "C"
+
+// ----------------------------------------------------------------- profiler
+
+namespace tdvp {
+
+ProfScope::ProfScope(tdvp_ctx c, const char* name, double flops, double bytes) : ctx(c) {
+    if (!ctx || !ctx->prof_on) return;
+    tdvp_prof_rec r;
+    r.name = name;
+    r.flops = flops;
+    r.bytes = bytes;
+    TDVP_CHECK_HIP(hipEventCreate(&r.start));
+    TDVP_CHECK_HIP(hipEventCreate(&r.stop));
+    TDVP_CHECK_HIP(hipEventRecord(r.start, ctx->stream));
+    idx = ctx->prof_pending.size();
+    ctx->prof_pending.push_back(r);
+}
+
+ProfScope::~ProfScope() {
+    if (idx != (size_t)-1) (void)hipEventRecord(ctx->prof_pending[idx].stop, ctx->stream);
+}
+
+}  // namespace tdvp
+
+extern "C" {
+
+int tdvp_profile_enable(tdvp_ctx ctx, int on) {
+    if (!ctx) return TDVP_E_ARG;
+    ctx->prof_on = on != 0;
+    return TDVP_OK;
+}
+
+int tdvp_profile_read(tdvp_ctx ctx, int max_entries, char* names, double* ms, double* flops,
+                      double* bytes, long* count, int* n_out) {
+    if (!ctx || !n_out || (max_entries > 0 && (!names || !ms || !flops || !bytes || !count))) return TDVP_E_ARG;
+    return tdvp::guarded(ctx, [&] {
+        TDVP_CHECK_HIP(hipStreamSynchronize(ctx->stream));
+        for (auto& r : ctx->prof_pending) {
+            float t = 0.0f;
+            TDVP_CHECK_HIP(hipEventElapsedTime(&t, r.start, r.stop));
+            auto& tot = ctx->prof_total[r.name];
+            tot.ms += t;
+            tot.flops += r.flops;
+            tot.bytes += r.bytes;
+            tot.count += 1;
+            (void)hipEventDestroy(r.start);
+            (void)hipEventDestroy(r.stop);
+        }
+        ctx->prof_pending.clear();
+        int i = 0;
+        for (auto& kv : ctx->prof_total) {
+            if (i >= max_entries) break;
+            std::memset(names + 64 * i, 0, 64);
+            std::strncpy(names + 64 * i, kv.first.c_str(), 63);
+            ms[i] = kv.second.ms;
+            flops[i] = kv.second.flops;
+            bytes[i] = kv.second.bytes;
+            count[i] = kv.second.count;
+            ++i;
+        }
+        *n_out = i;
+        ctx->prof_total.clear();
+    });
+}
+
+}  // extern "C"

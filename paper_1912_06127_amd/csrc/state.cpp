@@ -18,7 +18,7 @@ void zgemm_nn(tdvp_ctx ctx, const double2* A, const double2* B, double2* C, int 
     g.C = C;
     g.cdt = Dt::C128;
     g.ldc = n;
-    cgemm(g, true, 4, ctx->stream);
+    cgemm(ctx, g, true, 4);
 }
 
 // splitmix64 (Steele, Lea, Flood 2014) -> uniform doubles -> Box-Muller normals
