@@ -92,8 +92,9 @@ def time_heff(pkg, ctx, torch, tensors, steps, warmup, profile=False):
 
 
 def device_inputs(torch, wl, W, D, w, dtype):
+    import numpy as np
     Lk, Rk, theta = wl.heff_micro_inputs(D, w)
-    to = lambda x: torch.from_numpy(x).to(device="cuda", dtype=dtype)
+    to = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(device="cuda", dtype=dtype).contiguous()
     return to(Lk), to(Rk), to(theta), to(W)
 
 
@@ -105,7 +106,6 @@ def cpu_baseline(wl, W, D=512, reps=2):
     Lk, Rk, theta = wl.heff_micro_inputs(D, 10)
     beta = np.transpose(Lk, (1, 0, 2))
     gamma = np.transpose(Rk, (2, 0, 1))
-    oheff.apply_heff2(beta[:8], W, W, gamma[:8], theta[:8])  # warm the path search
     t0 = time.perf_counter()
     for _ in range(reps):
         oheff.apply_heff2(beta, W, W, gamma, theta)

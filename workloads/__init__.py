@@ -21,7 +21,7 @@ def hermitian_stack(seed: int, w: int, D: int) -> np.ndarray:
     """w Hermitian D x D blocks (G + G^H) / (2 sqrt(D)), complex Gaussian G."""
     rng = np.random.default_rng(seed)
     g = cgauss(rng, (w, D, D))
-    return (g + np.conj(np.transpose(g, (0, 2, 1)))) / (2.0 * np.sqrt(D))
+    return np.ascontiguousarray((g + np.conj(np.transpose(g, (0, 2, 1)))) / (2.0 * np.sqrt(D)))
 
 
 def unit_vector(seed: int, shape) -> np.ndarray:
