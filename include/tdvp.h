@@ -162,7 +162,13 @@ typedef struct {
     double eps_rel;      /* relative singular-value cut eps (Sec. III D) */
     int multiplet_guard; /* 1: never cut inside a degenerate multiplet */
     int strict;          /* 1: Krylov non-convergence returns TDVP_E_NOCONV */
-    int gemm_form;       /* 0 = default (3M for FP32, 4M for FP64), 3 = 3M, 4 = 4M */
+    int gemm_form;       /* 0 = default (3M for FP32, 4M for FP64), 3 = 3M, 4 = 4M;
+                            the FP64 path always uses 4M */
+    int svd_mode;        /* two-site split: 1 = SVD (one-sided Jacobi), 2 = eigen-
+                            decomposition of the reduced density matrix Theta Theta^dag
+                            (or Theta^dag Theta; eigenvalues = squared singular values,
+                            absolute accuracy ~1e-16 ||Theta||^2), 0 = automatic:
+                            density matrix when w_max >= 1e-13, else SVD */
 } tdvp_opts;
 
 typedef struct {
@@ -177,7 +183,7 @@ typedef struct {
 } tdvp_stats;
 
 /* Fill opts with defaults: C128, krylov_max 40, tol 1e-13, chi_max
- * 1<<30, w_max 0, eps_rel 0, guard on, strict off, gemm_form 0. */
+ * 1<<30, w_max 0, eps_rel 0, guard on, strict off, gemm_form 0, svd_mode 0. */
 int tdvp_opts_default(tdvp_opts* opts);
 
 /* One symmetric one-site TDVP step of size dt (Sec. II D, Eq. proj1site):

@@ -349,6 +349,7 @@ class TDVPOptions:
     multiplet_guard: bool = True
     strict: bool = False
     gemm_form: int = 0
+    svd_mode: int = 0           # 1 SVD, 2 density-matrix eigen-decomposition, 0 automatic
 
     def to_c(self) -> Opts:
         o = Opts()
@@ -361,6 +362,7 @@ class TDVPOptions:
         o.multiplet_guard = int(self.multiplet_guard)
         o.strict = int(self.strict)
         o.gemm_form = self.gemm_form
+        o.svd_mode = self.svd_mode
         return o
 
 

@@ -78,6 +78,7 @@ struct tdvp_ctx_s {
     std::string err;
     std::map<std::string, tdvp::Buffer> work;  // grow-only named workspaces
     bool prof_on = false;                       // HIP event pair around every launch
+    bool autotune = true;                       // time GEMM tiles per shape bucket
     std::vector<tdvp_prof_rec> prof_pending;
     std::map<std::string, tdvp_prof_total> prof_total;
 
@@ -186,6 +187,9 @@ void combine(double2* out, const double2* V, int64_t vstride, int nv, const doub
 // mask: 0 none, 1 zero where c < r (keep upper), 2 zero where c > r (keep lower)
 void copy2d(double2* dst, int64_t ldd, const double2* src, int64_t lds, int rows, int cols,
             int mask, hipStream_t s);
+// dst[c][r] = conj(src[r][c]) for r < rows, c < cols
+void conj_transpose(double2* dst, int64_t ldd, const double2* src, int64_t lds, int rows, int cols,
+                    hipStream_t s);
 // rows of V (row-major [rows][cols]) multiplied by real sv[r]
 void scale_rows(double2* V, int64_t ld, const double* sv, int rows, int cols, hipStream_t s);
 // columns of U (row-major [rows][cols]) multiplied by real sv[c]

@@ -25,6 +25,9 @@
 #include "common.hpp"
 
 #include <cstdio>
+#include <cstdlib>
+#include <mutex>
+#include <tuple>
 
 namespace tdvp {
 namespace {
@@ -95,26 +98,37 @@ __device__ inline void load_elem(const KOperand& o, int64_t idx, bool valid, T& 
     }
 }
 
-template <typename T, int WTM, int WTN, int BK, bool M3>
-__global__ void __launch_bounds__(256, 1) cgemm_kernel(KParams p) {
+// Second-generation tile: two LDS planes (re, im) per operand, the third 3M
+// operand (re + im) or the negated imaginary part (4M) formed in registers;
+// the LDS layout follows the operand's memory order so that staging stores
+// are conflict-free: k-contiguous operands are stored [outer][k] (each lane
+// reads its k-slice with vector loads), outer-contiguous operands [k][outer]
+// (consecutive lanes read consecutive outer indices).
+template <typename T, int BM, int BN, int BK, int WM, int WN, bool M3, bool AK, bool BKC>
+__global__ void __launch_bounds__(64 * WM * WN) cgemm2_kernel(KParams p) {
     using F = Mfma<T>;
     using acc_t = typename F::acc_t;
+    constexpr int NT = 64 * WM * WN;
     constexpr int MT = F::MT;
-    constexpr int BM = 2 * WTM * MT;
-    constexpr int BN = 2 * WTN * MT;
-    constexpr int S = BK / F::KT;               // instruction steps per k-tile
-    constexpr int LD = BK + (sizeof(T) == 4 ? 4 : 2);
-    constexpr int AE = BM * BK / 256;           // staged A elements per thread
-    constexpr int BE = BN * BK / 256;
-    constexpr int NA = M3 ? 3 : 2;              // accumulators per output tile
-    static_assert(AE * 256 == BM * BK && BE * 256 == BN * BK, "tile/thread mismatch");
+    constexpr int TM = BM / (WM * MT);  // MFMA tiles per wave along M
+    constexpr int TN = BN / (WN * MT);
+    static_assert(TM * WM * MT == BM && TN * WN * MT == BN, "tile shape");
+    constexpr int S = BK / F::KT;
+    constexpr int PADK = sizeof(T) == 4 ? 4 : 2;
+    constexpr int LDAk = BK + PADK;       // [outer][k] row stride
+    constexpr int LDAo = BM + PADK;       // [k][outer] row stride
+    constexpr int LDBo = BN + PADK;
+    constexpr int SA = AK ? BM * LDAk : BK * LDAo;
+    constexpr int SB = BKC ? BN * LDAk : BK * LDBo;
+    constexpr int AE = BM * BK / NT;
+    constexpr int BE = BN * BK / NT;
+    static_assert(AE * NT == BM * BK && BE * NT == BN * BK, "tile/thread mismatch");
+    static_assert(AE % 2 == 0 && BE % 2 == 0, "pairwise staging");
+    constexpr int NA = M3 ? 3 : 2;
 
-    __shared__ __align__(16) T sA[2][3][BM * LD];
-    __shared__ __align__(16) T sB[2][3][BN * LD];
+    __shared__ __align__(16) T sA[2][2][SA];
+    __shared__ __align__(16) T sB[2][2][SB];
 
-    // Block -> tile.  Consecutive tiles walk down M for a fixed N panel, and
-    // the hardware's round-robin dispatch over the 8 XCDs is undone so that
-    // one XCD gets a contiguous run of tiles (shared panels stay in its L2).
     const int ntiles = p.tiles_m * p.tiles_n;
     int t = blockIdx.x;
     if ((ntiles & 7) == 0) t = (t & 7) * (ntiles >> 3) + (t >> 3);
@@ -128,61 +142,63 @@ __global__ void __launch_bounds__(256, 1) cgemm_kernel(KParams p) {
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int wm = wave >> 1;
-    const int wn = wave & 1;
-    const int g = lane / MT;  // k group of this lane
-    const int r = lane % MT;  // row (A) / column (B) of this lane
+    const int wm = wave / WN;
+    const int wn = wave % WN;
+    const int g = lane / MT;
+    const int r = lane % MT;
 
     T ar[AE], ai[AE], br[BE], bi[BE];
 
     auto gload = [&](int k0) {
 #pragma unroll
-        for (int i = 0; i < AE; ++i) {
-            const int e = tid + 256 * i;
-            int o, k;
-            if (p.A.kcontig) { o = e / BK; k = e % BK; } else { k = e / BM; o = e % BM; }
+        for (int i = 0; i < AE / 2; ++i) {  // pairs along the contiguous index
+            const int e = 2 * (tid + NT * i);
+            const int o = AK ? e / BK : e % BM;
+            const int k = AK ? e % BK : e / BM;
             const int gm = m0 + o, gk = k0 + k;
-            const int64_t idx = p.A.kcontig ? (int64_t)gm * p.A.ld + gk : (int64_t)gk * p.A.ld + gm;
-            load_elem<T>(p.A, zA + idx, gm < p.M && gk < p.K, ar[i], ai[i]);
+            const int64_t idx = AK ? (int64_t)gm * p.A.ld + gk : (int64_t)gk * p.A.ld + gm;
+            const bool v0 = gm < p.M && gk < p.K;
+            const bool v1 = AK ? (gm < p.M && gk + 1 < p.K) : (gm + 1 < p.M && gk < p.K);
+            load_elem<T>(p.A, zA + idx, v0, ar[2 * i], ai[2 * i]);
+            load_elem<T>(p.A, zA + idx + 1, v1, ar[2 * i + 1], ai[2 * i + 1]);
         }
 #pragma unroll
-        for (int i = 0; i < BE; ++i) {
-            const int e = tid + 256 * i;
-            int o, k;
-            if (p.B.kcontig) { o = e / BK; k = e % BK; } else { k = e / BN; o = e % BN; }
+        for (int i = 0; i < BE / 2; ++i) {
+            const int e = 2 * (tid + NT * i);
+            const int o = BKC ? e / BK : e % BN;
+            const int k = BKC ? e % BK : e / BN;
             const int gn = n0 + o, gk = k0 + k;
-            const int64_t idx = p.B.kcontig ? (int64_t)gn * p.B.ld + gk : (int64_t)gk * p.B.ld + gn;
-            load_elem<T>(p.B, zB + idx, gn < p.N && gk < p.K, br[i], bi[i]);
+            const int64_t idx = BKC ? (int64_t)gn * p.B.ld + gk : (int64_t)gk * p.B.ld + gn;
+            const bool v0 = gn < p.N && gk < p.K;
+            const bool v1 = BKC ? (gn < p.N && gk + 1 < p.K) : (gn + 1 < p.N && gk < p.K);
+            load_elem<T>(p.B, zB + idx, v0, br[2 * i], bi[2 * i]);
+            load_elem<T>(p.B, zB + idx + 1, v1, br[2 * i + 1], bi[2 * i + 1]);
         }
     };
     auto lstore = [&](int buf) {
 #pragma unroll
         for (int i = 0; i < AE; ++i) {
-            const int e = tid + 256 * i;
-            int o, k;
-            if (p.A.kcontig) { o = e / BK; k = e % BK; } else { k = e / BM; o = e % BM; }
-            sA[buf][0][o * LD + k] = ar[i];
-            sA[buf][1][o * LD + k] = ai[i];
-            sA[buf][2][o * LD + k] = M3 ? ar[i] + ai[i] : -ai[i];
+            const int e = 2 * (tid + NT * (i / 2)) + (i & 1);
+            const int off = AK ? (e / BK) * LDAk + e % BK : (e / BM) * LDAo + e % BM;
+            sA[buf][0][off] = ar[i];
+            sA[buf][1][off] = ai[i];
         }
 #pragma unroll
         for (int i = 0; i < BE; ++i) {
-            const int e = tid + 256 * i;
-            int o, k;
-            if (p.B.kcontig) { o = e / BK; k = e % BK; } else { k = e / BN; o = e % BN; }
-            sB[buf][0][o * LD + k] = br[i];
-            sB[buf][1][o * LD + k] = bi[i];
-            if (M3) sB[buf][2][o * LD + k] = br[i] + bi[i];
+            const int e = 2 * (tid + NT * (i / 2)) + (i & 1);
+            const int off = BKC ? (e / BK) * LDAk + e % BK : (e / BN) * LDBo + e % BN;
+            sB[buf][0][off] = br[i];
+            sB[buf][1][off] = bi[i];
         }
     };
 
-    acc_t acc[NA][WTM][WTN];
+    acc_t acc[NA][TM][TN];
 #pragma unroll
     for (int q = 0; q < NA; ++q)
 #pragma unroll
-        for (int mi = 0; mi < WTM; ++mi)
+        for (int mi = 0; mi < TM; ++mi)
 #pragma unroll
-            for (int ni = 0; ni < WTN; ++ni)
+            for (int ni = 0; ni < TN; ++ni)
 #pragma unroll
                 for (int v = 0; v < F::NACC; ++v) acc[q][mi][ni][v] = T(0);
 
@@ -196,40 +212,41 @@ __global__ void __launch_bounds__(256, 1) cgemm_kernel(KParams p) {
     for (int kt = 0; kt < nk; ++kt) {
         const int cur = kt & 1;
         if (kt + 1 < nk) gload((kt + 1) * BK);
-
-        T fa[3][WTM][S], fb[3][WTN][S];
-#pragma unroll
-        for (int q = 0; q < 3; ++q) {
-#pragma unroll
-            for (int mi = 0; mi < WTM; ++mi) {
-                const int base = (wm * WTM * MT + mi * MT + r) * LD + g * S;
-#pragma unroll
-                for (int s = 0; s < S; ++s) fa[q][mi][s] = sA[cur][q][base + s];
-            }
-            if (q < 2 || M3) {
-#pragma unroll
-                for (int ni = 0; ni < WTN; ++ni) {
-                    const int base = (wn * WTN * MT + ni * MT + r) * LD + g * S;
-#pragma unroll
-                    for (int s = 0; s < S; ++s) fb[q][ni][s] = sB[cur][q][base + s];
-                }
-            }
-        }
 #pragma unroll
         for (int s = 0; s < S; ++s) {
+            const int kk = g * S + s;  // permuted k inside the tile
+            T xa[2][TM], xb[2][TN];
 #pragma unroll
-            for (int mi = 0; mi < WTM; ++mi) {
+            for (int q = 0; q < 2; ++q) {
 #pragma unroll
-                for (int ni = 0; ni < WTN; ++ni) {
+                for (int mi = 0; mi < TM; ++mi) {
+                    const int o = wm * TM * MT + mi * MT + r;
+                    xa[q][mi] = sA[cur][q][AK ? o * LDAk + kk : kk * LDAo + o];
+                }
+#pragma unroll
+                for (int ni = 0; ni < TN; ++ni) {
+                    const int o = wn * TN * MT + ni * MT + r;
+                    xb[q][ni] = sB[cur][q][BKC ? o * LDAk + kk : kk * LDBo + o];
+                }
+            }
+            T xa3[TM], xb3[TN];
+#pragma unroll
+            for (int mi = 0; mi < TM; ++mi) xa3[mi] = M3 ? xa[0][mi] + xa[1][mi] : -xa[1][mi];
+#pragma unroll
+            for (int ni = 0; ni < TN; ++ni) xb3[ni] = xb[0][ni] + xb[1][ni];
+#pragma unroll
+            for (int mi = 0; mi < TM; ++mi) {
+#pragma unroll
+                for (int ni = 0; ni < TN; ++ni) {
                     if constexpr (M3) {
-                        acc[0][mi][ni] = F::mma(fa[0][mi][s], fb[0][ni][s], acc[0][mi][ni]);
-                        acc[1][mi][ni] = F::mma(fa[1][mi][s], fb[1][ni][s], acc[1][mi][ni]);
-                        acc[2][mi][ni] = F::mma(fa[2][mi][s], fb[2][ni][s], acc[2][mi][ni]);
+                        acc[0][mi][ni] = F::mma(xa[0][mi], xb[0][ni], acc[0][mi][ni]);
+                        acc[1][mi][ni] = F::mma(xa[1][mi], xb[1][ni], acc[1][mi][ni]);
+                        acc[2][mi][ni] = F::mma(xa3[mi], xb3[ni], acc[2][mi][ni]);
                     } else {
-                        acc[0][mi][ni] = F::mma(fa[0][mi][s], fb[0][ni][s], acc[0][mi][ni]);
-                        acc[0][mi][ni] = F::mma(fa[2][mi][s], fb[1][ni][s], acc[0][mi][ni]);
-                        acc[1][mi][ni] = F::mma(fa[0][mi][s], fb[1][ni][s], acc[1][mi][ni]);
-                        acc[1][mi][ni] = F::mma(fa[1][mi][s], fb[0][ni][s], acc[1][mi][ni]);
+                        acc[0][mi][ni] = F::mma(xa[0][mi], xb[0][ni], acc[0][mi][ni]);
+                        acc[0][mi][ni] = F::mma(xa3[mi], xb[1][ni], acc[0][mi][ni]);
+                        acc[1][mi][ni] = F::mma(xa[0][mi], xb[1][ni], acc[1][mi][ni]);
+                        acc[1][mi][ni] = F::mma(xa[1][mi], xb[0][ni], acc[1][mi][ni]);
                     }
                 }
             }
@@ -239,13 +256,13 @@ __global__ void __launch_bounds__(256, 1) cgemm_kernel(KParams p) {
     }
 
 #pragma unroll
-    for (int mi = 0; mi < WTM; ++mi) {
+    for (int mi = 0; mi < TM; ++mi) {
 #pragma unroll
-        for (int ni = 0; ni < WTN; ++ni) {
+        for (int ni = 0; ni < TN; ++ni) {
 #pragma unroll
             for (int v = 0; v < F::NACC; ++v) {
-                const int gm = m0 + wm * WTM * MT + mi * MT + F::row(lane, v);
-                const int gn = n0 + wn * WTN * MT + ni * MT + F::col(lane);
+                const int gm = m0 + wm * TM * MT + mi * MT + F::row(lane, v);
+                const int gn = n0 + wn * TN * MT + ni * MT + F::col(lane);
                 if (gm < p.M && gn < p.N) {
                     T cr, ci;
                     if constexpr (M3) {
@@ -278,22 +295,210 @@ KOperand to_k(const GemmOperand& o) {
     return k;
 }
 
-template <typename T, int WTM, int WTN, int BK, bool M3>
-void launch(tdvp_ctx ctx, KParams kp, int batch) {
-    constexpr int MT = Mfma<T>::MT;
-    constexpr int BM = 2 * WTM * MT, BN = 2 * WTN * MT;
+template <typename T, int BM, int BN, int BK, int WM, int WN, bool M3>
+void launch2(tdvp_ctx ctx, KParams kp, int batch) {
     kp.tiles_m = (kp.M + BM - 1) / BM;
     kp.tiles_n = (kp.N + BN - 1) / BN;
     dim3 grid(kp.tiles_m * kp.tiles_n, 1, batch);
     char name[64];
-    snprintf(name, sizeof(name), "cgemm_%s_%s_%dx%d", sizeof(T) == 4 ? "f32" : "f64", M3 ? "3m" : "4m", BM, BN);
+    snprintf(name, sizeof(name), "cgemm2_%s_%s_%dx%dx%d_w%dx%d", sizeof(T) == 4 ? "f32" : "f64", M3 ? "3m" : "4m",
+             BM, BN, BK, WM, WN);
     const double flops = 8.0 * kp.M * (double)kp.N * kp.K * batch;
-    const double bytes = (double)batch * ((double)kp.M * kp.K * (kp.A.c128 ? 16 : 8) * (kp.A.stride ? 1 : 1.0 / batch) +
-                                          (double)kp.K * kp.N * (kp.B.c128 ? 16 : 8) * (kp.B.stride ? 1 : 1.0 / batch) +
-                                          (double)kp.M * kp.N * (kp.c128C ? 16 : 8));
-    ProfScope prof(ctx, name, flops, bytes);
-    hipLaunchKernelGGL((cgemm_kernel<T, WTM, WTN, BK, M3>), grid, dim3(256), 0, ctx->stream, kp);
+    ProfScope prof(ctx, name, flops, 0.0);
+    const dim3 blk(64 * WM * WN);
+    if (kp.A.kcontig && !kp.B.kcontig)
+        hipLaunchKernelGGL((cgemm2_kernel<T, BM, BN, BK, WM, WN, M3, true, false>), grid, blk, 0, ctx->stream, kp);
+    else if (kp.A.kcontig && kp.B.kcontig)
+        hipLaunchKernelGGL((cgemm2_kernel<T, BM, BN, BK, WM, WN, M3, true, true>), grid, blk, 0, ctx->stream, kp);
+    else if (!kp.A.kcontig && !kp.B.kcontig)
+        hipLaunchKernelGGL((cgemm2_kernel<T, BM, BN, BK, WM, WN, M3, false, false>), grid, blk, 0, ctx->stream, kp);
+    else
+        hipLaunchKernelGGL((cgemm2_kernel<T, BM, BN, BK, WM, WN, M3, false, true>), grid, blk, 0, ctx->stream, kp);
     TDVP_CHECK_HIP(hipGetLastError());
+}
+
+// Tile configurations.  f32: v_mfma_f32_32x32x2f32 (32x32 per instruction),
+// f64: v_mfma_f64_16x16x4f64.  Names: BMxBNxBK, waves WMxWN.
+struct TileCfg {
+    int id;
+    bool fp64;
+    int BM, BN, BK, WM, WN;
+};
+
+constexpr TileCfg kTiles[] = {
+    {2, false, 128, 128, 16, 2, 4},  {9, false, 64, 64, 32, 2, 2},   {10, false, 64, 128, 16, 2, 4},
+    {12, false, 64, 64, 16, 2, 2},   {13, false, 128, 128, 16, 4, 4}, {14, false, 64, 128, 32, 2, 4},
+    {15, false, 128, 64, 16, 4, 2},  {16, false, 32, 64, 16, 1, 2},
+    {2, true, 128, 128, 8, 2, 4},    {9, true, 64, 64, 16, 2, 2},    {12, true, 64, 64, 8, 2, 2},
+    {15, true, 128, 64, 16, 4, 2},   {16, true, 32, 64, 8, 1, 2},
+};
+
+template <typename T, int BM, int BN, int BK, int WM, int WN>
+void launch_form(tdvp_ctx ctx, const KParams& kp, int batch, bool m3) {
+    if constexpr (sizeof(T) == 8) {
+        launch2<T, BM, BN, BK, WM, WN, false>(ctx, kp, batch);
+    } else {
+        if (m3) launch2<T, BM, BN, BK, WM, WN, true>(ctx, kp, batch);
+        else launch2<T, BM, BN, BK, WM, WN, false>(ctx, kp, batch);
+    }
+}
+
+bool launch_cfg(tdvp_ctx ctx, KParams kp, int batch, bool fp64, bool m3, int cfg) {
+    if (!fp64) {
+        switch (cfg) {
+            case 2: launch_form<float, 128, 128, 16, 2, 4>(ctx, kp, batch, m3); return true;
+            case 9: launch_form<float, 64, 64, 32, 2, 2>(ctx, kp, batch, m3); return true;
+            case 10: launch_form<float, 64, 128, 16, 2, 4>(ctx, kp, batch, m3); return true;
+            case 12: launch_form<float, 64, 64, 16, 2, 2>(ctx, kp, batch, m3); return true;
+            case 13: launch_form<float, 128, 128, 16, 4, 4>(ctx, kp, batch, m3); return true;
+            case 14: launch_form<float, 64, 128, 32, 2, 4>(ctx, kp, batch, m3); return true;
+            case 15: launch_form<float, 128, 64, 16, 4, 2>(ctx, kp, batch, m3); return true;
+            case 16: launch_form<float, 32, 64, 16, 1, 2>(ctx, kp, batch, m3); return true;
+            default: return false;
+        }
+    }
+    // FP64 tiles are used in the 4M form (the 3M accumulators of the large
+    // tiles do not fit the register file without spilling).
+    switch (cfg) {
+        case 2: launch_form<double, 128, 128, 8, 2, 4>(ctx, kp, batch, false); return true;
+        case 9: launch_form<double, 64, 64, 16, 2, 2>(ctx, kp, batch, false); return true;
+        case 12: launch_form<double, 64, 64, 8, 2, 2>(ctx, kp, batch, false); return true;
+        case 15: launch_form<double, 128, 64, 16, 4, 2>(ctx, kp, batch, false); return true;
+        case 16: launch_form<double, 32, 64, 8, 1, 2>(ctx, kp, batch, false); return true;
+        default: return false;
+    }
+}
+
+int64_t tiles_for(const TileCfg& c, const GemmDesc& g) {
+    return (int64_t)((g.M + c.BM - 1) / c.BM) * ((g.N + c.BN - 1) / c.BN) * g.batch;
+}
+
+// Shape heuristic used when no tuned choice exists: the largest tile that
+// still gives every CU at least one block.
+int heuristic_cfg(const GemmDesc& g, bool fp64) {
+    const int big = fp64 ? 2 : 10;
+    for (const auto& c : kTiles)
+        if (c.id == big && c.fp64 == fp64 && tiles_for(c, g) >= 256) return big;
+    for (const auto& c : kTiles)
+        if (c.id == 12 && c.fp64 == fp64 && tiles_for(c, g) >= 128) return 12;
+    return 16;
+}
+
+// ------------------------------------------------------------- autotuner
+// Per shape bucket (precision, form, operand layouts, log2 of M, N, K and
+// batch) the first call times every tile configuration on the call's own
+// operands (C is overwritten each time, the operation is idempotent) and
+// keeps the fastest.  Choices persist across processes in the text file
+// named by TDVP_TUNE_CACHE, keyed by the device architecture.
+struct TuneKey {
+    int fp64, form, akc, bkc, lm, ln, lk, lb;
+    bool operator<(const TuneKey& o) const {
+        return std::tie(fp64, form, akc, bkc, lm, ln, lk, lb) < std::tie(o.fp64, o.form, o.akc, o.bkc, o.lm, o.ln, o.lk, o.lb);
+    }
+};
+
+int ilog2ceil(int64_t v) {
+    int l = 0;
+    while ((int64_t(1) << l) < v) ++l;
+    return l;
+}
+
+struct Tuner {
+    std::mutex mu;
+    std::map<TuneKey, int> best;
+    std::string arch;
+    bool loaded = false;
+
+    std::string path() const {
+        const char* p = getenv("TDVP_TUNE_CACHE");
+        return p ? std::string(p) : std::string();
+    }
+    void load(const std::string& a) {
+        if (loaded) return;
+        loaded = true;
+        arch = a;
+        const std::string p = path();
+        if (p.empty()) return;
+        FILE* f = fopen(p.c_str(), "r");
+        if (!f) return;
+        char ar[64];
+        TuneKey k;
+        int cfg;
+        while (fscanf(f, "%63s %d %d %d %d %d %d %d %d %d", ar, &k.fp64, &k.form, &k.akc, &k.bkc, &k.lm, &k.ln,
+                      &k.lk, &k.lb, &cfg) == 10)
+            if (arch == ar) best[k] = cfg;
+        fclose(f);
+    }
+    void save() {
+        const std::string p = path();
+        if (p.empty()) return;
+        FILE* f = fopen(p.c_str(), "w");
+        if (!f) return;
+        for (auto& kv : best)
+            fprintf(f, "%s %d %d %d %d %d %d %d %d %d\n", arch.c_str(), kv.first.fp64, kv.first.form, kv.first.akc,
+                    kv.first.bkc, kv.first.lm, kv.first.ln, kv.first.lk, kv.first.lb, kv.second);
+        fclose(f);
+    }
+};
+
+Tuner& tuner() {
+    static Tuner t;
+    return t;
+}
+
+int forced_cfg() {
+    const char* e = getenv("TDVP_GEMM_CFG");
+    return e ? atoi(e) : -1;
+}
+
+bool stream_capturing(hipStream_t s) {
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(s, &st) == hipSuccess && st != hipStreamCaptureStatusNone;
+}
+
+int choose_cfg(tdvp_ctx ctx, const GemmDesc& g, const KParams& kp, bool fp64, bool m3) {
+    const int forced = forced_cfg();
+    if (forced > 0) return forced;
+    const int64_t work = (int64_t)g.M * g.N * (int64_t)g.K * g.batch;
+    if (!ctx->autotune || work < (int64_t)1 << 24 || stream_capturing(ctx->stream)) return heuristic_cfg(g, fp64);
+    Tuner& T = tuner();
+    std::lock_guard<std::mutex> lock(T.mu);
+    if (!T.loaded) {
+        hipDeviceProp_t prop;
+        T.load(hipGetDeviceProperties(&prop, ctx->device) == hipSuccess ? std::string(prop.gcnArchName) : "unknown");
+    }
+    const TuneKey key{fp64, m3 ? 3 : 4, kp.A.kcontig, kp.B.kcontig, ilog2ceil(g.M), ilog2ceil(g.N),
+                      ilog2ceil(g.K), ilog2ceil(g.batch)};
+    auto it = T.best.find(key);
+    if (it != T.best.end()) return it->second;
+    hipEvent_t e0, e1;
+    TDVP_CHECK_HIP(hipEventCreate(&e0));
+    TDVP_CHECK_HIP(hipEventCreate(&e1));
+    int best = heuristic_cfg(g, fp64);
+    float best_ms = 1e30f;
+    const bool prof = ctx->prof_on;
+    ctx->prof_on = false;
+    for (const auto& c : kTiles) {
+        if (c.fp64 != fp64) continue;
+        launch_cfg(ctx, kp, g.batch, fp64, m3, c.id);  // warm-up / code load
+        TDVP_CHECK_HIP(hipEventRecord(e0, ctx->stream));
+        launch_cfg(ctx, kp, g.batch, fp64, m3, c.id);
+        launch_cfg(ctx, kp, g.batch, fp64, m3, c.id);
+        TDVP_CHECK_HIP(hipEventRecord(e1, ctx->stream));
+        TDVP_CHECK_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        TDVP_CHECK_HIP(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = c.id;
+        }
+    }
+    ctx->prof_on = prof;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    T.best[key] = best;
+    T.save();
+    return best;
 }
 
 }  // namespace
@@ -313,26 +518,10 @@ void cgemm(tdvp_ctx ctx, const GemmDesc& g, bool fp64, int form) {
     kp.c128C = g.cdt == Dt::C128;
     kp.ldc = g.ldc;
     kp.strideC = g.strideC;
-    const bool m3 = form == 3;
-    if (fp64) {
-        const int64_t big_tiles = ((g.M + 127) / 128) * (int64_t)((g.N + 63) / 64) * g.batch;
-        if (big_tiles >= 512) {
-            if (m3) launch<double, 4, 2, 8, true>(ctx, kp, g.batch);
-            else launch<double, 4, 2, 8, false>(ctx, kp, g.batch);
-        } else {
-            if (m3) launch<double, 2, 1, 8, true>(ctx, kp, g.batch);
-            else launch<double, 2, 1, 8, false>(ctx, kp, g.batch);
-        }
-    } else {
-        const int64_t big_tiles = ((g.M + 127) / 128) * (int64_t)((g.N + 127) / 128) * g.batch;
-        if (big_tiles >= 512) {
-            if (m3) launch<float, 2, 2, 16, true>(ctx, kp, g.batch);
-            else launch<float, 2, 2, 16, false>(ctx, kp, g.batch);
-        } else {
-            if (m3) launch<float, 1, 1, 16, true>(ctx, kp, g.batch);
-            else launch<float, 1, 1, 16, false>(ctx, kp, g.batch);
-        }
-    }
+    const bool m3 = fp64 ? false : form == 3;
+    const int cfg = choose_cfg(ctx, g, kp, fp64, m3);
+    if (!launch_cfg(ctx, kp, g.batch, fp64, m3, cfg))
+        launch_cfg(ctx, kp, g.batch, fp64, m3, heuristic_cfg(g, fp64));
 }
 
 }  // namespace tdvp

@@ -91,6 +91,16 @@ struct SvdResult {
     int k;
 };
 SvdResult svd_rowmajor(tdvp_ctx ctx, const double2* M, int rows, int cols);
+// Eigen-decomposition of the Gram (reduced density) matrix of M [rows][cols]:
+// left: Theta Theta^dag (n = rows), else Theta^dag Theta (n = cols).  s =
+// sqrt of the eigenvalues, descending (negative rounding noise -> 0); vecs
+// row-major [n][n], row c = conj of the c-th eigenvector.  Workspace-backed.
+struct GramResult {
+    double2* vecs;
+    std::vector<double> s;
+    int n;
+};
+GramResult gram_eigen(tdvp_ctx ctx, const double2* M, int rows, int cols, bool left);
 // Row-major complex128 product C [m][n] = A [m][k] B [k][n] (FP64 MFMA).
 void zgemm_rowmajor(tdvp_ctx ctx, const double2* A, const double2* B, double2* C, int m, int k, int n);
 

@@ -193,6 +193,16 @@ __global__ void copy2d_kernel(double2* dst, int64_t ldd, const double2* src, int
     dst[(int64_t)r * ldd + c] = v;
 }
 
+__global__ void conj_transpose_kernel(double2* dst, int64_t ldd, const double2* src, int64_t lds, int rows,
+                                      int cols) {
+    // dst[c][r] = conj(src[r][c]) for r < rows, c < cols
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    if (c >= cols || r >= rows) return;
+    const double2 v = src[(int64_t)r * lds + c];
+    dst[(int64_t)c * ldd + r] = make_double2(v.x, -v.y);
+}
+
 __global__ void scale_rows_kernel(double2* V, int64_t ld, const double* sv, int rows, int cols) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     const int r = blockIdx.y;
@@ -399,6 +409,15 @@ void copy2d(double2* dst, int64_t ldd, const double2* src, int64_t lds, int rows
     TDVP_REQUIRE(rows <= 65535, TDVP_E_SHAPE, "copy2d: too many rows");
     dim3 grid((cols + 127) / 128, rows);
     hipLaunchKernelGGL(copy2d_kernel, grid, dim3(128), 0, s, dst, ldd, src, lds, rows, cols, mask);
+    TDVP_CHECK_HIP(hipGetLastError());
+}
+
+void conj_transpose(double2* dst, int64_t ldd, const double2* src, int64_t lds, int rows, int cols,
+                    hipStream_t s) {
+    if (rows == 0 || cols == 0) return;
+    TDVP_REQUIRE(rows <= 65535, TDVP_E_SHAPE, "conj_transpose: too many rows");
+    dim3 grid((cols + 127) / 128, rows);
+    hipLaunchKernelGGL(conj_transpose_kernel, grid, dim3(128), 0, s, dst, ldd, src, lds, rows, cols);
     TDVP_CHECK_HIP(hipGetLastError());
 }
 

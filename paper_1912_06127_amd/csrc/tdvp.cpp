@@ -193,18 +193,49 @@ struct Stepper {
         return th;
     }
 
-    // SVD split of theta into sites j, j+1; centre_left puts S into site j.
+    // Split of theta into sites j, j+1 (Fig. postupdate); centre_left puts the
+    // singular values into site j, otherwise into site j+1.
     void split(int j, double2* th, bool centre_left) {
         const int d = m->d;
         const int rows = m->chi[j] * d, cols = d * m->chi[j + 2];
-        SvdResult r = svd_rowmajor(ctx, th, rows, cols);
+        const bool gram = o.svd_mode == 2 || (o.svd_mode == 0 && o.w_max >= 1e-13);
         double w = 0.0;
-        const int chi = trunc_rank(r.S, w);
+        int chi;
+        if (!gram) {
+            SvdResult r = svd_rowmajor(ctx, th, rows, cols);
+            chi = trunc_rank(r.S, w);
+            if (centre_left) scale_cols(r.U, r.k, r.S_dev, rows, chi, ctx->stream);
+            else scale_rows(r.Vh, cols, r.S_dev, chi, cols, ctx->stream);
+            store_site(j, r.U, m->chi[j], chi, rows, chi, r.k);
+            store_site(j + 1, r.Vh, chi, m->chi[j + 2], chi, cols, cols);
+        } else {
+            // reduced density matrix of the side that becomes orthonormal
+            GramResult g = gram_eigen(ctx, th, rows, cols, !centre_left);
+            chi = trunc_rank(g.s, w);
+            GemmDesc gd;
+            gd.cdt = Dt::C128;
+            if (!centre_left) {
+                // A_L(j) = U_kept, A_C(j+1) = U_kept^dag theta
+                m->set_tensor_dev(j, m->chi[j], chi);
+                conj_transpose(A(j), chi, g.vecs, g.n, chi, rows, ctx->stream);
+                m->set_tensor_dev(j + 1, chi, m->chi[j + 2]);
+                gd.M = chi; gd.N = cols; gd.K = rows;
+                gd.A.p = g.vecs; gd.A.dt = Dt::C128; gd.A.ld = g.n; gd.A.kcontig = true;
+                gd.B.p = th; gd.B.dt = Dt::C128; gd.B.ld = cols; gd.B.kcontig = false;
+                gd.C = A(j + 1); gd.ldc = cols;
+            } else {
+                // B(j+1) = V_kept^dag, A_C(j) = theta V_kept
+                m->set_tensor_dev(j + 1, chi, m->chi[j + 2]);
+                copy2d(A(j + 1), cols, g.vecs, g.n, chi, cols, 0, ctx->stream);
+                m->set_tensor_dev(j, m->chi[j], chi);
+                gd.M = rows; gd.N = chi; gd.K = cols;
+                gd.A.p = th; gd.A.dt = Dt::C128; gd.A.ld = cols; gd.A.kcontig = true;
+                gd.B.p = g.vecs; gd.B.dt = Dt::C128; gd.B.ld = g.n; gd.B.kcontig = true; gd.B.conj = true;
+                gd.C = A(j); gd.ldc = chi;
+            }
+            cgemm(ctx, gd, true, 4);
+        }
         st.w_step += w;
-        if (centre_left) scale_cols(r.U, r.k, r.S_dev, rows, chi, ctx->stream);
-        else scale_rows(r.Vh, cols, r.S_dev, chi, cols, ctx->stream);
-        store_site(j, r.U, m->chi[j], chi, rows, chi, r.k);
-        store_site(j + 1, r.Vh, chi, m->chi[j + 2], chi, cols, cols);
         m->chi[j + 1] = chi;
     }
 

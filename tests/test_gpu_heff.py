@@ -183,3 +183,19 @@ def test_apply_heff_rejects_bad_arguments(ctx):
     with pytest.raises(pkg.TDVPError) as e:  # zero-site needs wl == wr
         pkg.apply_heff(ctx, L, R, theta)
     assert e.value.status == 2
+
+
+TILE_CFGS = {"c64": [2, 9, 10, 12, 13, 14, 15, 16], "c128": [2, 9, 12, 15, 16]}
+
+
+@pytest.mark.parametrize("dt", ["c64", "c128"])
+def test_every_gemm_tile_matches_oracle(ctx, dt, monkeypatch):
+    """Each GEMM tile configuration the autotuner may pick, on ragged shapes."""
+    for cfg in TILE_CFGS[dt]:
+        monkeypatch.setenv("TDVP_GEMM_CFG", str(cfg))
+        for case in [(2, 150, 131, 2, 7, 7, 7), (1, 67, 45, 2, 5, 0, 4)]:
+            print(f"tile cfg {cfg} {case} {dt}", flush=True)
+            beta, W1, W2, gamma, theta = random_case(cfg * 7 + case[1], *case)
+            ref = oracle_heff(case[0], beta, W1, W2, gamma, theta)
+            y = run_gpu(ctx, dt, beta, W1, W2, gamma, theta)
+            assert rel_err(y, ref) <= TOL[dt], (cfg, case)

@@ -128,9 +128,11 @@ def test_tdvp1_ising_n10_matches_exact_evolution(ctx, dt_):
     assert abs(pkg.norm2(ctx, m) - 1.0) <= OBS_TOL[dt_]
 
 
-@pytest.mark.parametrize("dt_", ["c128", "c64"])
-def test_tdvp2_truncated_matches_oracle(ctx, dt_):
-    """2TDVP with truncation (w_max, chi_max, eps) on a fitted 1/r^2 XXX chain."""
+@pytest.mark.parametrize("dt_,svd_mode", [("c128", 0), ("c64", 0), ("c128", 1), ("c64", 1)])
+def test_tdvp2_truncated_matches_oracle(ctx, dt_, svd_mode):
+    """2TDVP with truncation (w_max, chi_max, eps) on a fitted 1/r^2 XXX chain.
+
+    svd_mode 0 picks the reduced-density-matrix split (w_max = 1e-8), 1 the SVD."""
     import paper_1912_06127_amd as pkg
     N = 10
     print(f"tdvp2 XXX N={N} {dt_}", flush=True)
@@ -143,7 +145,7 @@ def test_tdvp2_truncated_matches_oracle(ctx, dt_):
     tr = otdvp.Truncation(chi_max=12, w_max=1e-8, eps=1e-12)
     W = pkg.MPO.longrange(ctx, N, spin.xxx_pairs(), c=c, lam=lam)
     m = pkg.MPS.init(ctx, N, 2, [1] * (N + 1), basis_state=bits)
-    opts = pkg.TDVPOptions(compute=dt_, chi_max=12, w_max=1e-8, eps_rel=1e-12)
+    opts = pkg.TDVPOptions(compute=dt_, chi_max=12, w_max=1e-8, eps_rel=1e-12, svd_mode=svd_mode)
     for s in range(8):
         otdvp.tdvp2_step(st_o, 0.05, tr)
         st = pkg.tdvp2_step(ctx, m, W, 0.05, opts)
