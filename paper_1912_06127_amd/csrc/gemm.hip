@@ -28,6 +28,7 @@
 #include <cstdlib>
 #include <mutex>
 #include <tuple>
+#include <type_traits>
 
 namespace tdvp {
 namespace {
@@ -74,6 +75,7 @@ struct KOperand {
 struct KParams {
     int M, N, K;
     int tiles_m, tiles_n;
+    int ksplit, kchunk;  // split-K: blockIdx.z = batch * ksplit + split
     KOperand A, B;
     void* C;
     int c128C;
@@ -134,10 +136,12 @@ __global__ void __launch_bounds__(64 * WM * WN) cgemm2_kernel(KParams p) {
     if ((ntiles & 7) == 0) t = (t & 7) * (ntiles >> 3) + (t >> 3);
     const int m0 = (t % p.tiles_m) * BM;
     const int n0 = (t / p.tiles_m) * BN;
-    const int z = blockIdx.z;
+    const int z = blockIdx.z / p.ksplit;
+    const int kbeg = (blockIdx.z % p.ksplit) * p.kchunk;
+    const int kend = min(p.K, kbeg + p.kchunk);
     const int64_t zA = (int64_t)z * p.A.stride;
     const int64_t zB = (int64_t)z * p.B.stride;
-    const int64_t zC = (int64_t)z * p.strideC;
+    const int64_t zC = (int64_t)blockIdx.z * p.strideC;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -157,8 +161,8 @@ __global__ void __launch_bounds__(64 * WM * WN) cgemm2_kernel(KParams p) {
             const int k = AK ? e % BK : e / BM;
             const int gm = m0 + o, gk = k0 + k;
             const int64_t idx = AK ? (int64_t)gm * p.A.ld + gk : (int64_t)gk * p.A.ld + gm;
-            const bool v0 = gm < p.M && gk < p.K;
-            const bool v1 = AK ? (gm < p.M && gk + 1 < p.K) : (gm + 1 < p.M && gk < p.K);
+            const bool v0 = gm < p.M && gk < kend;
+            const bool v1 = AK ? (gm < p.M && gk + 1 < kend) : (gm + 1 < p.M && gk < kend);
             load_elem<T>(p.A, zA + idx, v0, ar[2 * i], ai[2 * i]);
             load_elem<T>(p.A, zA + idx + 1, v1, ar[2 * i + 1], ai[2 * i + 1]);
         }
@@ -169,8 +173,8 @@ __global__ void __launch_bounds__(64 * WM * WN) cgemm2_kernel(KParams p) {
             const int k = BKC ? e % BK : e / BN;
             const int gn = n0 + o, gk = k0 + k;
             const int64_t idx = BKC ? (int64_t)gn * p.B.ld + gk : (int64_t)gk * p.B.ld + gn;
-            const bool v0 = gn < p.N && gk < p.K;
-            const bool v1 = BKC ? (gn < p.N && gk + 1 < p.K) : (gn + 1 < p.N && gk < p.K);
+            const bool v0 = gn < p.N && gk < kend;
+            const bool v1 = BKC ? (gn < p.N && gk + 1 < kend) : (gn + 1 < p.N && gk < kend);
             load_elem<T>(p.B, zB + idx, v0, br[2 * i], bi[2 * i]);
             load_elem<T>(p.B, zB + idx + 1, v1, br[2 * i + 1], bi[2 * i + 1]);
         }
@@ -202,16 +206,16 @@ __global__ void __launch_bounds__(64 * WM * WN) cgemm2_kernel(KParams p) {
 #pragma unroll
                 for (int v = 0; v < F::NACC; ++v) acc[q][mi][ni][v] = T(0);
 
-    const int nk = (p.K + BK - 1) / BK;
+    const int nk = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
     if (nk > 0) {
-        gload(0);
+        gload(kbeg);
         lstore(0);
     }
     __syncthreads();
 
     for (int kt = 0; kt < nk; ++kt) {
         const int cur = kt & 1;
-        if (kt + 1 < nk) gload((kt + 1) * BK);
+        if (kt + 1 < nk) gload(kbeg + (kt + 1) * BK);
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             const int kk = g * S + s;  // permuted k inside the tile
@@ -284,6 +288,29 @@ __global__ void __launch_bounds__(64 * WM * WN) cgemm2_kernel(KParams p) {
     }
 }
 
+// Sum of split-K partials in a fixed order (deterministic), converted to
+// the output type: C[b][m][n] = sum_s part[b][s][m][n].
+template <typename T>
+__global__ void splitk_reduce_kernel(const void* part, int ks, int M, int N, int batch, void* C, int c128C,
+                                     int64_t ldc, int64_t strideC) {
+    using C2 = typename std::conditional<sizeof(T) == 4, float2, double2>::type;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t mn = (int64_t)M * N;
+    if (idx >= mn * batch) return;
+    const int64_t b = idx / mn, r = idx % mn;
+    const int m = (int)(r / N), n = (int)(r % N);
+    const C2* P = reinterpret_cast<const C2*>(part) + (b * ks) * mn + r;
+    T re = 0, im = 0;
+    for (int s = 0; s < ks; ++s) {
+        const C2 v = P[s * mn];
+        re += v.x;
+        im += v.y;
+    }
+    const int64_t o = b * strideC + (int64_t)m * ldc + n;
+    if (c128C) reinterpret_cast<double2*>(C)[o] = make_double2((double)re, (double)im);
+    else reinterpret_cast<float2*>(C)[o] = make_float2((float)re, (float)im);
+}
+
 KOperand to_k(const GemmOperand& o) {
     KOperand k;
     k.p = o.p;
@@ -299,10 +326,10 @@ template <typename T, int BM, int BN, int BK, int WM, int WN, bool M3>
 void launch2(tdvp_ctx ctx, KParams kp, int batch) {
     kp.tiles_m = (kp.M + BM - 1) / BM;
     kp.tiles_n = (kp.N + BN - 1) / BN;
-    dim3 grid(kp.tiles_m * kp.tiles_n, 1, batch);
+    dim3 grid(kp.tiles_m * kp.tiles_n, 1, batch * kp.ksplit);
     char name[64];
-    snprintf(name, sizeof(name), "cgemm2_%s_%s_%dx%dx%d_w%dx%d", sizeof(T) == 4 ? "f32" : "f64", M3 ? "3m" : "4m",
-             BM, BN, BK, WM, WN);
+    snprintf(name, sizeof(name), "cgemm2_%s_%s_%dx%dx%d_w%dx%d%s", sizeof(T) == 4 ? "f32" : "f64", M3 ? "3m" : "4m",
+             BM, BN, BK, WM, WN, kp.ksplit > 1 ? "_splitk" : "");
     const double flops = 8.0 * kp.M * (double)kp.N * kp.K * batch;
     ProfScope prof(ctx, name, flops, 0.0);
     const dim3 blk(64 * WM * WN);
@@ -343,7 +370,7 @@ void launch_form(tdvp_ctx ctx, const KParams& kp, int batch, bool m3) {
     }
 }
 
-bool launch_cfg(tdvp_ctx ctx, KParams kp, int batch, bool fp64, bool m3, int cfg) {
+bool launch_tile(tdvp_ctx ctx, const KParams& kp, int batch, bool fp64, bool m3, int cfg) {
     if (!fp64) {
         switch (cfg) {
             case 2: launch_form<float, 128, 128, 16, 2, 4>(ctx, kp, batch, m3); return true;
@@ -369,19 +396,72 @@ bool launch_cfg(tdvp_ctx ctx, KParams kp, int batch, bool fp64, bool m3, int cfg
     }
 }
 
+const TileCfg* find_tile(int cfg, bool fp64) {
+    for (const auto& c : kTiles)
+        if (c.id == cfg && c.fp64 == fp64) return &c;
+    return nullptr;
+}
+
+// Launch tile `cfg` with the K range split `ks` ways: partial products go to
+// a workspace in the compute precision and are summed by a second kernel.
+bool launch_cfg(tdvp_ctx ctx, KParams kp, int batch, bool fp64, bool m3, int cfg, int ks) {
+    const TileCfg* t = find_tile(cfg, fp64);
+    if (!t) return false;
+    if (ks <= 1) {
+        kp.ksplit = 1;
+        kp.kchunk = kp.K;
+        return launch_tile(ctx, kp, batch, fp64, m3, cfg);
+    }
+    const int chunk = ((kp.K + ks - 1) / ks + t->BK - 1) / t->BK * t->BK;
+    ks = (kp.K + chunk - 1) / chunk;
+    const int64_t mn = (int64_t)kp.M * kp.N;
+    const size_t esz = fp64 ? sizeof(double2) : sizeof(float2);
+    void* part = ctx->workspace("gemm_splitk", esz * (size_t)mn * ks * batch);
+    KParams q = kp;
+    q.ksplit = ks;
+    q.kchunk = chunk;
+    q.C = part;
+    q.c128C = fp64;
+    q.ldc = kp.N;
+    q.strideC = mn;
+    launch_tile(ctx, q, batch, fp64, m3, cfg);
+    const int64_t tot = mn * batch;
+    const unsigned blocks = (unsigned)((tot + 255) / 256);
+    if (fp64)
+        hipLaunchKernelGGL(splitk_reduce_kernel<double>, dim3(blocks), dim3(256), 0, ctx->stream, part, ks, kp.M,
+                           kp.N, batch, kp.C, kp.c128C, kp.ldc, kp.strideC);
+    else
+        hipLaunchKernelGGL(splitk_reduce_kernel<float>, dim3(blocks), dim3(256), 0, ctx->stream, part, ks, kp.M,
+                           kp.N, batch, kp.C, kp.c128C, kp.ldc, kp.strideC);
+    TDVP_CHECK_HIP(hipGetLastError());
+    return true;
+}
+
 int64_t tiles_for(const TileCfg& c, const GemmDesc& g) {
     return (int64_t)((g.M + c.BM - 1) / c.BM) * ((g.N + c.BN - 1) / c.BN) * g.batch;
 }
 
+struct Choice {
+    int cfg, ks;
+};
+
+// K split that gives at least two blocks per CU while every split keeps at
+// least eight k-tiles.
+int default_split(const TileCfg& c, const GemmDesc& g) {
+    int ks = 1;
+    const int64_t tiles = tiles_for(c, g);
+    while (tiles * ks < 512 && g.K / (2 * ks) >= 8 * c.BK && ks < 16) ks *= 2;
+    return ks;
+}
+
 // Shape heuristic used when no tuned choice exists: the largest tile that
-// still gives every CU at least one block.
-int heuristic_cfg(const GemmDesc& g, bool fp64) {
+// still gives every CU at least one block, else a small tile with split-K.
+Choice heuristic_cfg(const GemmDesc& g, bool fp64) {
     const int big = fp64 ? 2 : 10;
-    for (const auto& c : kTiles)
-        if (c.id == big && c.fp64 == fp64 && tiles_for(c, g) >= 256) return big;
-    for (const auto& c : kTiles)
-        if (c.id == 12 && c.fp64 == fp64 && tiles_for(c, g) >= 128) return 12;
-    return 16;
+    const TileCfg* b = find_tile(big, fp64);
+    if (tiles_for(*b, g) >= 256) return {big, 1};
+    const TileCfg* s = find_tile(12, fp64);
+    return {12, default_split(*s, g)};
 }
 
 // ------------------------------------------------------------- autotuner
@@ -405,7 +485,7 @@ int ilog2ceil(int64_t v) {
 
 struct Tuner {
     std::mutex mu;
-    std::map<TuneKey, int> best;
+    std::map<TuneKey, Choice> best;
     std::string arch;
     bool loaded = false;
 
@@ -423,10 +503,10 @@ struct Tuner {
         if (!f) return;
         char ar[64];
         TuneKey k;
-        int cfg;
-        while (fscanf(f, "%63s %d %d %d %d %d %d %d %d %d", ar, &k.fp64, &k.form, &k.akc, &k.bkc, &k.lm, &k.ln,
-                      &k.lk, &k.lb, &cfg) == 10)
-            if (arch == ar) best[k] = cfg;
+        Choice c;
+        while (fscanf(f, "%63s %d %d %d %d %d %d %d %d %d %d", ar, &k.fp64, &k.form, &k.akc, &k.bkc, &k.lm, &k.ln,
+                      &k.lk, &k.lb, &c.cfg, &c.ks) == 11)
+            if (arch == ar) best[k] = c;
         fclose(f);
     }
     void save() {
@@ -435,8 +515,8 @@ struct Tuner {
         FILE* f = fopen(p.c_str(), "w");
         if (!f) return;
         for (auto& kv : best)
-            fprintf(f, "%s %d %d %d %d %d %d %d %d %d\n", arch.c_str(), kv.first.fp64, kv.first.form, kv.first.akc,
-                    kv.first.bkc, kv.first.lm, kv.first.ln, kv.first.lk, kv.first.lb, kv.second);
+            fprintf(f, "%s %d %d %d %d %d %d %d %d %d %d\n", arch.c_str(), kv.first.fp64, kv.first.form, kv.first.akc,
+                    kv.first.bkc, kv.first.lm, kv.first.ln, kv.first.lk, kv.first.lb, kv.second.cfg, kv.second.ks);
         fclose(f);
     }
 };
@@ -456,9 +536,12 @@ bool stream_capturing(hipStream_t s) {
     return hipStreamIsCapturing(s, &st) == hipSuccess && st != hipStreamCaptureStatusNone;
 }
 
-int choose_cfg(tdvp_ctx ctx, const GemmDesc& g, const KParams& kp, bool fp64, bool m3) {
+Choice choose_cfg(tdvp_ctx ctx, const GemmDesc& g, const KParams& kp, bool fp64, bool m3) {
     const int forced = forced_cfg();
-    if (forced > 0) return forced;
+    if (forced > 0 && find_tile(forced, fp64)) {
+        const char* e = getenv("TDVP_GEMM_KSPLIT");
+        return {forced, e ? std::max(1, atoi(e)) : 1};
+    }
     const int64_t work = (int64_t)g.M * g.N * (int64_t)g.K * g.batch;
     if (!ctx->autotune || work < (int64_t)1 << 24 || stream_capturing(ctx->stream)) return heuristic_cfg(g, fp64);
     Tuner& T = tuner();
@@ -474,23 +557,26 @@ int choose_cfg(tdvp_ctx ctx, const GemmDesc& g, const KParams& kp, bool fp64, bo
     hipEvent_t e0, e1;
     TDVP_CHECK_HIP(hipEventCreate(&e0));
     TDVP_CHECK_HIP(hipEventCreate(&e1));
-    int best = heuristic_cfg(g, fp64);
+    Choice best = heuristic_cfg(g, fp64);
     float best_ms = 1e30f;
     const bool prof = ctx->prof_on;
     ctx->prof_on = false;
     for (const auto& c : kTiles) {
         if (c.fp64 != fp64) continue;
-        launch_cfg(ctx, kp, g.batch, fp64, m3, c.id);  // warm-up / code load
-        TDVP_CHECK_HIP(hipEventRecord(e0, ctx->stream));
-        launch_cfg(ctx, kp, g.batch, fp64, m3, c.id);
-        launch_cfg(ctx, kp, g.batch, fp64, m3, c.id);
-        TDVP_CHECK_HIP(hipEventRecord(e1, ctx->stream));
-        TDVP_CHECK_HIP(hipEventSynchronize(e1));
-        float ms = 0.f;
-        TDVP_CHECK_HIP(hipEventElapsedTime(&ms, e0, e1));
-        if (ms < best_ms) {
-            best_ms = ms;
-            best = c.id;
+        for (int ks = 1; ks <= 16; ks *= 2) {
+            if (ks > 1 && (g.K / ks < 4 * c.BK || tiles_for(c, g) * ks > 4096)) break;
+            launch_cfg(ctx, kp, g.batch, fp64, m3, c.id, ks);  // warm-up / code load
+            TDVP_CHECK_HIP(hipEventRecord(e0, ctx->stream));
+            launch_cfg(ctx, kp, g.batch, fp64, m3, c.id, ks);
+            launch_cfg(ctx, kp, g.batch, fp64, m3, c.id, ks);
+            TDVP_CHECK_HIP(hipEventRecord(e1, ctx->stream));
+            TDVP_CHECK_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            TDVP_CHECK_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = {c.id, ks};
+            }
         }
     }
     ctx->prof_on = prof;
@@ -519,9 +605,11 @@ void cgemm(tdvp_ctx ctx, const GemmDesc& g, bool fp64, int form) {
     kp.ldc = g.ldc;
     kp.strideC = g.strideC;
     const bool m3 = fp64 ? false : form == 3;
-    const int cfg = choose_cfg(ctx, g, kp, fp64, m3);
-    if (!launch_cfg(ctx, kp, g.batch, fp64, m3, cfg))
-        launch_cfg(ctx, kp, g.batch, fp64, m3, heuristic_cfg(g, fp64));
+    const Choice ch = choose_cfg(ctx, g, kp, fp64, m3);
+    if (!launch_cfg(ctx, kp, g.batch, fp64, m3, ch.cfg, ch.ks)) {
+        const Choice h = heuristic_cfg(g, fp64);
+        launch_cfg(ctx, kp, g.batch, fp64, m3, h.cfg, h.ks);
+    }
 }
 
 }  // namespace tdvp

@@ -190,11 +190,14 @@ TILE_CFGS = {"c64": [2, 9, 10, 12, 13, 14, 15, 16], "c128": [2, 9, 12, 15, 16]}
 
 @pytest.mark.parametrize("dt", ["c64", "c128"])
 def test_every_gemm_tile_matches_oracle(ctx, dt, monkeypatch):
-    """Each GEMM tile configuration the autotuner may pick, on ragged shapes."""
+    """Each GEMM tile configuration the autotuner may pick, on ragged shapes,
+    without and with the K range split over blocks."""
     for cfg in TILE_CFGS[dt]:
         monkeypatch.setenv("TDVP_GEMM_CFG", str(cfg))
-        for case in [(2, 150, 131, 2, 7, 7, 7), (1, 67, 45, 2, 5, 0, 4)]:
-            print(f"tile cfg {cfg} {case} {dt}", flush=True)
+        for ks, case in [(1, (2, 150, 131, 2, 7, 7, 7)), (3, (2, 150, 131, 2, 7, 7, 7)),
+                         (1, (1, 67, 45, 2, 5, 0, 4)), (2, (1, 67, 45, 2, 5, 0, 4))]:
+            monkeypatch.setenv("TDVP_GEMM_KSPLIT", str(ks))
+            print(f"tile cfg {cfg} split-K {ks} {case} {dt}", flush=True)
             beta, W1, W2, gamma, theta = random_case(cfg * 7 + case[1], *case)
             ref = oracle_heff(case[0], beta, W1, W2, gamma, theta)
             y = run_gpu(ctx, dt, beta, W1, W2, gamma, theta)
