@@ -93,10 +93,14 @@ def mpo_exponentials(N: int, c, lam, pairs, onsite=None, h: float = 0.0):
 def fit_exponentials(fvals: np.ndarray, K: int):
     """Matrix-pencil fit f(r) ~ sum_k c_k lam_k^r from samples f(1..R).
 
-    Returns (c, lam, max_abs_err) with complex c, lam.
+    Returns (c, lam, max_abs_err) with complex c, lam.  The shift matrix of
+    K exponentials is determined only by at least 2K samples; fewer are
+    rejected (the pencil would be rank deficient and the fit meaningless).
     """
     f = np.asarray(fvals, dtype=np.float64)
     R = len(f)
+    if K < 1 or R < 2 * K:
+        raise ValueError("need K >= 1 and at least 2K samples")
     P = R // 2
     Y = np.array([[f[i + j] for j in range(P + 1)] for i in range(R - P)])
     _, _, Vh = np.linalg.svd(Y)

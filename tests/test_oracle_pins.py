@@ -63,6 +63,15 @@ def test_fit_recovers_exact_exponentials():
     assert err < 1e-12
 
 
+def test_fit_rejects_underdetermined_pencil():
+    # K exponentials have 2K unknowns: fewer samples leave the shift matrix
+    # rank deficient, so the fit must refuse instead of returning garbage.
+    with pytest.raises(ValueError):
+        mpo.fit_exponentials(1.0 / np.arange(1, 6) ** 2.0, 3)
+    c, lam, err = mpo.fit_exponentials(0.5 ** np.arange(1, 7), 3)
+    assert err < 1e-12
+
+
 def test_fit_power_law_error_scale():
     # 1/r^2 with 12 exponentials on r <= 200: the paper reports an absolute
     # error of 1.5e-7 with its fit (Supplemental Material, XXX model).  A
