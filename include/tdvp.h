@@ -219,6 +219,22 @@ int apply_heff(tdvp_ctx ctx, int nsite, tdvp_dtype dtype, int chil, int chir, in
                int wl, int wm, int wr, const void* L, const void* W1, const void* W2,
                const void* R, const void* theta, void* out);
 
+/* Adjoint of apply_heff for reverse-mode differentiation (gradients in the
+ * convention g = dl/dRe z + i dl/dIm z for a real loss l, i.e. the
+ * convention of torch's complex autograd).  Given the gradient ybar of the
+ * output, computes (each output optional, NULL = skip):
+ *   theta_bar = H_eff^dagger ybar                       [chil][D][chir]
+ *   L_bar[k][a'][a] = sum ybar[a' s' b'] conj(W R theta)  [wl][chil][chil]
+ *   R_bar[n][b][b'] = sum conj(L W theta) ybar           [wr][chir][chir]
+ *   W1_bar[k][l][s'][s]  (nsite = 1 only)               [wl][wr][d][d]
+ * W2_bar must be NULL (MPO gradients are provided for the one-site form used
+ * by one-site TDVP).  Same shapes, layouts, dtype and stream semantics as
+ * apply_heff; outputs must not alias inputs. */
+int apply_heff_adjoint(tdvp_ctx ctx, int nsite, tdvp_dtype dtype, int chil, int chir, int d,
+                       int wl, int wm, int wr, const void* L, const void* W1, const void* W2,
+                       const void* R, const void* theta, const void* ybar, void* theta_bar,
+                       void* L_bar, void* W1_bar, void* W2_bar, void* R_bar);
+
 /* Environment update (Sec. III A, left-environment figure):
  *   dir = +1: out[l][b'][b] = sum conj(A[a'][s'][b']) env[k][a'][a] W[k][l][s'][s] A[a][s][b]
  *             (env = L_j [wl][chil][chil], out = L_{j+1} [wr][chir][chir])

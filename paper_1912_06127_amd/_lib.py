@@ -75,6 +75,7 @@ SIGNATURES = {
     "tdvp2_step": (_I, [_P, _P, _P, _D, C.POINTER(Opts), C.POINTER(Stats)]),
     "apply_heff": (_I, [_P, _I, _I, _I, _I, _I, _I, _I, _I, _P, _P, _P, _P, _P, _P]),
     "env_update": (_I, [_P, _I, _I, _I, _I, _I, _I, _I, _P, _P, _P, _P]),
+    "apply_heff_adjoint": (_I, [_P, _I, _I, _I, _I, _I, _I, _I, _I] + [_P] * 11),
     "expect": (_I, [_P, _P, _I, _PI, _PD, _PD]),
     "expect2": (_I, [_P, _P, _I, _PI, _PI, _PD, _PD, _PD]),
     "energy": (_I, [_P, _P, _P, _PD]),

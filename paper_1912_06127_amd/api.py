@@ -179,6 +179,35 @@ def apply_heff(ctx: Context, L, R, theta, W1=None, W2=None, out=None) -> torch.T
     return out
 
 
+def apply_heff_adjoint(ctx: Context, L, R, theta, ybar, W1=None, W2=None, need=("theta", "L", "R", "W")):
+    """Gradients of Re<ybar, H_eff theta> w.r.t. theta, L, R and (one-site) W.
+
+    Returns a dict with the requested entries ("theta", "L", "R", "W").
+    """
+    nsite = theta.dim() - 2
+    dt = theta.dtype
+    wl, chil = L.shape[0], L.shape[1]
+    wr, chir = R.shape[0], R.shape[1]
+    d = theta.shape[1] if nsite >= 1 else 1
+    wm = W1.shape[1] if nsite == 2 else wl
+    out = {}
+    if "theta" in need:
+        out["theta"] = torch.empty_like(theta)
+    if "L" in need:
+        out["L"] = torch.empty_like(L)
+    if "R" in need:
+        out["R"] = torch.empty_like(R)
+    if "W" in need and nsite == 1:
+        out["W"] = torch.empty_like(W1)
+    ptr = lambda t: _dev(t, dt) if t is not None else C.c_void_p()
+    rc = _lib.load().apply_heff_adjoint(
+        ctx.handle, nsite, _dtype_code(theta), chil, chir, d, wl, wm, wr, ptr(L), ptr(W1), ptr(W2), ptr(R),
+        ptr(theta), ptr(ybar), ptr(out.get("theta")), ptr(out.get("L")), ptr(out.get("W")), C.c_void_p(),
+        ptr(out.get("R")))
+    _check(ctx.handle, rc)
+    return out
+
+
 def env_update(ctx: Context, direction: int, env, A, W, out=None) -> torch.Tensor:
     """Left (direction=+1) or right (-1) environment update with site tensor A [chil][d][chir]."""
     dt = A.dtype

@@ -1,0 +1,245 @@
+"""Reverse-mode differentiation of one-site TDVP (Sec. II D, Eq. proj1site).
+
+Every effective-Hamiltonian application runs through ``ApplyHeff``, a
+``torch.autograd.Function`` whose forward is the library's ``apply_heff``
+kernel and whose backward is the hand-written ``apply_heff_adjoint`` kernel
+(gradients with respect to the state, both environments and the MPO tensor).
+The rest of the differentiable step (Lanczos recursion, the small Krylov
+exponential, QR/LQ gauge moves, environment updates) is composed of torch
+operations on device tensors, so autograd chains them.  Environments are not
+stored across time steps: ``checkpoint_every`` steps form one
+``torch.utils.checkpoint`` block that is recomputed during the backward pass.
+
+Layouts follow the library: site tensors A[a][s][b], MPO W[k][l][s'][s],
+environments L[k][a'][a] and R[l][b][b'].
+"""
+from __future__ import annotations
+
+import torch
+from torch.utils.checkpoint import checkpoint
+
+from . import api
+
+
+class ApplyHeff(torch.autograd.Function):
+    """y = H_eff x for a zero-site (W None) or one-site local state.
+
+    ``compute`` is the dtype the kernel runs in (complex64: FP32 MFMA; the
+    state may be complex128 and is cast on the way in and out).
+    """
+
+    @staticmethod
+    def forward(ctx_, lib_ctx, compute, x, L, W, R):
+        cx = x.to(compute).contiguous()
+        cL = L.to(compute).contiguous()
+        cR = R.to(compute).contiguous()
+        cW = None if W is None else W.to(compute).contiguous()
+        y = api.apply_heff(lib_ctx, cL, cR, cx, cW)
+        ctx_.save_for_backward(cx, cL, cW if cW is not None else torch.empty(0, device=x.device), cR)
+        ctx_.lib_ctx = lib_ctx
+        ctx_.has_w = W is not None
+        ctx_.dtypes = (x.dtype, L.dtype, None if W is None else W.dtype, R.dtype)
+        return y.to(x.dtype)
+
+    @staticmethod
+    def backward(ctx_, ybar):
+        cx, cL, cW, cR = ctx_.saved_tensors
+        W = cW if ctx_.has_w else None
+        need = []
+        if ctx_.needs_input_grad[2]:
+            need.append("theta")
+        if ctx_.needs_input_grad[3]:
+            need.append("L")
+        if ctx_.has_w and ctx_.needs_input_grad[4]:
+            need.append("W")
+        if ctx_.needs_input_grad[5]:
+            need.append("R")
+        g = api.apply_heff_adjoint(ctx_.lib_ctx, cL, cR, cx, ybar.to(cx.dtype).contiguous(), W, need=need)
+        xd, Ld, Wd, Rd = ctx_.dtypes
+        conv = lambda k, dt: g[k].to(dt) if k in g else None
+        return (None, None, conv("theta", xd), conv("L", Ld), conv("W", Wd) if Wd is not None else None,
+                conv("R", Rd))
+
+
+def env_left(L, A, W):
+    """L'[l][b'][b] = sum conj(A[a' s' b']) L[k][a'][a] W[k][l][s'][s] A[a s b]."""
+    return torch.einsum("kpa,ptb,klts,asc->lbc", L, A.conj(), W, A)
+
+
+def env_right(R, A, W):
+    """R'[k][a][a'] = sum A[a s b] W[k][l][s'][s] R[l][b][b'] conj(A[a' s' b'])."""
+    return torch.einsum("asb,klts,lbc,ptc->kap", A, W, R, A.conj())
+
+
+def expm_lanczos(op, x, tau, kmax=40, tol=1e-13, extra=5):
+    """exp(-i tau H) x by Lanczos with two Gram-Schmidt passes (differentiable).
+
+    The derivative of a Krylov approximation converges one order later than
+    its value, so ``extra`` iterations run past the convergence point (unless
+    the space is exhausted) to keep gradients as accurate as the forward."""
+    shape = x.shape
+    v = x.reshape(-1)
+    beta0 = torch.linalg.vector_norm(v)
+    V = [v / beta0]
+    alphas, betas = [], []
+    y = None
+    stop_at = kmax
+    for k in range(kmax):
+        w = op(V[k].reshape(shape)).reshape(-1)
+        a = torch.vdot(V[k], w).real
+        w = w - a * V[k]
+        if k > 0:
+            w = w - betas[-1] * V[k - 1]
+        Vm = torch.stack(V)
+        for _ in range(2):
+            w = w - Vm.T @ (Vm.conj() @ w)
+        b = torch.linalg.vector_norm(w)
+        alphas.append(a)
+        n = len(alphas)
+        T = torch.diag(torch.stack(alphas))
+        if n > 1:
+            off = torch.stack(betas)
+            T = T + torch.diag(off, 1) + torch.diag(off, -1)
+        E = torch.linalg.matrix_exp((-1j * tau) * T.to(x.dtype))
+        y = E[:, 0]
+        with torch.no_grad():
+            scale = max(max(abs(float(t)) for t in alphas), max((float(t) for t in betas), default=0.0))
+            exhausted = float(b) <= 1e-14 * scale or scale == 0.0 or len(alphas) >= v.numel()
+            if float(b) * float(abs(y[-1])) <= tol and stop_at == kmax:
+                stop_at = min(kmax, k + 1 + extra)
+        if exhausted or k + 1 >= stop_at:
+            break
+        betas.append(b)
+        V.append(w / b)
+    out = beta0 * (torch.stack(V[: len(alphas)]).T @ y)
+    return out.reshape(shape)
+
+
+def _lq(M):
+    """M = L Q with orthonormal rows of Q (through the QR of M^dagger)."""
+    Q, R = torch.linalg.qr(M.conj().T)
+    return R.conj().T, Q.conj().T
+
+
+def right_envs(T, Ws):
+    N = len(T)
+    one = torch.ones((1, 1, 1), dtype=T[0].dtype, device=T[0].device)
+    R = [None] * N
+    R[N - 1] = one
+    for j in range(N - 1, 0, -1):
+        R[j - 1] = env_right(R[j], T[j], Ws[j])
+    return R
+
+
+def tdvp1_step(lib_ctx, T, Ws, dt, compute=torch.complex128, kmax=40, tol=1e-13):
+    """One symmetric one-site TDVP step on torch tensors (returns new tensors).
+
+    T: right-canonical site tensors with the centre on site 1; Ws: MPO site
+    tensors.  Differentiable with respect to T and Ws.
+    """
+    T = list(T)
+    N = len(T)
+    tau = dt / 2.0
+    one = torch.ones((1, 1, 1), dtype=T[0].dtype, device=T[0].device)
+    L = [None] * N
+    L[0] = one
+    R = right_envs(T, Ws)
+    h1 = lambda j: (lambda x: ApplyHeff.apply(lib_ctx, compute, x, L[j], Ws[j], R[j]))
+    h0 = lambda j: (lambda x: ApplyHeff.apply(lib_ctx, compute, x, L[j + 1], None, R[j]))
+    for j in range(N - 1):
+        T[j] = expm_lanczos(h1(j), T[j], tau, kmax, tol)
+        chil, d, chir = T[j].shape
+        Q, C = torch.linalg.qr(T[j].reshape(chil * d, chir))
+        T[j] = Q.reshape(chil, d, chir)
+        L[j + 1] = env_left(L[j], T[j], Ws[j])
+        C = expm_lanczos(h0(j), C, -tau, kmax, tol)
+        T[j + 1] = torch.einsum("ab,bsc->asc", C, T[j + 1])
+    T[N - 1] = expm_lanczos(h1(N - 1), T[N - 1], dt, kmax, tol)
+    for j in range(N - 1, 0, -1):
+        chil, d, chir = T[j].shape
+        Lf, Q = _lq(T[j].reshape(chil, d * chir))
+        T[j] = Q.reshape(chil, d, chir)
+        R[j - 1] = env_right(R[j], T[j], Ws[j])
+        Lf = expm_lanczos(h0(j - 1), Lf, -tau, kmax, tol)
+        T[j - 1] = torch.einsum("asb,bc->asc", T[j - 1], Lf)
+        T[j - 1] = expm_lanczos(h1(j - 1), T[j - 1], tau, kmax, tol)
+    return T
+
+
+def expect_site(T, site, O):
+    """<psi|O_site|psi>/<psi|psi> (differentiable transfer contraction, 0-based site)."""
+    E = torch.ones((1, 1), dtype=T[0].dtype, device=T[0].device)
+    num = None
+    for j, A in enumerate(T):
+        if j == site:
+            num = torch.einsum("xy,xtb,ts,ysc->bc", E, A.conj(), O, A)
+        elif num is not None:
+            num = torch.einsum("xy,xsb,ysc->bc", num, A.conj(), A)
+        E = torch.einsum("xy,xsb,ysc->bc", E, A.conj(), A)
+    return (num[0, 0] / E[0, 0]).real
+
+
+def evolve(lib_ctx, T, Ws, dt, steps, compute=torch.complex128, checkpoint_every=5, kmax=40, tol=1e-13):
+    """`steps` 1TDVP steps; each block of `checkpoint_every` steps is recomputed in backward."""
+    T = list(T)
+    done = 0
+    while done < steps:
+        nblk = min(checkpoint_every, steps - done) if checkpoint_every > 0 else steps - done
+
+        def block(*args, nblk=nblk):
+            ts = list(args[: len(T)])
+            ws = list(args[len(T):])
+            for _ in range(nblk):
+                ts = tdvp1_step(lib_ctx, ts, ws, dt, compute, kmax, tol)
+            return tuple(ts)
+
+        if checkpoint_every and torch.is_grad_enabled():
+            T = list(checkpoint(block, *T, *Ws, use_reentrant=False))
+        else:
+            T = list(block(*T, *Ws))
+        done += nblk
+    return T
+
+
+def mpo_sum_of_exponentials(N, c, lam, pairs, onsite, J, h, dtype=torch.complex128, device="cuda"):
+    """MPO site tensors of J sum_{i<j} f(j-i) sum_a g_a A_a B_a + h sum X as torch
+    functions of the real parameters J and h (Sec. II C, sums of exponentials).
+
+    Returns (Ws, bulk): ``bulk`` is the bulk tensor W[k][l][s'][s]; site j uses
+    row 0 (first site), column m-1 (last site) or all of it.
+    """
+    c = torch.as_tensor(c, dtype=torch.complex128, device=device)
+    lam = torch.as_tensor(lam, dtype=torch.complex128, device=device)
+    K = len(c)
+    m = len(pairs) * K + 2
+    d = onsite.shape[0]
+    eye = torch.eye(d, dtype=torch.complex128, device=device)
+    base = torch.zeros((m, m, d, d), dtype=torch.complex128, device=device)
+    WJ = torch.zeros_like(base)
+    Wh = torch.zeros_like(base)
+    base[0, 0] = eye
+    base[m - 1, m - 1] = eye
+    Wh[0, m - 1] = torch.as_tensor(onsite, dtype=torch.complex128, device=device)
+    for a, (g, A, B) in enumerate(pairs):
+        A = torch.as_tensor(A, dtype=torch.complex128, device=device)
+        B = torch.as_tensor(B, dtype=torch.complex128, device=device)
+        for k in range(K):
+            s = 1 + a * K + k
+            base[0, s] = A
+            base[s, s] = lam[k] * eye
+            WJ[s, m - 1] = g * c[k] * lam[k] * B
+    bulk = (base + J.to(torch.complex128) * WJ + h.to(torch.complex128) * Wh).to(dtype)
+    return sites_from_bulk(bulk, N), bulk
+
+
+def sites_from_bulk(bulk, N):
+    m = bulk.shape[0]
+    Ws = []
+    for j in range(N):
+        if j == 0:
+            Ws.append(bulk[0:1])
+        elif j == N - 1:
+            Ws.append(bulk[:, m - 1:m])
+        else:
+            Ws.append(bulk)
+    return Ws

@@ -204,10 +204,19 @@ void nan_check(const double2* x, int64_t n, int* flag, hipStream_t s);
 namespace tdvp {
 // MPO-stage operator kinds (rows <- cols):
 //   0 zero-site identity (w x w), 1 one-site / left environment (l,s')<-(k,s),
-//   2 two-site (n,s1's2')<-(k,s1s2), 3 right environment (k,s')<-(l,s).
+//   2 two-site (n,s1's2')<-(k,s1s2), 3 right environment (k,s')<-(l,s),
+//   4 kind 1 with the physical adjoint conj(W[k][l][s][s']), 5 kind 2 with
+//   both factors physically adjoint, 6 two-site right orientation
+//   (k,s1's2')<-(n,s1s2).
 void mop_build(int kind, const void* W1, Dt w1dt, const void* W2, Dt w2dt, int wl, int wm, int wr,
                int d, int rows, int cols, double2* dense, int* row_ptr, int* col, void* val,
                bool val_fp64, hipStream_t s);
+// out[z] = in[z]^dagger for `batch` n x n blocks of dtype dt.
+void conj_transpose_batched(void* out, const void* in, Dt dt, int n, int batch, hipStream_t s);
+// out[k][l][s'][s] = sum_{a',b} conj(T1[k][a'][s][b]) Z[l][a'][s'][b] (T1 [wl][chil][d][chir],
+// Z [wr][chil][d][chir], out [wl][wr][d][d], all of dtype dt).
+void wgrad(const void* T1, const void* Z, Dt dt, int wl, int wr, int d, int chil, int chir, void* out,
+           hipStream_t s);
 // out[0] = sum_{i,j} X[i][j] Y[j][i] for n x n complex128 matrices.
 void trace_xyT(tdvp_ctx ctx, const double2* X, const double2* Y, int n, double2* out);
 }  // namespace tdvp

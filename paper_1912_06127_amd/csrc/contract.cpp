@@ -31,9 +31,10 @@ void mop_make(tdvp_ctx ctx, Mop& m, int kind, const void* W1, const void* W2, Dt
     int rows, cols;
     switch (kind) {
         case 0: rows = wl; cols = wl; break;
-        case 1: rows = wr * d; cols = wl * d; break;
-        case 2: rows = wr * d * d; cols = wl * d * d; break;
+        case 1: case 4: rows = wr * d; cols = wl * d; break;
+        case 2: case 5: rows = wr * d * d; cols = wl * d * d; break;
         case 3: rows = wl * d; cols = wr * d; break;
+        case 6: rows = wl * d * d; cols = wr * d * d; break;
         default: throw Error(TDVP_E_ARG, "mop_make: bad kind");
     }
     const size_t nz = (size_t)rows * cols;

@@ -203,6 +203,50 @@ __global__ void conj_transpose_kernel(double2* dst, int64_t ldd, const double2* 
     dst[(int64_t)c * ldd + r] = make_double2(v.x, -v.y);
 }
 
+// out[z][j][i] = conj(in[z][i][j]) for n x n blocks, any complex dtype
+__global__ void conj_transpose_batched_kernel(void* out, const void* in, int c128, int n) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.y;
+    const int64_t z = blockIdx.z;
+    if (j >= n) return;
+    const int64_t base = z * (int64_t)n * n;
+    double re, im;
+    ld<double>(in, c128, base + (int64_t)i * n + j, re, im);
+    st<double>(out, c128, base + (int64_t)j * n + i, re, -im);
+}
+
+// MPO-tensor gradient of the one-site effective Hamiltonian:
+// out[k][l][s'][s] = sum_{a', b} conj(T1[k][a'][s][b]) Z[l][a'][s'][b],
+// one block per output entry, fixed-order reduction.
+template <typename T>
+__global__ void wgrad_kernel(const void* T1, const void* Z, int c128, int wl, int wr, int d, int chil,
+                             int chir, void* out, int out128) {
+    __shared__ double sre[256], sim[256];
+    const int e = blockIdx.x;  // (k, l, s', s)
+    const int s = e % d, sp = (e / d) % d, l = (e / (d * d)) % wr, k = e / (d * d * wr);
+    double re = 0.0, im = 0.0;
+    const int64_t nn = (int64_t)chil * chir;
+    for (int64_t t = threadIdx.x; t < nn; t += blockDim.x) {
+        const int a = (int)(t / chir), b = (int)(t % chir);
+        T xr, xi, zr, zi;
+        ld<T>(T1, c128, (((int64_t)k * chil + a) * d + s) * chir + b, xr, xi);
+        ld<T>(Z, c128, (((int64_t)l * chil + a) * d + sp) * chir + b, zr, zi);
+        re += (double)(xr * zr + xi * zi);
+        im += (double)(xr * zi - xi * zr);
+    }
+    sre[threadIdx.x] = re;
+    sim[threadIdx.x] = im;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) {
+            sre[threadIdx.x] += sre[threadIdx.x + h];
+            sim[threadIdx.x] += sim[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) st<double>(out, out128, e, sre[0], sim[0]);
+}
+
 __global__ void scale_rows_kernel(double2* V, int64_t ld, const double* sv, int rows, int cols) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     const int r = blockIdx.y;
@@ -253,14 +297,32 @@ __global__ void mop_dense_kernel(int kind, const void* W1, int w1_128, const voi
     } else if (kind == 3) {  // (k, s') <- (l, s): W[k][l][s'][s]
         const int k = row / d, sp = row % d, l = col / d, s = col % d;
         ld<double>(W1, w1_128, (((int64_t)k * wr + l) * d + sp) * d + s, re, im);
-    } else {  // kind 2: (n, s1' s2') <- (k, s1 s2): sum_l W1[k][l][s1'][s1] W2[l][n][s2'][s2]
+    } else if (kind == 4) {  // (l, s') <- (k, s): conj(W[k][l][s][s'])  (physical adjoint)
+        const int l = row / d, sp = row % d, k = col / d, s = col % d;
+        ld<double>(W1, w1_128, (((int64_t)k * wr + l) * d + s) * d + sp, re, im);
+        im = -im;
+    } else {
+        // kind 2: (n, s1' s2') <- (k, s1 s2): sum_l W1[k][l][s1'][s1] W2[l][n][s2'][s2]
+        // kind 5: as kind 2 with both factors physically adjoint (conj, s <-> s')
+        // kind 6: (k, s1' s2') <- (n, s1 s2): sum_l W1[k][l][s1'][s1] W2[l][n][s2'][s2]
         const int dd = d * d;
-        const int n = row / dd, s1p = (row % dd) / d, s2p = row % d;
-        const int k = col / dd, s1 = (col % dd) / d, s2 = col % d;
+        int n, s1p, s2p, k, s1, s2;
+        if (kind == 6) {
+            k = row / dd; s1p = (row % dd) / d; s2p = row % d;
+            n = col / dd; s1 = (col % dd) / d; s2 = col % d;
+        } else {
+            n = row / dd; s1p = (row % dd) / d; s2p = row % d;
+            k = col / dd; s1 = (col % dd) / d; s2 = col % d;
+        }
+        const bool adj = kind == 5;
         for (int l = 0; l < wm; ++l) {
             double ar, ai, br, bi;
-            ld<double>(W1, w1_128, (((int64_t)k * wm + l) * d + s1p) * d + s1, ar, ai);
-            ld<double>(W2, w2_128, (((int64_t)l * wr + n) * d + s2p) * d + s2, br, bi);
+            ld<double>(W1, w1_128, (((int64_t)k * wm + l) * d + (adj ? s1 : s1p)) * d + (adj ? s1p : s1), ar, ai);
+            ld<double>(W2, w2_128, (((int64_t)l * wr + n) * d + (adj ? s2 : s2p)) * d + (adj ? s2p : s2), br, bi);
+            if (adj) {
+                ai = -ai;
+                bi = -bi;
+            }
             re += ar * br - ai * bi;
             im += ar * bi + ai * br;
         }
@@ -458,6 +520,25 @@ void mop_build(int kind, const void* W1, Dt w1dt, const void* W2, Dt w2dt, int w
                        cols, dense);
     hipLaunchKernelGGL(mop_csr_kernel, dim3(1), dim3(256), 0, s, dense, rows, cols, row_ptr, col,
                        val, (int)val_fp64);
+    TDVP_CHECK_HIP(hipGetLastError());
+}
+
+void conj_transpose_batched(void* out, const void* in, Dt dt, int n, int batch, hipStream_t s) {
+    if (n == 0 || batch == 0) return;
+    TDVP_REQUIRE(n <= 65535 && batch <= 65535, TDVP_E_SHAPE, "conj_transpose_batched: too large");
+    dim3 grid((n + 127) / 128, n, batch);
+    hipLaunchKernelGGL(conj_transpose_batched_kernel, grid, dim3(128), 0, s, out, in, (int)(dt == Dt::C128), n);
+    TDVP_CHECK_HIP(hipGetLastError());
+}
+
+void wgrad(const void* T1, const void* Z, Dt dt, int wl, int wr, int d, int chil, int chir, void* out,
+           hipStream_t s) {
+    const int nout = wl * wr * d * d;
+    if (nout == 0) return;
+    if (dt == Dt::C128)
+        hipLaunchKernelGGL(wgrad_kernel<double>, dim3(nout), dim3(256), 0, s, T1, Z, 1, wl, wr, d, chil, chir, out, 1);
+    else
+        hipLaunchKernelGGL(wgrad_kernel<float>, dim3(nout), dim3(256), 0, s, T1, Z, 0, wl, wr, d, chil, chir, out, 0);
     TDVP_CHECK_HIP(hipGetLastError());
 }
 
