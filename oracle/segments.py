@@ -1,0 +1,287 @@
+"""Segment-parallel two-site TDVP in the inverse canonical gauge (oracle).
+
+Test infrastructure only: nothing in the product path imports this module.
+
+Inverse canonical gauge (Sec. II A): the state is Psi_1 V_1 Psi_2 ... V_{N-1}
+Psi_N with Psi_j = Lambda_{j-1} Gamma_j Lambda_j and V_j = Lambda_j^{-1}, so
+that Psi_j V_j is left orthonormal and V_{j-1} Psi_j right orthonormal.  The
+two-site local state is Theta = Psi_j V_j Psi_{j+1}; after its update the
+truncated SVD Theta = U S Vh gives Psi_j = U S, V_j = 1/S, Psi_{j+1} = S Vh
+(Fig. postupdate).  A left environment beta_{j+1} is built from beta_j and
+A_j = Psi_j V_j, a right environment gamma_j from gamma_{j+1} and B_{j+1} =
+V_j Psi_{j+1} (Fig. environments).
+
+Segment schedule (Sec. III B, Fig. partitioning).  The chain is cut into p
+contiguous segments (p = 1 or even, each of at least two sites).  In the
+first half of a time step the two central segments sweep away from the centre
+and neighbours alternate direction; the second half reverses every direction.
+The paper's step-by-step diagrams of the parallel step are not part of the
+text, so the following reading is ours; at p = 1 it is exactly the serial
+step (Sec. III A):
+
+* Every boundary -- a bond between two segments, and each chain end -- owns
+  one boundary pair: (b, b+1) for the bond after site b, (0, 1) for the left
+  end and (N-2, N-1) for the right end.  A boundary is *meeting* in a half
+  when the segment(s) next to it sweep toward it, else *departing*.
+* A segment's own sweep covers sites ls..rs, where ls = lo (or 1 at the
+  left chain end) and rs = hi (or N-2 at the right chain end).  Sweeping
+  right it does: backward step on ls, then for j = ls..rs-1 the pair (j, j+1)
+  forward by dt/2 and a backward step on j+1 (mirror image sweeping left).
+  Every site in ls..rs thus gets one backward half step per half.
+* First half: before the sweeps, every departing boundary pair is evolved by
+  dt/2; after the sweeps every meeting boundary pair is evolved by dt (the
+  merged turning point of Sec. III A).  Second half: departing boundary pairs
+  (which met in the first half) get nothing, meeting pairs get dt/2 after the
+  sweeps -- the other dt/2 is the first operation of the next step.
+* The left segment performs a boundary-pair update (Sec. III B); afterwards
+  both environments across that bond, beta_{b+1} and gamma_b, are rebuilt.
+  Environments of a departing boundary are the ones left by the last update
+  there, i.e. out of date (Sec. III D, item i).
+
+Within one phase the segments touch disjoint tensors and environments, so
+they may run in any order with identical results.  Per step every pair is
+evolved forward by dt and every site 1..N-2 backward by dt, as in Eq. proj2site.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from .env import trivial_env, update_left, update_right
+from .heff import apply_heff1, apply_heff2
+from .krylov import expm_krylov
+from .tdvp import Truncation, truncation_rank
+
+
+# --------------------------------------------------------------------- gauge
+
+def to_inverse_canonical(tensors):
+    """Any MPS -> (Psi, V) in the inverse canonical gauge (Sec. II A).
+
+    Right-orthonormalise, then sweep left to right with SVDs: the singular
+    values at bond j are the Schmidt coefficients Lambda_j, A_j = U is left
+    orthonormal and Psi_j = A_j Lambda_j, V_j = 1/Lambda_j.  The norm stays in
+    Psi_{N-1}.
+    """
+    T = [np.array(A, dtype=np.complex128) for A in tensors]
+    N = len(T)
+    for j in range(N - 1, 0, -1):  # right-orthonormalise by LQ (via QR of the adjoint)
+        chil, d, chir = T[j].shape
+        Q, R = np.linalg.qr(T[j].reshape(chil, d * chir).conj().T)
+        T[j] = Q.conj().T.reshape(Q.shape[1], d, chir)
+        T[j - 1] = np.einsum("asb,bc->asc", T[j - 1], R.conj().T)
+    Psi, V = [], []
+    M = T[0]
+    for j in range(N - 1):
+        chil, d, chir = M.shape
+        U, S, Vh = np.linalg.svd(M.reshape(chil * d, chir), full_matrices=False)
+        Psi.append((U * S[None, :]).reshape(chil, d, len(S)))
+        V.append(1.0 / S)
+        M = np.einsum("ab,bsc->asc", S[:, None] * Vh, T[j + 1])
+    Psi.append(M)
+    return Psi, V
+
+
+def from_inverse_canonical(Psi, V):
+    """Site tensors of the same state in an ordinary MPS (V folded to the right)."""
+    T = [Psi[0]]
+    for j in range(1, len(Psi)):
+        T.append(V[j - 1][:, None, None] * Psi[j])
+    return T
+
+
+# ------------------------------------------------------------------ schedule
+
+def directions(p: int, first_half: bool):
+    """+1 (right) or -1 (left) per segment (Fig. partitioning)."""
+    if p == 1:
+        return [1 if first_half else -1]
+    if p % 2:
+        raise ValueError("the number of segments must be 1 or even")
+    h = p // 2
+    dirs = []
+    for s in range(p):
+        dist = (h - 1 - s) if s < h else (s - h)
+        away = -1 if s < h else 1  # away from the centre
+        dirs.append(away if dist % 2 == 0 else -away)
+    return dirs if first_half else [-x for x in dirs]
+
+
+@dataclass
+class Op:
+    kind: str        # "pair" or "site"
+    j: int           # first site of the pair, or the site
+    tau: float       # forward time (negative for backward steps)
+    segment: int
+    refresh: str     # "left", "right", "both" or "" (pairs only)
+
+
+@dataclass
+class Phase:
+    name: str
+    ops: list = field(default_factory=list)
+
+
+def schedule(sizes, dt: float, first_half: bool):
+    """Phases of one half step; the ops inside a phase are independent.
+
+    Returns a list of phases: boundary pairs before the sweeps, the sweep
+    micro-steps (op i of every still active segment), boundary pairs after.
+    """
+    p = len(sizes)
+    if any(n < 2 for n in sizes):
+        raise ValueError("every segment needs at least two sites")
+    N = sum(sizes)
+    if N < 4:
+        raise ValueError("need at least four sites")
+    bounds, lo = [], 0
+    for n in sizes:
+        bounds.append((lo, lo + n - 1))
+        lo += n
+    dirs = directions(p, first_half)
+    half = dt / 2.0
+
+    # boundaries: ("left-end", seg), ("bond", left seg), ("right-end", seg)
+    def meets(kind, s):
+        if kind == "left-end":
+            return dirs[s] == -1
+        if kind == "right-end":
+            return dirs[s] == 1
+        return dirs[s] == 1 and dirs[s + 1] == -1
+
+    boundaries = [("left-end", 0, 0)]
+    boundaries += [("bond", s, bounds[s][1]) for s in range(p - 1)]
+    boundaries += [("right-end", p - 1, N - 2)]
+
+    before, after = Phase("boundary pairs (departing)"), Phase("boundary pairs (meeting)")
+    for kind, s, j in boundaries:
+        if meets(kind, s):
+            after.ops.append(Op("pair", j, dt if first_half else half, s, "both"))
+        elif first_half:
+            before.ops.append(Op("pair", j, half, s, "both"))
+
+    sweeps = []
+    for s, (lo_s, hi_s) in enumerate(bounds):
+        ls, rs = max(lo_s, 1), min(hi_s, N - 2)
+        ops = []
+        if dirs[s] == 1:
+            ops.append(Op("site", ls, -half, s, ""))
+            for j in range(ls, rs):
+                ops.append(Op("pair", j, half, s, "left"))
+                ops.append(Op("site", j + 1, -half, s, ""))
+        else:
+            ops.append(Op("site", rs, -half, s, ""))
+            for j in range(rs - 1, ls - 1, -1):
+                ops.append(Op("pair", j, half, s, "right"))
+                ops.append(Op("site", j, -half, s, ""))
+        sweeps.append(ops)
+    phases = [before] if before.ops else []
+    for i in range(max(len(o) for o in sweeps)):
+        ph = Phase(f"sweep micro-step {i}")
+        ph.ops = [o[i] for o in sweeps if i < len(o)]
+        phases.append(ph)
+    if after.ops:
+        phases.append(after)
+    return phases
+
+
+# --------------------------------------------------------------------- state
+
+@dataclass
+class SegStats:
+    w_total: float = 0.0
+    matvecs: int = 0
+    pair_updates: int = 0
+    site_updates: int = 0
+
+
+class SegmentState:
+    """Inverse canonical MPS, MPO and one stored beta/gamma per site.
+
+    ``chi_static``: optional per-bond caps (bond j after site j) for static
+    shapes; combined with ``tr`` by taking the smaller chi_max.
+    """
+
+    def __init__(self, tensors, Ws, tr: Truncation | None = None, chi_static=None,
+                 kmax: int = 40, tol: float = 1e-13):
+        self.Psi, self.V = to_inverse_canonical(tensors)
+        self.W = [np.asarray(W, dtype=np.complex128) for W in Ws]
+        self.N = len(self.Psi)
+        self.tr = tr if tr is not None else Truncation()
+        self.chi_static = chi_static
+        self.kmax, self.tol = kmax, tol
+        self.stats = SegStats()
+        # all environments from the initial (exactly canonical) state (Sec. III B)
+        N = self.N
+        self.beta = [None] * N
+        self.gamma = [None] * N
+        self.beta[0] = trivial_env()
+        self.gamma[N - 1] = trivial_env()
+        for j in range(N - 1):
+            A = self.Psi[j] * self.V[j][None, None, :]
+            self.beta[j + 1] = update_left(self.beta[j], A, self.W[j])
+        for j in range(N - 1, 0, -1):
+            B = self.V[j - 1][:, None, None] * self.Psi[j]
+            self.gamma[j - 1] = update_right(self.gamma[j], B, self.W[j])
+
+    def tensors(self):
+        return from_inverse_canonical(self.Psi, self.V)
+
+    def _expm(self, apply, x, tau):
+        count = [0]
+
+        def op(v):
+            count[0] += 1
+            return apply(v)
+
+        out = expm_krylov(op, x, tau, kmax=self.kmax, tol=self.tol)
+        self.stats.matvecs += count[0]
+        return out
+
+    def site_update(self, j: int, tau: float):
+        b, W, g = self.beta[j], self.W[j], self.gamma[j]
+        self.Psi[j] = self._expm(lambda x: apply_heff1(b, W, g, x), self.Psi[j], tau)
+        self.stats.site_updates += 1
+
+    def pair_update(self, j: int, tau: float, refresh: str):
+        theta = np.einsum("asb,b,btc->astc", self.Psi[j], self.V[j], self.Psi[j + 1])
+        b, W1, W2, g = self.beta[j], self.W[j], self.W[j + 1], self.gamma[j + 1]
+        theta = self._expm(lambda x: apply_heff2(b, W1, W2, g, x), theta, tau)
+        chil, d1, d2, chir = theta.shape
+        U, S, Vh = np.linalg.svd(theta.reshape(chil * d1, d2 * chir), full_matrices=False)
+        tr = self.tr
+        if self.chi_static is not None:
+            tr = Truncation(min(tr.chi_max, self.chi_static[j]), tr.w_max, tr.eps, tr.multiplet_guard)
+        chi, w = truncation_rank(S, tr)
+        U, S, Vh = U[:, :chi], S[:chi], Vh[:chi, :]
+        self.stats.w_total += w
+        self.stats.pair_updates += 1
+        self.Psi[j] = (U * S[None, :]).reshape(chil, d1, chi)
+        self.V[j] = 1.0 / S
+        self.Psi[j + 1] = (S[:, None] * Vh).reshape(chi, d2, chir)
+        if refresh in ("left", "both"):
+            self.beta[j + 1] = update_left(self.beta[j], U.reshape(chil, d1, chi), self.W[j])
+        if refresh in ("right", "both"):
+            self.gamma[j] = update_right(self.gamma[j + 1], Vh.reshape(chi, d2, chir), self.W[j + 1])
+
+    def run(self, op: Op):
+        if op.kind == "site":
+            self.site_update(op.j, op.tau)
+        else:
+            self.pair_update(op.j, op.tau, op.refresh)
+
+
+def step(st: SegmentState, sizes, dt: float, order=None):
+    """One time step of the segment schedule.  ``order`` (a permutation of the
+    segment indices) changes the execution order inside each phase; results
+    do not depend on it."""
+    for first in (True, False):
+        for ph in schedule(sizes, dt, first):
+            ops = ph.ops
+            if order is not None:
+                rank = {s: i for i, s in enumerate(order)}
+                ops = sorted(ops, key=lambda o: rank[o.segment])
+            for op in ops:
+                st.run(op)
+    return st

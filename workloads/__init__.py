@@ -48,6 +48,42 @@ def full_rank_bonds(N: int, d: int, cap: int | None = None):
     return chi
 
 
+def segment_bounds(sizes):
+    """[(lo, hi)] inclusive 0-based site ranges of contiguous segments."""
+    out, lo = [], 0
+    for n in sizes:
+        out.append((lo, lo + n - 1))
+        lo += n
+    return out
+
+
+def segment_bond_profile(sizes, d: int, chi_lo: int, chi_hi: int, seed: int):
+    """Bond dimensions chi_0..chi_N for a segmented chain with uneven bonds.
+
+    One value D_s per segment drawn uniformly from [chi_lo, chi_hi]; bonds
+    inside segment s take D_s, a bond between two segments the smaller of the
+    two; then chi_j <= min(d^j, d^(N-j)) and chi_j <= d min(chi_{j-1},
+    chi_{j+1}) are imposed until nothing changes, so that every site tensor
+    can be an isometry in either direction.
+    """
+    N = sum(sizes)
+    Ds = np.random.default_rng(seed).integers(chi_lo, chi_hi + 1, len(sizes))
+    seg_of = np.repeat(np.arange(len(sizes)), sizes)
+    chi = [1] * (N + 1)
+    for j in range(1, N):
+        chi[j] = int(min(Ds[seg_of[j - 1]], Ds[seg_of[j]]))
+        chi[j] = min(chi[j], d ** min(j, N - j))
+    changed = True
+    while changed:
+        changed = False
+        for j in range(1, N):
+            cap = d * min(chi[j - 1], chi[j + 1])
+            if chi[j] > cap:
+                chi[j] = cap
+                changed = True
+    return chi
+
+
 # ---------------------------------------------------------------------------
 # Workload parameters (spin-1/2 chains, d = 2).
 # ---------------------------------------------------------------------------
