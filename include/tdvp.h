@@ -57,6 +57,7 @@ typedef enum { TDVP_C64 = 0, TDVP_C128 = 1 } tdvp_dtype;
 typedef struct tdvp_ctx_s* tdvp_ctx;
 typedef struct tdvp_mps_s* tdvp_mps;
 typedef struct tdvp_mpo_s* tdvp_mpo;
+typedef struct tdvp_seg_s* tdvp_seg;
 
 /* Optional device allocator.  alloc returns a device pointer of at least
  * `bytes` bytes usable on `stream`, or NULL; free releases it.  With NULL
@@ -199,6 +200,87 @@ int tdvp1_step(tdvp_ctx ctx, tdvp_mps mps, tdvp_mpo mpo, double dt,
  * evolved once by the full dt.  Same canonical-form contract as tdvp1_step. */
 int tdvp2_step(tdvp_ctx ctx, tdvp_mps mps, tdvp_mpo mpo, double dt,
                const tdvp_opts* opts, tdvp_stats* stats);
+
+/* ------------------------------------- segment-parallel two-site TDVP ---- */
+/* Sec. III B (Fig. partitioning) on one device.  The state is held in the
+ * inverse canonical gauge of Sec. II A: Psi_j = Lambda_{j-1} Gamma_j Lambda_j
+ * (complex128 [chi_j][d][chi_{j+1}]) and V_j = 1/Lambda_j on every bond, plus
+ * one stored left and right environment per site (in the compute dtype).
+ * The chain is cut into p contiguous segments (p = 1 or even, each of at
+ * least two sites).  A time step has two halves; in the first the two
+ * central segments sweep away from the centre and neighbours alternate, in
+ * the second every direction is reversed.  Each segment sweeps its own sites
+ * with two-site forward steps (dt/2) and one-site backward steps (dt/2);
+ * the pair straddling two segments (and each chain-end pair) is evolved
+ * before the sweeps (dt/2, first half, where the segments depart), after
+ * them where they meet (dt in the first half, the merged turning point of
+ * Sec. III A; dt/2 in the second), by the left segment, after which both
+ * environments across that bond are rebuilt.  Environments across a
+ * departing boundary keep their last value (out of date, Sec. III D).  At
+ * p = 1 the step equals tdvp2_step.  The paper's diagrams of the parallel
+ * step are not in its text; this schedule is the library's reading.
+ *
+ * All segments of a phase update at once: their Lanczos exponentiations
+ * (krylov_k steps each, fixed, as in the paper's runs) share one grouped
+ * launch per contraction stage per Krylov iteration; splits and environment
+ * refreshes run per segment.  With static_shapes every bond keeps its
+ * initial dimension as its cap, so each phase has a fixed memory layout and
+ * use_graph can capture its batched exponentiation in a HIP graph (captured
+ * on first use, replayed afterwards, re-captured if library workspaces
+ * move). */
+typedef struct {
+    tdvp_dtype compute;  /* matvec / environment precision; must equal the
+                            dtype given to seg_init.  Lanczos and splits FP64. */
+    int krylov_k;        /* Lanczos steps per exponentiation, 1..16 (paper: 8) */
+    int chi_max;         /* bond dimension cap */
+    double w_max;        /* discarded weight per split, Eq. (discweight) */
+    double eps_rel;      /* relative singular-value cut (Sec. III D) */
+    int multiplet_guard; /* 1: never cut inside a degenerate multiplet */
+    int static_shapes;   /* 1: bond j never exceeds its initial dimension */
+    int batched;         /* 1: one batched exponentiation per phase; 0: one
+                            segment after the other (reference path) */
+    int use_graph;       /* 1: replay each phase's exponentiation from a HIP
+                            graph (needs batched and static_shapes) */
+    int svd_mode;        /* 0: density-matrix split, SVD when a kept singular
+                            value is below 1e-6 of the largest; 1: SVD; 2:
+                            density matrix always */
+} tdvp_seg_opts;
+
+/* Defaults: C64, krylov_k 8, chi_max 1<<30, w_max 0, eps_rel 0, guard on,
+ * static_shapes 1, batched 1, use_graph 0, svd_mode 0. */
+int tdvp_seg_opts_default(tdvp_seg_opts* opts);
+
+/* Build the segmented state from host site tensors (complex128
+ * [chi[j]][d][chi[j+1]], C order; copied, the caller keeps ownership):
+ * right-orthonormalisation, then a left-to-right split sweep that yields
+ * Psi_j and V_j (the Schmidt coefficients must be non-zero), then every left
+ * and right environment (Sec. III B: all initial environments are built
+ * sequentially).  chi must be isometry-feasible (chi_{j+1} <= d chi_j and
+ * chi_j <= d chi_{j+1}) with chi_0 = chi_N = 1; compute is the dtype of the
+ * environments and of the matvecs of later steps.  Errors: TDVP_E_SHAPE for
+ * inconsistent sizes, TDVP_E_NUMERIC for a zero Schmidt coefficient. */
+int seg_init(tdvp_ctx ctx, tdvp_mpo mpo, int N, int d, const int* chi, const void* const* tensors,
+             int nseg, const int* seg_sizes, tdvp_dtype compute, tdvp_seg* out);
+/* One time step of size dt.  TDVP_E_NUMERIC if a Krylov recursion produced a
+ * non-finite value or a kept singular value is zero. */
+int seg_step(tdvp_ctx ctx, tdvp_seg seg, tdvp_mpo mpo, double dt, const tdvp_seg_opts* opts,
+             tdvp_stats* stats);
+/* N, d, the bond dimensions chi[N+1] and the cumulative discarded weight
+ * (any output may be NULL). */
+int seg_get_info(tdvp_seg seg, int* N, int* d, int* chi, double* w_total);
+/* Psi_j to host memory (complex128 [chi_j][d][chi_{j+1}]). */
+int seg_get_psi(tdvp_seg seg, int j, void* out);
+/* V_j = 1/Lambda_j of bond j (between sites j and j+1, 0-based) to host
+ * memory (double [chi_{j+1}]). */
+int seg_get_bond(tdvp_seg seg, int j, double* out);
+int seg_destroy(tdvp_seg seg);
+/* The operations of one half step (host only, no device work): for op n,
+ * phase[n] (ops of one phase run together), kind[n] (2: pair (site, site+1)
+ * forward, 1: one-site backward), site[n] (0-based) and tau[n] (forward
+ * time; negative for backward steps).  n_out receives the op count;
+ * TDVP_E_SHAPE if it exceeds max_ops (outputs may then be NULL). */
+int seg_schedule(int nseg, const int* seg_sizes, double dt, int first_half, int max_ops, int* phase,
+                 int* kind, int* site, double* tau, int* n_out);
 
 /* ------------------------------------------------------ raw-pointer kernels */
 

@@ -37,6 +37,14 @@ class Opts(C.Structure):
     ]
 
 
+class SegOpts(C.Structure):
+    _fields_ = [
+        ("compute", C.c_int), ("krylov_k", C.c_int), ("chi_max", C.c_int), ("w_max", C.c_double),
+        ("eps_rel", C.c_double), ("multiplet_guard", C.c_int), ("static_shapes", C.c_int),
+        ("batched", C.c_int), ("use_graph", C.c_int), ("svd_mode", C.c_int),
+    ]
+
+
 class Stats(C.Structure):
     _fields_ = [
         ("w_step", C.c_double), ("w_total", C.c_double), ("seconds", C.c_double), ("flops", C.c_double),
@@ -81,6 +89,14 @@ SIGNATURES = {
     "energy": (_I, [_P, _P, _P, _PD]),
     "norm2": (_I, [_P, _P, _PD]),
     "overlap": (_I, [_P, _P, _P, _PD]),
+    "tdvp_seg_opts_default": (_I, [C.POINTER(SegOpts)]),
+    "seg_init": (_I, [_P, _P, _I, _I, _PI, C.POINTER(_P), _I, _PI, _I, C.POINTER(_P)]),
+    "seg_step": (_I, [_P, _P, _P, _D, C.POINTER(SegOpts), C.POINTER(Stats)]),
+    "seg_get_info": (_I, [_P, _PI, _PI, _PI, _PD]),
+    "seg_get_psi": (_I, [_P, _I, _PD]),
+    "seg_get_bond": (_I, [_P, _I, _PD]),
+    "seg_destroy": (_I, [_P]),
+    "seg_schedule": (_I, [_I, _PI, _D, _I, _I, _PI, _PI, _PI, _PD, _PI]),
     "tdvp_profile_enable": (_I, [_P, _I]),
     "tdvp_profile_read": (_I, [_P, _I, C.c_char_p, _PD, _PD, _PD, C.POINTER(C.c_long), _PI]),
 }

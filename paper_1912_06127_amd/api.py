@@ -17,7 +17,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import TDVP_C64, TDVP_C128, MpoSpec, Opts, Stats
+from ._lib import TDVP_C64, TDVP_C128, MpoSpec, Opts, SegOpts, Stats
 
 
 class TDVPError(RuntimeError):
@@ -407,6 +407,130 @@ def tdvp2_step(ctx: Context, mps: MPS, mpo: MPO, dt: float, opts: TDVPOptions | 
     st = Stats()
     _check(ctx.handle, _lib.load().tdvp2_step(ctx.handle, mps.handle, mpo.handle, float(dt), C.byref(o), C.byref(st)))
     return st.as_dict()
+
+
+@dataclass
+class SegmentOptions:
+    compute: str = "c64"         # matvec / environment precision (fixed at construction)
+    krylov_k: int = 8            # Lanczos steps per exponentiation
+    chi_max: int = 1 << 30
+    w_max: float = 0.0
+    eps_rel: float = 0.0
+    multiplet_guard: bool = True
+    static_shapes: bool = True
+    batched: bool = True
+    use_graph: bool = False
+    svd_mode: int = 0
+
+    def to_c(self) -> SegOpts:
+        o = SegOpts()
+        o.compute = TDVP_C64 if self.compute == "c64" else TDVP_C128
+        o.krylov_k = self.krylov_k
+        o.chi_max = self.chi_max
+        o.w_max = self.w_max
+        o.eps_rel = self.eps_rel
+        o.multiplet_guard = int(self.multiplet_guard)
+        o.static_shapes = int(self.static_shapes)
+        o.batched = int(self.batched)
+        o.use_graph = int(self.use_graph)
+        o.svd_mode = self.svd_mode
+        return o
+
+
+def segment_schedule(sizes, dt: float, first_half: bool):
+    """[(phase, kind, site, tau)] of one half step as the library runs it (kind 2 pair, 1 site)."""
+    sz = np.ascontiguousarray(sizes, dtype=np.int32)
+    n = C.c_int()
+    lib = _lib.load()
+    rc = lib.seg_schedule(len(sz), _iptr(sz), float(dt), int(first_half), 0, None, None, None, None, C.byref(n))
+    if rc != 0 and not (rc == 2 and n.value > 0):  # 2: the count exceeds max_ops = 0
+        raise TDVPError(rc, "seg_schedule rejected the segment sizes")
+    m = n.value
+    ph, kd, st = (np.zeros(m, dtype=np.int32) for _ in range(3))
+    tau = np.zeros(m)
+    rc = lib.seg_schedule(len(sz), _iptr(sz), float(dt), int(first_half), m, _iptr(ph), _iptr(kd), _iptr(st),
+                          _dptr(tau), C.byref(n))
+    if rc != 0:
+        raise TDVPError(rc, "seg_schedule failed")
+    return [(int(a), int(b), int(c), float(t)) for a, b, c, t in zip(ph, kd, st, tau)]
+
+
+class Segments:
+    """Segment-parallel two-site TDVP state (inverse canonical gauge) held by the library."""
+
+    def __init__(self, ctx: Context, handle, compute: str):
+        self.ctx = ctx
+        self.handle = handle
+        self.compute = compute
+        ctx._adopt(self)
+        N, d = C.c_int(), C.c_int()
+        _check(ctx.handle, _lib.load().seg_get_info(handle, C.byref(N), C.byref(d), None, None))
+        self.N, self.d = N.value, d.value
+
+    @classmethod
+    def init(cls, ctx: Context, mpo: "MPO", tensors, sizes, compute: str = "c64"):
+        """From host site tensors [chi_l][d][chi_r] (any gauge) and segment sizes."""
+        N = len(tensors)
+        d = tensors[0].shape[1]
+        arrs = [np.ascontiguousarray(T, dtype=np.complex128) for T in tensors]
+        chi = np.ascontiguousarray([1] + [A.shape[2] for A in arrs], dtype=np.int32)
+        ptrs = (C.c_void_p * N)(*[A.ctypes.data for A in arrs])
+        sz = np.ascontiguousarray(sizes, dtype=np.int32)
+        h_ = C.c_void_p()
+        rc = _lib.load().seg_init(ctx.handle, mpo.handle, N, d, _iptr(chi), ptrs, len(sz), _iptr(sz),
+                                  TDVP_C64 if compute == "c64" else TDVP_C128, C.byref(h_))
+        _check(ctx.handle, rc)
+        return cls(ctx, h_, compute)
+
+    def step(self, mpo: "MPO", dt: float, opts: SegmentOptions | None = None) -> dict:
+        o = (opts or SegmentOptions(compute=self.compute)).to_c()
+        st = Stats()
+        _check(self.ctx.handle, _lib.load().seg_step(self.ctx.handle, self.handle, mpo.handle, float(dt),
+                                                     C.byref(o), C.byref(st)))
+        return st.as_dict()
+
+    @property
+    def chi(self):
+        c = np.zeros(self.N + 1, dtype=np.int32)
+        _check(self.ctx.handle, _lib.load().seg_get_info(self.handle, None, None, _iptr(c), None))
+        return [int(x) for x in c]
+
+    @property
+    def w_total(self) -> float:
+        w = C.c_double()
+        _check(self.ctx.handle, _lib.load().seg_get_info(self.handle, None, None, None, C.byref(w)))
+        return w.value
+
+    def psi(self, j: int) -> np.ndarray:
+        chi = self.chi
+        out = np.zeros((chi[j], self.d, chi[j + 1]), dtype=np.complex128)
+        _check(self.ctx.handle, _lib.load().seg_get_psi(self.handle, j, _dptr(out.view(np.float64))))
+        return out
+
+    def bond(self, j: int) -> np.ndarray:
+        """V_j = 1/Lambda_j of the bond after site j."""
+        out = np.zeros(self.chi[j + 1], dtype=np.float64)
+        _check(self.ctx.handle, _lib.load().seg_get_bond(self.handle, j, _dptr(out)))
+        return out
+
+    def tensors(self):
+        """Ordinary MPS tensors of the state: Psi_0, V_0 Psi_1, V_1 Psi_2, ..."""
+        out = [self.psi(0)]
+        for j in range(1, self.N):
+            out.append(self.bond(j - 1)[:, None, None] * self.psi(j))
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            if self.ctx.handle:
+                _lib.load().seg_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def expect(ctx: Context, mps: MPS, sites, ops) -> np.ndarray:

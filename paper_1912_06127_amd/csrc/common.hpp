@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <memory>
 #include <stdexcept>
@@ -77,6 +78,7 @@ struct tdvp_ctx_s {
     rocblas_handle blas = nullptr;
     std::string err;
     std::map<std::string, tdvp::Buffer> work;  // grow-only named workspaces
+    uint64_t ws_gen = 0;                        // bumped whenever a workspace moves
     bool prof_on = false;                       // HIP event pair around every launch
     bool autotune = true;                       // time GEMM tiles per shape bucket
     std::vector<tdvp_prof_rec> prof_pending;
@@ -150,6 +152,22 @@ struct GemmDesc {
 // fp64: FP64 MFMA, else FP32 MFMA.  form: 3 (Gauss 3-real-product) or 4.
 void cgemm(tdvp_ctx ctx, const GemmDesc& g, bool fp64, int form);
 
+// Many independent products (batch 1 each, shapes may differ) in one launch.
+// The plan uploads the problem table (device memory owned by the plan) and
+// picks one tile for the group (timed once per shape signature); operands
+// are referenced by pointer, so a plan can be re-run, also inside a captured
+// graph, as long as those buffers stay in place.
+struct GroupedGemm {
+    DevMem probs;
+    int nprob = 0;
+    int64_t total = 0;
+    int cfg = 0;
+    bool fp64 = false, m3 = false, ak = true, bkc = false;
+    double flops = 0.0;
+};
+void grouped_gemm_plan(tdvp_ctx ctx, const std::vector<GemmDesc>& g, bool fp64, int form, GroupedGemm& out);
+void grouped_gemm_run(tdvp_ctx ctx, const GroupedGemm& gg);
+
 // Sparse local-operator stage.  For every grid point (p, q):
 //   out[n][s'](p, q) = sum_{k,s} M[(n,s'),(k,s)] in[k][s](p, q)
 // with in offset  k*ik + s*is + p*ip + q  and out offset n*on + s'*os + p*op + q.
@@ -165,6 +183,46 @@ struct WStageDesc {
     bool fp64 = false;
 };
 void wstage(tdvp_ctx ctx, const WStageDesc& w);
+// Many MPO stages of one precision in one launch (see GroupedGemm).
+struct GroupedWStage {
+    DevMem probs;
+    int nprob = 0, nt = 256;
+    int64_t blocks = 0;
+    size_t shmem = 0;
+    bool fp64 = false;
+    double bytes = 0.0;
+};
+void grouped_wstage_plan(tdvp_ctx ctx, const std::vector<WStageDesc>& ds, GroupedWStage& out);
+void grouped_wstage_run(tdvp_ctx ctx, const GroupedWStage& g);
+
+// ------------------------------------- batched Krylov over packed instances
+// Instance i of a batch owns elements [off[i], off[i+1]) of packed vectors.
+struct SegLayout {
+    int ninst = 0, nblk = 0;
+    int64_t total = 0;
+    std::vector<int64_t> off;          // host copy [ninst + 1]
+    DevMem d_off, d_iblk, d_binst, d_blo;
+};
+void seg_layout(tdvp_ctx ctx, const std::vector<int64_t>& sizes, SegLayout& L);
+// packed <- per-instance sources / per-instance destinations <- packed
+// (pointer tables in device memory).
+void seg_gather(tdvp_ctx ctx, const SegLayout& L, double2* packed, const double2* const* src_dev);
+void seg_scatter(tdvp_ctx ctx, const SegLayout& L, double2* const* dst_dev, const double2* packed);
+// y = H x for all instances at once (packed complex128 vectors).
+using BatchOp = std::function<void(const double2* x, double2* y)>;
+struct BatchState {
+    int ninst = 0;
+    int* bad = nullptr;  // device [ninst]: non-finite value seen (valid until the next call)
+};
+// theta_i <- exp(-i tau H_i) theta_i by K Lanczos steps per instance (two
+// Gram-Schmidt passes, breakdown handled per instance), no host sync.
+void batch_expm(tdvp_ctx ctx, const SegLayout& L, const BatchOp& op, double2* theta, double tau, int K,
+                BatchState& st);
+void batch_expm_reserve(tdvp_ctx ctx, const SegLayout& L, int K);
+// flag[0] = 1 if any instance of the last batch_expm saw a non-finite value;
+// reset_flag sets flag[0] = 0 (kernels, so both may sit inside a graph).
+void seg_flag_or(tdvp_ctx ctx, const BatchState& st, int* flag);
+void reset_flag(tdvp_ctx ctx, int* flag);
 
 // ----------------------------------------------- FP64 vector kernels (c128)
 // All pointers device; n complex elements.

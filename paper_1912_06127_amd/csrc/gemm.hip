@@ -106,8 +106,19 @@ __device__ inline void load_elem(const KOperand& o, int64_t idx, bool valid, T& 
 // are conflict-free: k-contiguous operands are stored [outer][k] (each lane
 // reads its k-slice with vector loads), outer-contiguous operands [k][outer]
 // (consecutive lanes read consecutive outer indices).
+template <typename T, int BM, int BN, int BK, bool AK, bool BKC>
+struct TileSmem {
+    static constexpr int PADK = sizeof(T) == 4 ? 4 : 2;
+    static constexpr int SA = AK ? BM * (BK + PADK) : BK * (BM + PADK);
+    static constexpr int SB = BKC ? BN * (BK + PADK) : BK * (BN + PADK);
+    T a[2][2][SA];
+    T b[2][2][SB];
+};
+
+// One output tile (m0, n0) of batch entry z over k in [kbeg, kend).
 template <typename T, int BM, int BN, int BK, int WM, int WN, bool M3, bool AK, bool BKC>
-__global__ void __launch_bounds__(64 * WM * WN) cgemm2_kernel(KParams p) {
+__device__ __forceinline__ void gemm_block(const KParams& p, TileSmem<T, BM, BN, BK, AK, BKC>& sm, int m0, int n0,
+                                           int64_t zA, int64_t zB, int64_t zC, int kbeg, int kend) {
     using F = Mfma<T>;
     using acc_t = typename F::acc_t;
     constexpr int NT = 64 * WM * WN;
@@ -127,21 +138,9 @@ __global__ void __launch_bounds__(64 * WM * WN) cgemm2_kernel(KParams p) {
     static_assert(AE * NT == BM * BK && BE * NT == BN * BK, "tile/thread mismatch");
     static_assert(AE % 2 == 0 && BE % 2 == 0, "pairwise staging");
     constexpr int NA = M3 ? 3 : 2;
-
-    __shared__ __align__(16) T sA[2][2][SA];
-    __shared__ __align__(16) T sB[2][2][SB];
-
-    const int ntiles = p.tiles_m * p.tiles_n;
-    int t = blockIdx.x;
-    if ((ntiles & 7) == 0) t = (t & 7) * (ntiles >> 3) + (t >> 3);
-    const int m0 = (t % p.tiles_m) * BM;
-    const int n0 = (t / p.tiles_m) * BN;
-    const int z = blockIdx.z / p.ksplit;
-    const int kbeg = (blockIdx.z % p.ksplit) * p.kchunk;
-    const int kend = min(p.K, kbeg + p.kchunk);
-    const int64_t zA = (int64_t)z * p.A.stride;
-    const int64_t zB = (int64_t)z * p.B.stride;
-    const int64_t zC = (int64_t)blockIdx.z * p.strideC;
+    static_assert(SA == TileSmem<T, BM, BN, BK, AK, BKC>::SA && SB == TileSmem<T, BM, BN, BK, AK, BKC>::SB, "smem");
+    auto& sA = sm.a;
+    auto& sB = sm.b;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -288,6 +287,48 @@ __global__ void __launch_bounds__(64 * WM * WN) cgemm2_kernel(KParams p) {
     }
 }
 
+template <typename T, int BM, int BN, int BK, int WM, int WN, bool M3, bool AK, bool BKC>
+__global__ void __launch_bounds__(64 * WM * WN) cgemm2_kernel(KParams p) {
+    __shared__ __align__(16) TileSmem<T, BM, BN, BK, AK, BKC> sm;
+    const int ntiles = p.tiles_m * p.tiles_n;
+    int t = blockIdx.x;
+    if ((ntiles & 7) == 0) t = (t & 7) * (ntiles >> 3) + (t >> 3);  // contiguous tile range per XCD
+    const int m0 = (t % p.tiles_m) * BM;
+    const int n0 = (t / p.tiles_m) * BN;
+    const int z = blockIdx.z / p.ksplit;
+    const int kbeg = (blockIdx.z % p.ksplit) * p.kchunk;
+    const int kend = min(p.K, kbeg + p.kchunk);
+    gemm_block<T, BM, BN, BK, WM, WN, M3, AK, BKC>(p, sm, m0, n0, (int64_t)z * p.A.stride, (int64_t)z * p.B.stride,
+                                                   (int64_t)blockIdx.z * p.strideC, kbeg, kend);
+}
+
+// Grouped form: many independent products of different shapes in one launch.
+// Block b (after the XCD remap over all tiles) finds its problem by binary
+// search over the problems' first tile indices.
+struct GProblem {
+    KParams p;
+    int64_t tile_begin;
+};
+
+template <typename T, int BM, int BN, int BK, int WM, int WN, bool M3, bool AK, bool BKC>
+__global__ void __launch_bounds__(64 * WM * WN) cgemm2_grouped_kernel(const GProblem* __restrict__ probs, int nprob,
+                                                                      int64_t total) {
+    __shared__ __align__(16) TileSmem<T, BM, BN, BK, AK, BKC> sm;
+    int64_t t = blockIdx.x;
+    if ((total & 7) == 0) t = (t & 7) * (total >> 3) + (t >> 3);
+    int lo = 0, hi = nprob - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (probs[mid].tile_begin <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    const KParams p = probs[lo].p;
+    const int tl = (int)(t - probs[lo].tile_begin);
+    const int m0 = (tl % p.tiles_m) * BM;
+    const int n0 = (tl / p.tiles_m) * BN;
+    gemm_block<T, BM, BN, BK, WM, WN, M3, AK, BKC>(p, sm, m0, n0, 0, 0, 0, 0, p.K);
+}
+
 // Sum of split-K partials in a fixed order (deterministic), converted to
 // the output type: C[b][m][n] = sum_s part[b][s][m][n].
 template <typename T>
@@ -344,6 +385,28 @@ void launch2(tdvp_ctx ctx, KParams kp, int batch) {
     TDVP_CHECK_HIP(hipGetLastError());
 }
 
+template <typename T, int BM, int BN, int BK, int WM, int WN, bool M3>
+void launch_grouped(tdvp_ctx ctx, const GProblem* probs, int nprob, int64_t total, bool ak, bool bkc, double flops) {
+    char name[64];
+    snprintf(name, sizeof(name), "cgemm2g_%s_%s_%dx%dx%d_w%dx%d", sizeof(T) == 4 ? "f32" : "f64", M3 ? "3m" : "4m", BM,
+             BN, BK, WM, WN);
+    ProfScope prof(ctx, name, flops, 0.0);
+    const dim3 grid((unsigned)total), blk(64 * WM * WN);
+    if (ak && !bkc)
+        hipLaunchKernelGGL((cgemm2_grouped_kernel<T, BM, BN, BK, WM, WN, M3, true, false>), grid, blk, 0, ctx->stream,
+                           probs, nprob, total);
+    else if (ak && bkc)
+        hipLaunchKernelGGL((cgemm2_grouped_kernel<T, BM, BN, BK, WM, WN, M3, true, true>), grid, blk, 0, ctx->stream,
+                           probs, nprob, total);
+    else if (!ak && !bkc)
+        hipLaunchKernelGGL((cgemm2_grouped_kernel<T, BM, BN, BK, WM, WN, M3, false, false>), grid, blk, 0, ctx->stream,
+                           probs, nprob, total);
+    else
+        hipLaunchKernelGGL((cgemm2_grouped_kernel<T, BM, BN, BK, WM, WN, M3, false, true>), grid, blk, 0, ctx->stream,
+                           probs, nprob, total);
+    TDVP_CHECK_HIP(hipGetLastError());
+}
+
 // Tile configurations.  f32: v_mfma_f32_32x32x2f32 (32x32 per instruction),
 // f64: v_mfma_f64_16x16x4f64.  Names: BMxBNxBK, waves WMxWN.
 struct TileCfg {
@@ -392,6 +455,42 @@ bool launch_tile(tdvp_ctx ctx, const KParams& kp, int batch, bool fp64, bool m3,
         case 12: launch_form<double, 64, 64, 8, 2, 2>(ctx, kp, batch, false); return true;
         case 15: launch_form<double, 128, 64, 16, 4, 2>(ctx, kp, batch, false); return true;
         case 16: launch_form<double, 32, 64, 8, 1, 2>(ctx, kp, batch, false); return true;
+        default: return false;
+    }
+}
+
+template <typename T, int BM, int BN, int BK, int WM, int WN>
+void grouped_form(tdvp_ctx ctx, const GProblem* probs, int nprob, int64_t total, bool m3, bool ak, bool bkc,
+                  double flops) {
+    if constexpr (sizeof(T) == 8) {
+        launch_grouped<T, BM, BN, BK, WM, WN, false>(ctx, probs, nprob, total, ak, bkc, flops);
+    } else {
+        if (m3) launch_grouped<T, BM, BN, BK, WM, WN, true>(ctx, probs, nprob, total, ak, bkc, flops);
+        else launch_grouped<T, BM, BN, BK, WM, WN, false>(ctx, probs, nprob, total, ak, bkc, flops);
+    }
+}
+
+bool launch_grouped_tile(tdvp_ctx ctx, const GProblem* probs, int nprob, int64_t total, bool fp64, bool m3, bool ak,
+                         bool bkc, int cfg, double flops) {
+    if (!fp64) {
+        switch (cfg) {
+            case 2: grouped_form<float, 128, 128, 16, 2, 4>(ctx, probs, nprob, total, m3, ak, bkc, flops); return true;
+            case 9: grouped_form<float, 64, 64, 32, 2, 2>(ctx, probs, nprob, total, m3, ak, bkc, flops); return true;
+            case 10: grouped_form<float, 64, 128, 16, 2, 4>(ctx, probs, nprob, total, m3, ak, bkc, flops); return true;
+            case 12: grouped_form<float, 64, 64, 16, 2, 2>(ctx, probs, nprob, total, m3, ak, bkc, flops); return true;
+            case 13: grouped_form<float, 128, 128, 16, 4, 4>(ctx, probs, nprob, total, m3, ak, bkc, flops); return true;
+            case 14: grouped_form<float, 64, 128, 32, 2, 4>(ctx, probs, nprob, total, m3, ak, bkc, flops); return true;
+            case 15: grouped_form<float, 128, 64, 16, 4, 2>(ctx, probs, nprob, total, m3, ak, bkc, flops); return true;
+            case 16: grouped_form<float, 32, 64, 16, 1, 2>(ctx, probs, nprob, total, m3, ak, bkc, flops); return true;
+            default: return false;
+        }
+    }
+    switch (cfg) {
+        case 2: grouped_form<double, 128, 128, 8, 2, 4>(ctx, probs, nprob, total, false, ak, bkc, flops); return true;
+        case 9: grouped_form<double, 64, 64, 16, 2, 2>(ctx, probs, nprob, total, false, ak, bkc, flops); return true;
+        case 12: grouped_form<double, 64, 64, 8, 2, 2>(ctx, probs, nprob, total, false, ak, bkc, flops); return true;
+        case 15: grouped_form<double, 128, 64, 16, 4, 2>(ctx, probs, nprob, total, false, ak, bkc, flops); return true;
+        case 16: grouped_form<double, 32, 64, 8, 1, 2>(ctx, probs, nprob, total, false, ak, bkc, flops); return true;
         default: return false;
     }
 }
@@ -610,6 +709,141 @@ void cgemm(tdvp_ctx ctx, const GemmDesc& g, bool fp64, int form) {
         const Choice h = heuristic_cfg(g, fp64);
         launch_cfg(ctx, kp, g.batch, fp64, m3, h.cfg, h.ks);
     }
+}
+
+namespace {
+
+// Problem table for tile `cfg` (tile counts depend on the tile edge).
+int64_t build_table(const std::vector<GemmDesc>& g, const TileCfg& c, std::vector<GProblem>& out) {
+    out.clear();
+    int64_t total = 0;
+    for (const auto& d : g) {
+        if (d.M == 0 || d.N == 0) continue;
+        GProblem q{};
+        q.p.M = d.M;
+        q.p.N = d.N;
+        q.p.K = d.K;
+        q.p.tiles_m = (d.M + c.BM - 1) / c.BM;
+        q.p.tiles_n = (d.N + c.BN - 1) / c.BN;
+        q.p.ksplit = 1;
+        q.p.kchunk = d.K;
+        q.p.A = to_k(d.A);
+        q.p.B = to_k(d.B);
+        q.p.C = d.C;
+        q.p.c128C = d.cdt == Dt::C128;
+        q.p.ldc = d.ldc;
+        q.p.strideC = 0;
+        q.tile_begin = total;
+        total += (int64_t)q.p.tiles_m * q.p.tiles_n;
+        out.push_back(q);
+    }
+    return total;
+}
+
+struct GroupTuner {
+    std::mutex mu;
+    std::map<std::vector<int>, int> best;  // (fp64, form, shapes...) -> tile
+};
+GroupTuner& group_tuner() {
+    static GroupTuner t;
+    return t;
+}
+
+}  // namespace
+
+void grouped_gemm_plan(tdvp_ctx ctx, const std::vector<GemmDesc>& g, bool fp64, int form, GroupedGemm& out) {
+    out.fp64 = fp64;
+    out.m3 = fp64 ? false : form == 3;
+    out.flops = 0.0;
+    bool first = true;
+    std::vector<int> sig{fp64 ? 1 : 0, out.m3 ? 3 : 4};
+    for (const auto& d : g) {
+        TDVP_REQUIRE(d.batch == 1, TDVP_E_ARG, "grouped gemm: batch must be 1");
+        TDVP_REQUIRE(d.M >= 0 && d.N >= 0 && d.K >= 0, TDVP_E_SHAPE, "grouped gemm: bad sizes");
+        if (d.M == 0 || d.N == 0) continue;
+        TDVP_REQUIRE(d.A.p && d.B.p && d.C, TDVP_E_ARG, "grouped gemm: null operand");
+        if (first) {
+            out.ak = d.A.kcontig;
+            out.bkc = d.B.kcontig;
+            first = false;
+        }
+        TDVP_REQUIRE(d.A.kcontig == out.ak && d.B.kcontig == out.bkc, TDVP_E_ARG,
+                     "grouped gemm: all problems must share operand layouts");
+        out.flops += 8.0 * d.M * (double)d.N * d.K;
+        sig.push_back(d.M);
+        sig.push_back(d.N);
+        sig.push_back(d.K);
+    }
+    std::vector<GProblem> tab;
+    auto upload = [&](int cfg) {
+        const TileCfg* c = find_tile(cfg, fp64);
+        out.total = build_table(g, *c, tab);
+        out.nprob = (int)tab.size();
+        out.cfg = cfg;
+        if (out.probs.bytes < sizeof(GProblem) * tab.size()) out.probs = DevMem(ctx, sizeof(GProblem) * tab.size());
+        if (!tab.empty())
+            TDVP_CHECK_HIP(hipMemcpyAsync(out.probs.ptr, tab.data(), sizeof(GProblem) * tab.size(),
+                                          hipMemcpyHostToDevice, ctx->stream));
+        // the table must be on the device before the host vector goes away
+        TDVP_CHECK_HIP(hipStreamSynchronize(ctx->stream));
+    };
+    const int forced = forced_cfg();
+    if (forced > 0 && find_tile(forced, fp64)) {
+        upload(forced);
+        return;
+    }
+    // heuristic: the large tile when it still gives every CU two blocks
+    int cfg = fp64 ? 2 : 10;
+    {
+        std::vector<GProblem> t2;
+        if (build_table(g, *find_tile(cfg, fp64), t2) < 512) cfg = 12;
+    }
+    GroupTuner& T = group_tuner();
+    {
+        std::lock_guard<std::mutex> lock(T.mu);
+        auto it = T.best.find(sig);
+        if (it != T.best.end()) cfg = it->second;
+        else if (ctx->autotune && out.flops >= 1e11 && !stream_capturing(ctx->stream)) {
+            hipEvent_t e0, e1;
+            TDVP_CHECK_HIP(hipEventCreate(&e0));
+            TDVP_CHECK_HIP(hipEventCreate(&e1));
+            float best_ms = 1e30f;
+            const bool prof = ctx->prof_on;
+            ctx->prof_on = false;
+            // candidates: the tiles that win on large ragged groups
+            const int cand32[] = {10, 2, 12, 15}, cand64[] = {2, 12, 15};
+            const int* cand = fp64 ? cand64 : cand32;
+            const int ncand = fp64 ? 3 : 4;
+            for (int ci = 0; ci < ncand; ++ci) {
+                const TileCfg& c = *find_tile(cand[ci], fp64);
+                upload(c.id);
+                auto* pr = static_cast<const GProblem*>(out.probs.ptr);
+                launch_grouped_tile(ctx, pr, out.nprob, out.total, fp64, out.m3, out.ak, out.bkc, c.id, out.flops);
+                TDVP_CHECK_HIP(hipEventRecord(e0, ctx->stream));
+                launch_grouped_tile(ctx, pr, out.nprob, out.total, fp64, out.m3, out.ak, out.bkc, c.id, out.flops);
+                TDVP_CHECK_HIP(hipEventRecord(e1, ctx->stream));
+                TDVP_CHECK_HIP(hipEventSynchronize(e1));
+                float ms = 0.f;
+                TDVP_CHECK_HIP(hipEventElapsedTime(&ms, e0, e1));
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    cfg = c.id;
+                }
+            }
+            ctx->prof_on = prof;
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            T.best[sig] = cfg;
+        }
+    }
+    upload(cfg);
+}
+
+void grouped_gemm_run(tdvp_ctx ctx, const GroupedGemm& gg) {
+    if (gg.nprob == 0 || gg.total == 0) return;
+    TDVP_REQUIRE(gg.total <= 0x7fffffff, TDVP_E_SHAPE, "grouped gemm: too many tiles");
+    launch_grouped_tile(ctx, static_cast<const GProblem*>(gg.probs.ptr), gg.nprob, gg.total, gg.fp64, gg.m3, gg.ak,
+                        gg.bkc, gg.cfg, gg.flops);
 }
 
 }  // namespace tdvp

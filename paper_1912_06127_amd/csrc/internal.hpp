@@ -77,6 +77,18 @@ KrylovInfo expm_krylov(tdvp_ctx ctx, const MatVec& op, double2* theta, int64_t n
 void tridiag_eigen(const std::vector<double>& alpha, const std::vector<double>& beta,
                    std::vector<double>& evals, std::vector<double>& evecs);
 
+// Truncation rule of a two-site split (Sec. III C, Eq. discweight; Sec. III D
+// relative cut): chi_w = smallest rank whose discarded weight is <= w_max,
+// chi_eps = count of s >= eps s_1, chi = max(1, min(chi_w, chi_max, chi_eps)),
+// then lowered while s_{chi+1} is within 1e-10 of s_chi (multiplet guard).
+// s descending; returns chi and the discarded weight in w.
+struct TruncRule {
+    int chi_max;
+    double w_max, eps;
+    bool guard;
+};
+int truncation_rank(const std::vector<double>& s, const TruncRule& r, double& w);
+
 // ------------------------------------------------------------- solvers
 // Row-major QR: M [rows][cols] = Q [rows][k] R [k][cols], k = min(rows, cols).
 void qr_rowmajor(tdvp_ctx ctx, const double2* M, int rows, int cols, double2* Q, double2* R);

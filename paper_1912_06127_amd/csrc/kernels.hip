@@ -48,21 +48,16 @@ struct WParams {
     const void* val;
 };
 
+// Grid point (p, q) of one MPO stage; xin is this thread's LDS column.
 template <typename T>
-__global__ void wstage_kernel(WParams w) {
+__device__ __forceinline__ void wstage_point(const WParams& w, int p, int q, typename cplx<T>::t* xin, int nt) {
     using C = typename cplx<T>::t;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    C* xin = reinterpret_cast<C*>(smem_raw);  // [nin][blockDim.x]
-    const int nt = blockDim.x;
-    const int q = blockIdx.x * nt + threadIdx.x;
-    const int p = blockIdx.y;
-    if (q >= w.Q) return;  // no barrier below: each thread uses only its column
     const int64_t pin = (int64_t)p * w.ip + q;
     for (int c = 0; c < w.nin; ++c) {
         const int k = c / w.D, s = c % w.D;
         T re, im;
         ld<T>(w.in, w.in128, pin + k * w.ik + s * w.is, re, im);
-        xin[c * nt + threadIdx.x] = C{re, im};
+        xin[c * nt] = C{re, im};
     }
     const C* val = reinterpret_cast<const C*>(w.val);
     const int64_t pout = (int64_t)p * w.op + q;
@@ -71,13 +66,51 @@ __global__ void wstage_kernel(WParams w) {
         const int e1 = w.row_ptr[r + 1];
         for (int e = w.row_ptr[r]; e < e1; ++e) {
             const C v = val[e];
-            const C x = xin[w.col[e] * nt + threadIdx.x];
+            const C x = xin[w.col[e] * nt];
             ar += v.x * x.x - v.y * x.y;
             ai += v.x * x.y + v.y * x.x;
         }
         const int n = r / w.D, s = r % w.D;
         st<T>(w.out, w.out128, pout + n * w.on + s * w.os, ar, ai);
     }
+}
+
+template <typename T>
+__global__ void wstage_kernel(WParams w) {
+    using C = typename cplx<T>::t;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C* xin = reinterpret_cast<C*>(smem_raw);  // [nin][blockDim.x]
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= w.Q) return;  // no barrier: each thread uses only its column
+    wstage_point<T>(w, blockIdx.y, q, xin + threadIdx.x, blockDim.x);
+}
+
+// Grouped MPO stage: problem g owns blocks [blk_begin, blk_begin + P*qblocks).
+struct GWProblem {
+    WParams w;
+    int64_t blk_begin;
+    int qblocks;
+};
+
+template <typename T>
+__global__ void wstage_grouped_kernel(const GWProblem* __restrict__ probs, int nprob) {
+    using C = typename cplx<T>::t;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C* xin = reinterpret_cast<C*>(smem_raw);
+    const int64_t b = blockIdx.x;
+    int lo = 0, hi = nprob - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (probs[mid].blk_begin <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    const int qb = probs[lo].qblocks;
+    const int64_t local = b - probs[lo].blk_begin;
+    const int p = (int)(local / qb);
+    const int q = (int)(local % qb) * blockDim.x + threadIdx.x;
+    const WParams w = probs[lo].w;
+    if (q >= w.Q) return;
+    wstage_point<T>(w, p, q, xin + threadIdx.x, blockDim.x);
 }
 
 // ------------------------------------------------------------ FP64 vectors
@@ -419,6 +452,74 @@ void wstage(tdvp_ctx ctx, const WStageDesc& d) {
                    pts * (w.nin * elem_bytes(d.in_dt) + w.nout * elem_bytes(d.out_dt)));
     if (d.fp64) hipLaunchKernelGGL(wstage_kernel<double>, grid, dim3(nt), shmem, s, w);
     else hipLaunchKernelGGL(wstage_kernel<float>, grid, dim3(nt), shmem, s, w);
+    TDVP_CHECK_HIP(hipGetLastError());
+}
+
+void grouped_wstage_plan(tdvp_ctx ctx, const std::vector<WStageDesc>& ds, GroupedWStage& out) {
+    std::vector<GWProblem> tab;
+    int nin_max = 1;
+    bool first = true;
+    out.bytes = 0.0;
+    for (const auto& d : ds) {
+        if (first) {
+            out.fp64 = d.fp64;
+            first = false;
+        }
+        TDVP_REQUIRE(d.fp64 == out.fp64, TDVP_E_ARG, "grouped wstage: mixed precision");
+        nin_max = std::max(nin_max, d.w_in * d.D);
+    }
+    const size_t esz = out.fp64 ? sizeof(double2) : sizeof(float2);
+    int nt = 256;
+    while (nt > 64 && (size_t)nt * nin_max * esz > 48 * 1024) nt /= 2;
+    out.nt = nt;
+    out.shmem = (size_t)nt * nin_max * esz;
+    TDVP_REQUIRE(out.shmem <= 160 * 1024, TDVP_E_SHAPE, "wstage: MPO bond dimension too large");
+    int64_t blocks = 0;
+    for (const auto& d : ds) {
+        if (d.P == 0 || d.Q == 0) continue;
+        GWProblem g{};
+        WParams& w = g.w;
+        w.in = d.in;
+        w.in128 = d.in_dt == Dt::C128;
+        w.out = d.out;
+        w.out128 = d.out_dt == Dt::C128;
+        w.P = d.P;
+        w.Q = d.Q;
+        w.D = d.D;
+        w.nin = d.w_in * d.D;
+        w.nout = d.w_out * d.D;
+        w.ik = d.ik; w.is = d.is; w.ip = d.ip;
+        w.on = d.on; w.os = d.os; w.op = d.op;
+        w.row_ptr = d.row_ptr;
+        w.col = d.col;
+        w.val = d.val;
+        g.qblocks = (d.Q + nt - 1) / nt;
+        g.blk_begin = blocks;
+        blocks += (int64_t)d.P * g.qblocks;
+        out.bytes += (double)d.P * d.Q * (w.nin * elem_bytes(d.in_dt) + w.nout * elem_bytes(d.out_dt));
+        tab.push_back(g);
+    }
+    TDVP_REQUIRE(blocks <= 0x7fffffff, TDVP_E_SHAPE, "grouped wstage: grid too large");
+    out.nprob = (int)tab.size();
+    out.blocks = blocks;
+    if (out.probs.bytes < sizeof(GWProblem) * tab.size()) out.probs = DevMem(ctx, sizeof(GWProblem) * tab.size());
+    if (!tab.empty()) {
+        TDVP_CHECK_HIP(hipMemcpyAsync(out.probs.ptr, tab.data(), sizeof(GWProblem) * tab.size(), hipMemcpyHostToDevice,
+                                      ctx->stream));
+        TDVP_CHECK_HIP(hipStreamSynchronize(ctx->stream));
+    }
+}
+
+void grouped_wstage_run(tdvp_ctx ctx, const GroupedWStage& g) {
+    if (g.nprob == 0 || g.blocks == 0) return;
+    ProfScope prof(ctx, g.fp64 ? "wstage_grouped_f64" : "wstage_grouped_f32", 0.0, g.bytes);
+    const auto* pr = static_cast<const GWProblem*>(g.probs.ptr);
+    if (g.fp64)
+        hipLaunchKernelGGL(wstage_grouped_kernel<double>, dim3((unsigned)g.blocks), dim3(g.nt), g.shmem, ctx->stream,
+                           pr, g.nprob);
+    else
+        hipLaunchKernelGGL(wstage_grouped_kernel<float>, dim3((unsigned)g.blocks), dim3(g.nt), g.shmem, ctx->stream,
+                           pr, g.nprob);
     TDVP_CHECK_HIP(hipGetLastError());
 }
 

@@ -36,6 +36,7 @@ void* tdvp_ctx_s::workspace(const std::string& name, size_t bytes) {
         size_t cap = bytes + bytes / 4 + 256;
         b.ptr = dev_alloc(cap);
         b.bytes = cap;
+        ++ws_gen;  // anything that recorded workspace addresses must re-record them
     }
     return b.ptr;
 }

@@ -10,6 +10,25 @@
 
 using namespace tdvp;
 
+int tdvp::truncation_rank(const std::vector<double>& s, const TruncRule& r, double& w) {
+    const int full = (int)s.size();
+    std::vector<double> tail(full + 1, 0.0);
+    for (int c = full - 1; c >= 0; --c) tail[c] = tail[c + 1] + s[c] * s[c];
+    int chi_w = full;
+    for (int c = 1; c <= full; ++c)
+        if (tail[c] <= r.w_max) {
+            chi_w = c;
+            break;
+        }
+    int chi_eps = 0;
+    for (int c = 0; c < full; ++c) chi_eps += (s[c] >= r.eps * s[0]);
+    int chi = std::max(1, std::min(std::min(chi_w, r.chi_max), chi_eps));
+    if (r.guard)
+        while (chi > 1 && chi < full && s[chi] >= (1.0 - 1e-10) * s[chi - 1]) --chi;
+    w = tail[chi];
+    return chi;
+}
+
 namespace {
 
 struct Stepper {
@@ -167,22 +186,7 @@ struct Stepper {
 
     // ------------------------------------------------------------- 2TDVP
     int trunc_rank(const std::vector<double>& s, double& w) {
-        const int full = (int)s.size();
-        std::vector<double> tail(full + 1, 0.0);
-        for (int c = full - 1; c >= 0; --c) tail[c] = tail[c + 1] + s[c] * s[c];
-        int chi_w = full;
-        for (int c = 1; c <= full; ++c)
-            if (tail[c] <= o.w_max) {
-                chi_w = c;
-                break;
-            }
-        int chi_eps = 0;
-        for (int c = 0; c < full; ++c) chi_eps += (s[c] >= o.eps_rel * s[0]);
-        int chi = std::max(1, std::min(std::min(chi_w, o.chi_max), chi_eps));
-        if (o.multiplet_guard)
-            while (chi > 1 && chi < full && s[chi] >= (1.0 - 1e-10) * s[chi - 1]) --chi;
-        w = tail[chi];
-        return chi;
+        return truncation_rank(s, TruncRule{o.chi_max, o.w_max, o.eps_rel, o.multiplet_guard != 0}, w);
     }
 
     double2* form_theta(int j) {

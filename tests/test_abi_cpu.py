@@ -60,3 +60,20 @@ def test_package_fit_matches_oracle_fit():
         g2 = omp.eval_exponentials(c2, l2, R)[1:]
         assert np.max(np.abs(g1 - g2)) < 1e-10
         assert abs(e1 - e2) < 1e-10
+
+
+@pytest.mark.parametrize("sizes", [[10], [5, 5], [3, 2, 2, 3], [2, 2, 2, 2, 2, 2], [11] + [6] * 30 + [10]])
+def test_library_segment_schedule_equals_oracle(sizes):
+    """The library's segment schedule (host logic, no device) lists the same
+    operations, phase by phase, as the oracle's reading of Sec. III B."""
+    import paper_1912_06127_amd as pkg
+    from oracle import segments as oseg
+    for first in (True, False):
+        got = pkg.segment_schedule(sizes, 0.1, first)
+        ref = []
+        for p, ph in enumerate(oseg.schedule(sizes, 0.1, first)):
+            for op in ph.ops:
+                ref.append((p, 2 if op.kind == "pair" else 1, op.j, op.tau))
+        assert sorted(got) == sorted(ref)
+    with pytest.raises(pkg.TDVPError):
+        pkg.segment_schedule([3, 3, 3], 0.1, True)
