@@ -57,12 +57,14 @@ from .tdvp import Truncation, truncation_rank
 # --------------------------------------------------------------------- gauge
 
 def to_inverse_canonical(tensors):
-    """Any MPS -> (Psi, V) in the inverse canonical gauge (Sec. II A).
+    """Any MPS -> (Psi, V) of the normalised state in the inverse canonical
+    gauge (Sec. II A).
 
     Right-orthonormalise, then sweep left to right with SVDs: the singular
-    values at bond j are the Schmidt coefficients Lambda_j, A_j = U is left
-    orthonormal and Psi_j = A_j Lambda_j, V_j = 1/Lambda_j.  The norm stays in
-    Psi_{N-1}.
+    values at bond j are the Schmidt coefficients Lambda_j (unit 2-norm for
+    the normalised state), A_j = U is left orthonormal and Psi_j = A_j
+    Lambda_j, V_j = 1/Lambda_j.  The global factor is dropped on the way (it
+    would overflow for long chains of unnormalised tensors).
     """
     T = [np.array(A, dtype=np.complex128) for A in tensors]
     N = len(T)
@@ -71,11 +73,13 @@ def to_inverse_canonical(tensors):
         Q, R = np.linalg.qr(T[j].reshape(chil, d * chir).conj().T)
         T[j] = Q.conj().T.reshape(Q.shape[1], d, chir)
         T[j - 1] = np.einsum("asb,bc->asc", T[j - 1], R.conj().T)
+        T[j - 1] /= np.linalg.norm(T[j - 1])
     Psi, V = [], []
     M = T[0]
     for j in range(N - 1):
         chil, d, chir = M.shape
         U, S, Vh = np.linalg.svd(M.reshape(chil * d, chir), full_matrices=False)
+        S = S / np.linalg.norm(S)
         Psi.append((U * S[None, :]).reshape(chil, d, len(S)))
         V.append(1.0 / S)
         M = np.einsum("ab,bsc->asc", S[:, None] * Vh, T[j + 1])
