@@ -317,6 +317,19 @@ int apply_heff_adjoint(tdvp_ctx ctx, int nsite, tdvp_dtype dtype, int chil, int 
                        const void* R, const void* theta, const void* ybar, void* theta_bar,
                        void* L_bar, void* W1_bar, void* W2_bar, void* R_bar);
 
+/* Many independent effective-Hamiltonian applications at once (the
+ * segments of Sec. III B as one batch): descriptor i has the meaning of the
+ * arguments of apply_heff; sizes and nsite may differ between descriptors.
+ * One grouped launch per contraction stage serves all of them.  All device
+ * pointers of `dtype`; outputs must not alias any input or another output.
+ * Synchronises the context stream before returning. */
+typedef struct {
+    int nsite, chil, chir, d, wl, wm, wr;
+    const void *L, *W1, *W2, *R, *theta;
+    void* out;
+} tdvp_heff_desc;
+int apply_heff_batched(tdvp_ctx ctx, tdvp_dtype dtype, int n, const tdvp_heff_desc* descs);
+
 /* Environment update (Sec. III A, left-environment figure):
  *   dir = +1: out[l][b'][b] = sum conj(A[a'][s'][b']) env[k][a'][a] W[k][l][s'][s] A[a][s][b]
  *             (env = L_j [wl][chil][chil], out = L_{j+1} [wr][chir][chir])

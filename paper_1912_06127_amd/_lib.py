@@ -45,6 +45,14 @@ class SegOpts(C.Structure):
     ]
 
 
+class HeffDesc(C.Structure):
+    _fields_ = [
+        ("nsite", C.c_int), ("chil", C.c_int), ("chir", C.c_int), ("d", C.c_int), ("wl", C.c_int),
+        ("wm", C.c_int), ("wr", C.c_int), ("L", C.c_void_p), ("W1", C.c_void_p), ("W2", C.c_void_p),
+        ("R", C.c_void_p), ("theta", C.c_void_p), ("out", C.c_void_p),
+    ]
+
+
 class Stats(C.Structure):
     _fields_ = [
         ("w_step", C.c_double), ("w_total", C.c_double), ("seconds", C.c_double), ("flops", C.c_double),
@@ -82,6 +90,7 @@ SIGNATURES = {
     "tdvp1_step": (_I, [_P, _P, _P, _D, C.POINTER(Opts), C.POINTER(Stats)]),
     "tdvp2_step": (_I, [_P, _P, _P, _D, C.POINTER(Opts), C.POINTER(Stats)]),
     "apply_heff": (_I, [_P, _I, _I, _I, _I, _I, _I, _I, _I, _P, _P, _P, _P, _P, _P]),
+    "apply_heff_batched": (_I, [_P, _I, _I, C.POINTER(HeffDesc)]),
     "env_update": (_I, [_P, _I, _I, _I, _I, _I, _I, _I, _P, _P, _P, _P]),
     "apply_heff_adjoint": (_I, [_P, _I, _I, _I, _I, _I, _I, _I, _I] + [_P] * 11),
     "expect": (_I, [_P, _P, _I, _PI, _PD, _PD]),

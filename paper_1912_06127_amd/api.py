@@ -179,6 +179,36 @@ def apply_heff(ctx: Context, L, R, theta, W1=None, W2=None, out=None) -> torch.T
     return out
 
 
+def apply_heff_batched(ctx: Context, problems):
+    """H_eff theta for many local states at once.
+
+    problems: sequence of (L, R, theta, W1, W2) tuples as for apply_heff (W1,
+    W2 may be None); all tensors of one dtype.  Returns the list of outputs.
+    """
+    if not problems:
+        return []
+    dt = problems[0][2].dtype
+    descs = (_lib.HeffDesc * len(problems))()
+    outs, keep = [], []
+    ptr = lambda t: _dev(t, dt).value if t is not None else None
+    for i, (L, R, theta, W1, W2) in enumerate(problems):
+        nsite = theta.dim() - 2
+        out = torch.empty_like(theta)
+        outs.append(out)
+        keep += [L, R, theta, W1, W2]
+        q = descs[i]
+        q.nsite = nsite
+        q.chil, q.chir = L.shape[1], R.shape[1]
+        q.d = theta.shape[1] if nsite >= 1 else 1
+        q.wl, q.wr = L.shape[0], R.shape[0]
+        q.wm = W1.shape[1] if nsite == 2 else L.shape[0]
+        q.L, q.R, q.theta, q.out = ptr(L), ptr(R), ptr(theta), ptr(out)
+        q.W1, q.W2 = ptr(W1), ptr(W2)
+    rc = _lib.load().apply_heff_batched(ctx.handle, _dtype_code(problems[0][2]), len(problems), descs)
+    _check(ctx.handle, rc)
+    return outs
+
+
 def apply_heff_adjoint(ctx: Context, L, R, theta, ybar, W1=None, W2=None, need=("theta", "L", "R", "W")):
     """Gradients of Re<ybar, H_eff theta> w.r.t. theta, L, R and (one-site) W.
 

@@ -285,6 +285,86 @@ int apply_heff(tdvp_ctx ctx, int nsite, tdvp_dtype dtype, int chil, int chir, in
     });
 }
 
+int apply_heff_batched(tdvp_ctx ctx, tdvp_dtype dtype, int n, const tdvp_heff_desc* descs) {
+    if (!ctx) return TDVP_E_ARG;
+    return guarded(ctx, [&] {
+        const Dt dt = to_dt(dtype);
+        TDVP_REQUIRE(n >= 0 && (n == 0 || descs), TDVP_E_ARG, "apply_heff_batched: null descriptor array");
+        if (n == 0) return;
+        const bool fp64 = dt == Dt::C128;
+        const size_t esz = elem_bytes(dt);
+        std::vector<Mop> mops(n);
+        std::vector<int64_t> o1(n), o3(n);
+        int64_t t1 = 0, t3 = 0;
+        for (int i = 0; i < n; ++i) {
+            const tdvp_heff_desc& q = descs[i];
+            TDVP_REQUIRE(q.nsite >= 0 && q.nsite <= 2, TDVP_E_ARG, "apply_heff_batched: nsite must be 0, 1 or 2");
+            TDVP_REQUIRE(q.chil >= 1 && q.chir >= 1 && q.wl >= 1 && q.wr >= 1, TDVP_E_SHAPE,
+                         "apply_heff_batched: dimensions must be positive");
+            TDVP_REQUIRE(q.nsite == 0 || q.d >= 1, TDVP_E_SHAPE, "apply_heff_batched: d must be positive");
+            TDVP_REQUIRE(q.nsite != 2 || q.wm >= 1, TDVP_E_SHAPE, "apply_heff_batched: wm must be positive");
+            TDVP_REQUIRE(q.nsite != 0 || q.wl == q.wr, TDVP_E_SHAPE, "apply_heff_batched: zero-site needs wl == wr");
+            TDVP_REQUIRE(q.L && q.R && q.theta && q.out, TDVP_E_ARG, "apply_heff_batched: null pointer");
+            TDVP_REQUIRE(q.nsite < 1 || q.W1, TDVP_E_ARG, "apply_heff_batched: W1 is null");
+            TDVP_REQUIRE(q.nsite < 2 || q.W2, TDVP_E_ARG, "apply_heff_batched: W2 is null");
+            for (int k = 0; k < n; ++k)
+                TDVP_REQUIRE(q.out != descs[k].theta && q.out != descs[k].L && q.out != descs[k].R &&
+                                 (k == i || q.out != descs[k].out),
+                             TDVP_E_ARG, "apply_heff_batched: an output aliases an input or another output");
+            const int kind = q.nsite == 0 ? 0 : (q.nsite == 1 ? 1 : 2);
+            mop_make(ctx, mops[i], kind, q.W1, q.W2, dt, q.wl, q.nsite == 2 ? q.wm : q.wl, q.wr, q.d, fp64, true);
+            const int64_t D = q.nsite == 0 ? 1 : pow_int(q.d, q.nsite);
+            o1[i] = t1;
+            o3[i] = t3;
+            t1 += (int64_t)q.wl * q.chil * D * q.chir;
+            t3 += (int64_t)q.wr * q.chil * D * q.chir;
+        }
+        char* T1 = static_cast<char*>(ctx->workspace("heffb_T1", esz * (size_t)t1));
+        char* T3 = static_cast<char*>(ctx->workspace("heffb_T3", esz * (size_t)t3));
+        std::vector<GemmDesc> ga(n), gb(n);
+        std::vector<WStageDesc> ws(n);
+        for (int i = 0; i < n; ++i) {
+            const tdvp_heff_desc& q = descs[i];
+            const int64_t D = q.nsite == 0 ? 1 : pow_int(q.d, q.nsite);
+            const int64_t chil = q.chil, chir = q.chir;
+            GemmDesc& g1 = ga[i];  // T1[(k a')][(s b)] = L x
+            g1.M = (int)(q.wl * chil);
+            g1.N = (int)(D * chir);
+            g1.K = (int)chil;
+            g1.A = op(q.L, dt, chil, true);
+            g1.B = op(q.theta, dt, D * chir, false);
+            g1.C = T1 + esz * o1[i];
+            g1.cdt = dt;
+            g1.ldc = D * chir;
+            WStageDesc& w = ws[i];
+            w.in = T1 + esz * o1[i]; w.in_dt = dt; w.out = T3 + esz * o3[i]; w.out_dt = dt;
+            w.P = (int)chil; w.Q = (int)chir; w.D = (int)D; w.w_in = q.wl; w.w_out = q.wr;
+            w.ik = chil * D * chir; w.is = chir; w.ip = D * chir;
+            w.on = chir; w.os = q.wr * chir; w.op = D * q.wr * chir;
+            w.row_ptr = mops[i].row_ptr; w.col = mops[i].col; w.val = mops[i].val; w.fp64 = fp64;
+            GemmDesc& g2 = gb[i];  // y[(a' s')][b'] = T3 R
+            g2.M = (int)(chil * D);
+            g2.N = (int)chir;
+            g2.K = (int)(q.wr * chir);
+            g2.A = op(T3 + esz * o3[i], dt, q.wr * chir, true);
+            g2.B = op(q.R, dt, chir, false);
+            g2.C = q.out;
+            g2.cdt = dt;
+            g2.ldc = chir;
+        }
+        GroupedGemm A, B;
+        GroupedWStage W;
+        grouped_gemm_plan(ctx, ga, fp64, fp64 ? 4 : 3, A);
+        grouped_wstage_plan(ctx, ws, W);
+        grouped_gemm_plan(ctx, gb, fp64, fp64 ? 4 : 3, B);
+        grouped_gemm_run(ctx, A);
+        grouped_wstage_run(ctx, W);
+        grouped_gemm_run(ctx, B);
+        // the plans' tables and the operators are freed on return
+        TDVP_CHECK_HIP(hipStreamSynchronize(ctx->stream));
+    });
+}
+
 int env_update(tdvp_ctx ctx, int dir, tdvp_dtype dtype, int chil, int chir, int d, int wl, int wr,
                const void* env_in, const void* A, const void* W, void* env_out) {
     if (!ctx) return TDVP_E_ARG;

@@ -202,3 +202,21 @@ def test_every_gemm_tile_matches_oracle(ctx, dt, monkeypatch):
             ref = oracle_heff(case[0], beta, W1, W2, gamma, theta)
             y = run_gpu(ctx, dt, beta, W1, W2, gamma, theta)
             assert rel_err(y, ref) <= TOL[dt], (cfg, case)
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_apply_heff_batched_matches_oracle(ctx, dt):
+    """Ragged batch mixing two-, one- and zero-site problems, one grouped launch per stage."""
+    import paper_1912_06127_amd as pkg
+    cases = [(2, 37, 45, 2, 5, 4, 6), (2, 150, 130, 2, 7, 7, 7), (1, 200, 170, 2, 11, 0, 9), (2, 1, 1, 2, 1, 1, 1),
+             (0, 96, 96, 2, 8, 0, 8), (1, 5, 7, 3, 4, 0, 3), (2, 64, 64, 2, 14, 14, 14)]
+    probs, refs = [], []
+    for i, cs in enumerate(cases):
+        beta, W1, W2, gamma, theta = random_case(900 + i, *cs)
+        refs.append(oracle_heff(cs[0], beta, W1, W2, gamma, theta))
+        probs.append((_t(L_from_beta(beta), dt), _t(R_from_gamma(gamma), dt), _t(theta, dt),
+                      None if W1 is None else _t(W1, dt), None if W2 is None else _t(W2, dt)))
+    print(f"apply_heff_batched {len(cases)} problems {dt}", flush=True)
+    outs = pkg.apply_heff_batched(ctx, probs)
+    for cs, y, ref in zip(cases, outs, refs):
+        assert rel_err(_h(y), ref) <= TOL[dt], cs
