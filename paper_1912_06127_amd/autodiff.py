@@ -35,16 +35,21 @@ class ApplyHeff(torch.autograd.Function):
         cR = R.to(compute).contiguous()
         cW = None if W is None else W.to(compute).contiguous()
         y = api.apply_heff(lib_ctx, cL, cR, cx, cW)
-        ctx_.save_for_backward(cx, cL, cW if cW is not None else torch.empty(0, device=x.device), cR)
+        # the originals are saved (shared by every matvec of a Krylov run),
+        # not the converted copies
+        ctx_.save_for_backward(x, L, W if W is not None else torch.empty(0, device=x.device), R)
         ctx_.lib_ctx = lib_ctx
+        ctx_.compute = compute
         ctx_.has_w = W is not None
         ctx_.dtypes = (x.dtype, L.dtype, None if W is None else W.dtype, R.dtype)
         return y.to(x.dtype)
 
     @staticmethod
     def backward(ctx_, ybar):
-        cx, cL, cW, cR = ctx_.saved_tensors
-        W = cW if ctx_.has_w else None
+        x, L, W0, R = ctx_.saved_tensors
+        cdt = ctx_.compute
+        cx, cL, cR = (t.to(cdt).contiguous() for t in (x, L, R))
+        W = W0.to(cdt).contiguous() if ctx_.has_w else None
         need = []
         if ctx_.needs_input_grad[2]:
             need.append("theta")
@@ -71,6 +76,33 @@ def env_right(R, A, W):
     return torch.einsum("asb,klts,lbc,ptc->kap", A, W, R, A.conj())
 
 
+class Project(torch.autograd.Function):
+    """w - sum_i V_i (V_i^H w) for 1-D vectors V_i (one Gram-Schmidt pass).
+
+    Saves references to its inputs only, so a Krylov run keeps O(k) vectors
+    for the backward pass instead of a stacked copy of the basis per step.
+    Backward (gradients in the convention g = dl/dRe + i dl/dIm):
+    g_w = G - sum_i V_i (V_i^H G), g_{V_i} = -G conj(V_i^H w) - w conj(V_i^H G).
+    """
+
+    @staticmethod
+    def forward(ctx_, w, *V):
+        Vm = torch.stack(V)
+        out = w - Vm.T @ (Vm.conj() @ w)
+        ctx_.save_for_backward(w, *V)
+        return out
+
+    @staticmethod
+    def backward(ctx_, G):
+        w, *V = ctx_.saved_tensors
+        Vm = torch.stack(V)
+        c = Vm.conj() @ w
+        a = Vm.conj() @ G
+        gw = G - Vm.T @ a
+        gV = -(c.conj()[:, None] * G[None, :]) - (a.conj()[:, None] * w[None, :])
+        return (gw, *gV.unbind(0))
+
+
 def expm_lanczos(op, x, tau, kmax=40, tol=1e-13, extra=5):
     """exp(-i tau H) x by Lanczos with two Gram-Schmidt passes (differentiable).
 
@@ -90,9 +122,8 @@ def expm_lanczos(op, x, tau, kmax=40, tol=1e-13, extra=5):
         w = w - a * V[k]
         if k > 0:
             w = w - betas[-1] * V[k - 1]
-        Vm = torch.stack(V)
         for _ in range(2):
-            w = w - Vm.T @ (Vm.conj() @ w)
+            w = Project.apply(w, *V)
         b = torch.linalg.vector_norm(w)
         alphas.append(a)
         n = len(alphas)

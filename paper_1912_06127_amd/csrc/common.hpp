@@ -230,6 +230,12 @@ void reset_flag(tdvp_ctx ctx, int* flag);
 // reduced into out[nv] (complex) = sum conj(V[j][i]) w[i].
 void vdot_multi(tdvp_ctx ctx, const double2* V, int64_t vstride, int nv, const double2* w,
                 int64_t n, double2* out);
+// One Lanczos step on a short vector in a single workgroup (n <= kSmallLanczos,
+// k < 64): w <- w - alpha v_k - beta_prev v_{k-1} with alpha = Re<v_k, w>, two
+// Gram-Schmidt passes against V[0..k], out[0] = alpha, out[1] = ||w||^2 (device
+// doubles), V[k+1] = w / ||w|| (zero if w vanishes).  V holds n-element rows.
+constexpr int64_t kSmallLanczos = 8192;
+void lanczos_small_step(double2* V, int64_t n, int k, double2* w, double beta_prev, double* out, hipStream_t s);
 // w -= sum_j coef[j] V[j]   (coef device complex[nv])
 void axpy_multi(const double2* V, int64_t vstride, int nv, const double2* coef, double2* w,
                 int64_t n, hipStream_t s);

@@ -36,8 +36,11 @@ __device__ inline void st(void* p, int c128, int64_t i, T re, T im) {
 // ---------------------------------------------------------------- MPO stage
 // One thread per grid point (p, q).  The w_in*D input values of the point
 // are staged in a thread-private LDS column, then each output row is a
-// short sparse dot product with the MPO entries (read with uniform
-// addresses).  Loads and stores are coalesced along q.
+// short sparse dot product with the MPO entries.  The sparse operator (a few
+// hundred entries for the MPOs used here) is first copied into LDS by the
+// whole block, so the inner loop reads broadcast LDS values instead of a
+// chain of dependent global loads; larger operators are read from global
+// memory.  Loads and stores are coalesced along q.
 struct WParams {
     const void* in; int in128;
     void* out; int out128;
@@ -48,25 +51,50 @@ struct WParams {
     const void* val;
 };
 
-// Grid point (p, q) of one MPO stage; xin is this thread's LDS column.
+constexpr int kWNnzCap = 512;  // operator entries staged in LDS
+constexpr int kWRowCap = 512;  // operator rows staged in LDS
+
+// bytes of the staged operator, rounded up so that the input columns behind
+// it stay 16-byte aligned
 template <typename T>
-__device__ __forceinline__ void wstage_point(const WParams& w, int p, int q, typename cplx<T>::t* xin, int nt) {
+constexpr size_t wstage_op_bytes() {
+    return ((size_t)kWNnzCap * (sizeof(typename cplx<T>::t) + sizeof(int)) + (size_t)(kWRowCap + 1) * sizeof(int) + 15) /
+           16 * 16;
+}
+
+// A block handles kWPts consecutive q of one p with kWSub waves: every wave
+// loads every kWSub-th input row of the 64 points (coalesced along q) into
+// the shared [nin][kWPts] tile, then computes every kWSub-th output row.
+// Sharing each point over four waves keeps the LDS per thread small enough
+// for several blocks per CU, so many loads are in flight.
+constexpr int kWSub = 4;
+constexpr int kWPts = 64;
+constexpr int kWThreads = kWSub * kWPts;
+
+template <typename T>
+__device__ __forceinline__ void wstage_tile(const WParams& w, int p, int q0, typename cplx<T>::t* xin, const int* rp,
+                                            const int* cl, const typename cplx<T>::t* vl) {
     using C = typename cplx<T>::t;
+    const int lane = threadIdx.x & 63, sub = threadIdx.x >> 6;
+    const int q = q0 + lane;
+    const bool live = q < w.Q;
     const int64_t pin = (int64_t)p * w.ip + q;
-    for (int c = 0; c < w.nin; ++c) {
+#pragma unroll 4
+    for (int c = sub; c < w.nin; c += kWSub) {
         const int k = c / w.D, s = c % w.D;
-        T re, im;
-        ld<T>(w.in, w.in128, pin + k * w.ik + s * w.is, re, im);
-        xin[c * nt] = C{re, im};
+        T re = 0, im = 0;
+        if (live) ld<T>(w.in, w.in128, pin + k * w.ik + s * w.is, re, im);
+        xin[c * kWPts + lane] = C{re, im};
     }
-    const C* val = reinterpret_cast<const C*>(w.val);
+    __syncthreads();
+    if (!live) return;  // no barrier below
     const int64_t pout = (int64_t)p * w.op + q;
-    for (int r = 0; r < w.nout; ++r) {
+    for (int r = sub; r < w.nout; r += kWSub) {
         T ar = 0, ai = 0;
-        const int e1 = w.row_ptr[r + 1];
-        for (int e = w.row_ptr[r]; e < e1; ++e) {
-            const C v = val[e];
-            const C x = xin[w.col[e] * nt];
+        const int e1 = rp[r + 1];
+        for (int e = rp[r]; e < e1; ++e) {
+            const C v = vl[e];
+            const C x = xin[cl[e] * kWPts + lane];
             ar += v.x * x.x - v.y * x.y;
             ai += v.x * x.y + v.y * x.x;
         }
@@ -75,14 +103,42 @@ __device__ __forceinline__ void wstage_point(const WParams& w, int p, int q, typ
     }
 }
 
+// Copies the operator into LDS when it fits (block-uniform decision) and
+// returns the pointers the tile should read.  Contains a barrier: every
+// thread of the block must call it.
 template <typename T>
-__global__ void wstage_kernel(WParams w) {
+__device__ __forceinline__ void wstage_stage_op(const WParams& w, unsigned char* smem, const int*& rp, const int*& cl,
+                                                const typename cplx<T>::t*& vl) {
+    using C = typename cplx<T>::t;
+    const int nnz = w.row_ptr[w.nout];
+    C* sv = reinterpret_cast<C*>(smem);
+    int* sc = reinterpret_cast<int*>(sv + kWNnzCap);
+    int* sr = sc + kWNnzCap;
+    const bool fits = nnz <= kWNnzCap && w.nout <= kWRowCap;
+    if (fits) {
+        const C* gv = reinterpret_cast<const C*>(w.val);
+        for (int i = threadIdx.x; i < nnz; i += blockDim.x) {
+            sv[i] = gv[i];
+            sc[i] = w.col[i];
+        }
+        for (int i = threadIdx.x; i <= w.nout; i += blockDim.x) sr[i] = w.row_ptr[i];
+    }
+    __syncthreads();
+    rp = fits ? sr : w.row_ptr;
+    cl = fits ? sc : w.col;
+    vl = fits ? sv : reinterpret_cast<const C*>(w.val);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kWThreads) wstage_kernel(WParams w) {
     using C = typename cplx<T>::t;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    C* xin = reinterpret_cast<C*>(smem_raw);  // [nin][blockDim.x]
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= w.Q) return;  // no barrier: each thread uses only its column
-    wstage_point<T>(w, blockIdx.y, q, xin + threadIdx.x, blockDim.x);
+    const int* rp;
+    const int* cl;
+    const C* vl;
+    wstage_stage_op<T>(w, smem_raw, rp, cl, vl);
+    C* xin = reinterpret_cast<C*>(smem_raw + wstage_op_bytes<T>());  // [nin][kWPts]
+    wstage_tile<T>(w, blockIdx.y, blockIdx.x * kWPts, xin, rp, cl, vl);
 }
 
 // Grouped MPO stage: problem g owns blocks [blk_begin, blk_begin + P*qblocks).
@@ -93,10 +149,9 @@ struct GWProblem {
 };
 
 template <typename T>
-__global__ void wstage_grouped_kernel(const GWProblem* __restrict__ probs, int nprob) {
+__global__ void __launch_bounds__(kWThreads) wstage_grouped_kernel(const GWProblem* __restrict__ probs, int nprob) {
     using C = typename cplx<T>::t;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    C* xin = reinterpret_cast<C*>(smem_raw);
     const int64_t b = blockIdx.x;
     int lo = 0, hi = nprob - 1;
     while (lo < hi) {
@@ -107,10 +162,115 @@ __global__ void wstage_grouped_kernel(const GWProblem* __restrict__ probs, int n
     const int qb = probs[lo].qblocks;
     const int64_t local = b - probs[lo].blk_begin;
     const int p = (int)(local / qb);
-    const int q = (int)(local % qb) * blockDim.x + threadIdx.x;
+    const int q0 = (int)(local % qb) * kWPts;
     const WParams w = probs[lo].w;
-    if (q >= w.Q) return;
-    wstage_point<T>(w, p, q, xin + threadIdx.x, blockDim.x);
+    const int* rp;
+    const int* cl;
+    const C* vl;
+    wstage_stage_op<T>(w, smem_raw, rp, cl, vl);  // the whole block shares problem lo
+    C* xin = reinterpret_cast<C*>(smem_raw + wstage_op_bytes<T>());
+    wstage_tile<T>(w, p, q0, xin, rp, cl, vl);
+}
+
+// ------------------------------------------------------- small Lanczos step
+// One Lanczos step for a short vector (n <= kSmallLanczos) in one workgroup:
+// alpha = Re<v_k, w>, w -= alpha v_k + beta v_{k-1}, two classical
+// Gram-Schmidt passes against v_0..v_k, then ||w||^2 and v_{k+1} = w/||w||.
+// Replaces about a dozen launches of the general path when every launch
+// costs more than the arithmetic (small bond dimensions).
+constexpr int kSmallThreads = 1024;
+constexpr int kSmallWaves = kSmallThreads / 64;
+constexpr int kSmallMaxK = 64;
+
+__device__ inline double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__global__ void __launch_bounds__(kSmallThreads) lanczos_small_kernel(double2* V, int64_t n, int k, double2* w,
+                                                                      double beta_prev, double* out) {
+    __shared__ double sre[kSmallMaxK + 1][kSmallWaves], sim[kSmallMaxK + 1][kSmallWaves];
+    __shared__ double coef_re[kSmallMaxK + 1], coef_im[kSmallMaxK + 1];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const double2* vk = V + (int64_t)k * n;
+    // alpha_k = Re <v_k, w>
+    double a = 0.0;
+    for (int64_t e = tid; e < n; e += kSmallThreads) a += vk[e].x * w[e].x + vk[e].y * w[e].y;
+    a = wave_sum(a);
+    if (lane == 0) sre[0][wave] = a;
+    __syncthreads();
+    if (tid == 0) {
+        double t = 0.0;
+        for (int i = 0; i < kSmallWaves; ++i) t += sre[0][i];
+        coef_re[0] = t;
+    }
+    __syncthreads();
+    const double alpha = coef_re[0];
+    for (int64_t e = tid; e < n; e += kSmallThreads) {
+        double2 x = w[e];
+        x.x -= alpha * vk[e].x;
+        x.y -= alpha * vk[e].y;
+        if (k > 0) {
+            const double2 u = V[(int64_t)(k - 1) * n + e];
+            x.x -= beta_prev * u.x;
+            x.y -= beta_prev * u.y;
+        }
+        w[e] = x;
+    }
+    __syncthreads();
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int j = 0; j <= k; ++j) {  // c_j = <v_j, w>
+            const double2* v = V + (int64_t)j * n;
+            double re = 0.0, im = 0.0;
+            for (int64_t e = tid; e < n; e += kSmallThreads) {
+                re += v[e].x * w[e].x + v[e].y * w[e].y;
+                im += v[e].x * w[e].y - v[e].y * w[e].x;
+            }
+            re = wave_sum(re);
+            im = wave_sum(im);
+            if (lane == 0) {
+                sre[j][wave] = re;
+                sim[j][wave] = im;
+            }
+        }
+        __syncthreads();
+        if (tid <= k) {
+            double re = 0.0, im = 0.0;
+            for (int i = 0; i < kSmallWaves; ++i) {
+                re += sre[tid][i];
+                im += sim[tid][i];
+            }
+            coef_re[tid] = re;
+            coef_im[tid] = im;
+        }
+        __syncthreads();
+        for (int64_t e = tid; e < n; e += kSmallThreads) {  // w -= sum_j c_j v_j
+            double2 x = w[e];
+            for (int j = 0; j <= k; ++j) {
+                const double2 v = V[(int64_t)j * n + e];
+                x.x -= coef_re[j] * v.x - coef_im[j] * v.y;
+                x.y -= coef_re[j] * v.y + coef_im[j] * v.x;
+            }
+            w[e] = x;
+        }
+        __syncthreads();
+    }
+    double nn = 0.0;
+    for (int64_t e = tid; e < n; e += kSmallThreads) nn += w[e].x * w[e].x + w[e].y * w[e].y;
+    nn = wave_sum(nn);
+    if (lane == 0) sre[0][wave] = nn;
+    __syncthreads();
+    if (tid == 0) {
+        double t = 0.0;
+        for (int i = 0; i < kSmallWaves; ++i) t += sre[0][i];
+        coef_re[0] = t;
+        out[0] = alpha;
+        out[1] = t;
+    }
+    __syncthreads();
+    const double inv = coef_re[0] > 0.0 ? 1.0 / sqrt(coef_re[0]) : 0.0;
+    double2* vn = V + (int64_t)(k + 1) * n;
+    for (int64_t e = tid; e < n; e += kSmallThreads) vn[e] = make_double2(w[e].x * inv, w[e].y * inv);
 }
 
 // ------------------------------------------------------------ FP64 vectors
@@ -441,12 +601,11 @@ void wstage(tdvp_ctx ctx, const WStageDesc& d) {
     w.col = d.col;
     w.val = d.val;
     const size_t esz = d.fp64 ? sizeof(double2) : sizeof(float2);
-    int nt = 256;
-    while (nt > 64 && (size_t)nt * w.nin * esz > 48 * 1024) nt /= 2;
-    const size_t shmem = (size_t)nt * w.nin * esz;
+    const size_t shmem = (size_t)kWPts * w.nin * esz + (d.fp64 ? wstage_op_bytes<double>() : wstage_op_bytes<float>());
     TDVP_REQUIRE(shmem <= 160 * 1024, TDVP_E_SHAPE, "wstage: MPO bond dimension too large");
-    TDVP_REQUIRE(d.P <= 65535 * 1024, TDVP_E_SHAPE, "wstage: grid too large");
-    dim3 grid((d.Q + nt - 1) / nt, d.P);
+    TDVP_REQUIRE(d.P <= 65535, TDVP_E_SHAPE, "wstage: grid too large");
+    const int nt = kWThreads;
+    dim3 grid((d.Q + kWPts - 1) / kWPts, d.P);
     const double pts = (double)d.P * d.Q;
     ProfScope prof(ctx, d.fp64 ? "wstage_f64" : "wstage_f32", 0.0,
                    pts * (w.nin * elem_bytes(d.in_dt) + w.nout * elem_bytes(d.out_dt)));
@@ -469,10 +628,9 @@ void grouped_wstage_plan(tdvp_ctx ctx, const std::vector<WStageDesc>& ds, Groupe
         nin_max = std::max(nin_max, d.w_in * d.D);
     }
     const size_t esz = out.fp64 ? sizeof(double2) : sizeof(float2);
-    int nt = 256;
-    while (nt > 64 && (size_t)nt * nin_max * esz > 48 * 1024) nt /= 2;
-    out.nt = nt;
-    out.shmem = (size_t)nt * nin_max * esz;
+    const int nt = kWPts;  // points per block (kWThreads threads)
+    out.nt = kWThreads;
+    out.shmem = (size_t)kWPts * nin_max * esz + (out.fp64 ? wstage_op_bytes<double>() : wstage_op_bytes<float>());
     TDVP_REQUIRE(out.shmem <= 160 * 1024, TDVP_E_SHAPE, "wstage: MPO bond dimension too large");
     int64_t blocks = 0;
     for (const auto& d : ds) {
@@ -520,6 +678,12 @@ void grouped_wstage_run(tdvp_ctx ctx, const GroupedWStage& g) {
     else
         hipLaunchKernelGGL(wstage_grouped_kernel<float>, dim3((unsigned)g.blocks), dim3(g.nt), g.shmem, ctx->stream,
                            pr, g.nprob);
+    TDVP_CHECK_HIP(hipGetLastError());
+}
+
+void lanczos_small_step(double2* V, int64_t n, int k, double2* w, double beta_prev, double* out, hipStream_t s) {
+    TDVP_REQUIRE(n <= kSmallLanczos && k < kSmallMaxK, TDVP_E_ARG, "lanczos_small_step: vector or basis too large");
+    hipLaunchKernelGGL(lanczos_small_kernel, dim3(1), dim3(kSmallThreads), 0, s, V, n, k, w, beta_prev, out);
     TDVP_CHECK_HIP(hipGetLastError());
 }
 

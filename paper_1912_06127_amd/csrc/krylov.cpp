@@ -79,22 +79,34 @@ KrylovInfo expm_krylov(tdvp_ctx ctx, const MatVec& op, double2* theta, int64_t n
     std::vector<double> alphas, betas, evals, evecs;
     std::vector<double2> y;
     int k_used = 0;
+    const bool small = n <= kSmallLanczos && kmax < 64;
     for (int k = 0; k < kmax; ++k) {
         double2* vk = V + (size_t)k * n;
         op(vk, w);
         ++info.matvecs;
-        vdot_multi(ctx, vk, 0, 1, w, n, scal);  // alpha_k = <v_k, H v_k>
-        lanczos_3term(w, vk, k > 0 ? V + (size_t)(k - 1) * n : nullptr, scal,
-                      k > 0 ? betas.back() : 0.0, n, s);
-        for (int pass = 0; pass < 2; ++pass) {  // classical Gram-Schmidt, twice
-            vdot_multi(ctx, V, n, k + 1, w, n, coef);
-            axpy_multi(V, n, k + 1, coef, w, n, s);
+        double a, b;
+        if (small) {  // the whole recurrence step in one workgroup; writes v_{k+1} too
+            double* sc = reinterpret_cast<double*>(scal);
+            lanczos_small_step(V, n, k, w, k > 0 ? betas.back() : 0.0, sc, s);
+            double hs[2];
+            TDVP_CHECK_HIP(hipMemcpyAsync(hs, sc, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+            TDVP_CHECK_HIP(hipStreamSynchronize(s));
+            a = hs[0];
+            b = std::sqrt(std::max(0.0, hs[1]));
+        } else {
+            vdot_multi(ctx, vk, 0, 1, w, n, scal);  // alpha_k = <v_k, H v_k>
+            lanczos_3term(w, vk, k > 0 ? V + (size_t)(k - 1) * n : nullptr, scal,
+                          k > 0 ? betas.back() : 0.0, n, s);
+            for (int pass = 0; pass < 2; ++pass) {  // classical Gram-Schmidt, twice
+                vdot_multi(ctx, V, n, k + 1, w, n, coef);
+                axpy_multi(V, n, k + 1, coef, w, n, s);
+            }
+            vdot_multi(ctx, w, 0, 1, w, n, scal + 1);
+            TDVP_CHECK_HIP(hipMemcpyAsync(host, scal, 2 * sizeof(double2), hipMemcpyDeviceToHost, s));
+            TDVP_CHECK_HIP(hipStreamSynchronize(s));
+            a = host[0].x;
+            b = std::sqrt(std::max(0.0, host[1].x));
         }
-        vdot_multi(ctx, w, 0, 1, w, n, scal + 1);
-        TDVP_CHECK_HIP(hipMemcpyAsync(host, scal, 2 * sizeof(double2), hipMemcpyDeviceToHost, s));
-        TDVP_CHECK_HIP(hipStreamSynchronize(s));
-        const double a = host[0].x;
-        const double b = std::sqrt(std::max(0.0, host[1].x));
         TDVP_REQUIRE(std::isfinite(a) && std::isfinite(b), TDVP_E_NUMERIC,
                      "Krylov: non-finite value in H_eff application");
         alphas.push_back(a);
@@ -121,7 +133,7 @@ KrylovInfo expm_krylov(tdvp_ctx ctx, const MatVec& op, double2* theta, int64_t n
             break;
         }
         betas.push_back(b);
-        scale_copy(V + (size_t)(k + 1) * n, w, 1.0 / b, n, s);
+        if (!small) scale_copy(V + (size_t)(k + 1) * n, w, 1.0 / b, n, s);
     }
     for (auto& c : y) {
         c.x *= beta0;
