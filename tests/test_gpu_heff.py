@@ -220,3 +220,47 @@ def test_apply_heff_batched_matches_oracle(ctx, dt):
     outs = pkg.apply_heff_batched(ctx, probs)
     for cs, y, ref in zip(cases, outs, refs):
         assert rel_err(_h(y), ref) <= TOL[dt], cs
+
+
+def test_apply_heff_batched_full_segment_shapes_sampled(ctx):
+    """The 32 two-site instances of the first sweep phase of the N = 201
+    segment workload (real bond dimensions up to ~1000, w = 14), complex64,
+    one grouped launch per stage; sampled rows of four instances checked one by
+    one against the oracle."""
+    import torch
+    import paper_1912_06127_amd as pkg
+    p = wl.XY_N201
+    chi = wl.segment_bond_profile(p["segments"], 2, p["chi_lo"], p["chi_hi"], p["seed_chi"])
+    c, lam, _ = ompo.fit_exponentials(1.0 / np.arange(1, 201) ** 1.5, 6)
+    W = ompo.mpo_exponentials(6, c, lam, [(0.5, spin.SX, spin.SX), (0.5, spin.SY, spin.SY)])[2]
+    w = W.shape[0]
+    bounds = wl.segment_bounds(p["segments"])
+    sites = [max(lo, 1) for lo, _ in bounds]  # first pair of every segment
+    rng = np.random.default_rng(2011)
+    probs, host = [], []
+    Wd = _t(W, "c64")
+    for j in sites:
+        chil, chir = chi[j], chi[j + 2]
+        print(f"batched full-shape instance site {j}: {chil} x {chir}", flush=True)
+        Lh = torch.randn((w, chil, chil), dtype=torch.complex64, device="cuda") / np.sqrt(chil)
+        Rh = torch.randn((w, chir, chir), dtype=torch.complex64, device="cuda") / np.sqrt(chir)
+        th = torch.randn((chil, 2, 2, chir), dtype=torch.complex64, device="cuda")
+        probs.append((Lh, Rh, th, Wd, Wd))
+        host.append(j)
+    outs = pkg.apply_heff_batched(ctx, probs)
+    ctx.sync()
+    for i in rng.choice(len(sites), 4, replace=False):
+        Lh, Rh, th, _, _ = probs[i]
+        L = _h(Lh)
+        R = _h(Rh)
+        theta = _h(th)
+        y = _h(outs[i])
+        beta = np.transpose(L, (1, 0, 2))
+        gamma = np.transpose(R, (2, 0, 1))
+        num = den = 0.0
+        for a1, b1 in zip(rng.integers(0, L.shape[1], 2), rng.integers(0, R.shape[1], 2)):
+            ref = oheff.apply_heff2(beta[[a1]], W, W, gamma[[b1]], theta)[0, :, :, 0]
+            num += np.linalg.norm(y[a1, :, :, b1] - ref) ** 2
+            den += np.linalg.norm(ref) ** 2
+        assert np.sqrt(num / den) <= TOL["c64"], i
+        assert np.all(np.isfinite(y))
