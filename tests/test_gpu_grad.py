@@ -117,7 +117,14 @@ def directions(c, lam, N):
     dy[0, m - 1] = spin.SY
     dz = np.zeros_like(dJ)
     dz[0, m - 1] = spin.SZ
-    return {"J": dJ, "h": dh, "onsite_y": dy, "onsite_z": dz}
+    dirs = {"J": dJ, "h": dh, "onsite_y": dy, "onsite_z": dz}
+    # random directions with every block W[k][l] Hermitian: each virtual path is
+    # then a Kronecker product of Hermitian matrices, so H stays Hermitian
+    rng = np.random.default_rng(2024)
+    for i in range(2):
+        G = wl.cgauss(rng, (m, m, 2, 2))
+        dirs[f"random_hermitian_{i}"] = 0.02 * (G + np.conj(np.transpose(G, (0, 1, 3, 2))))
+    return dirs
 
 
 @pytest.mark.parametrize("compute", ["c128", "c64"])
