@@ -24,7 +24,6 @@ from __future__ import annotations
 
 import numpy as np
 
-from .spin import ID2
 
 
 def _boundaries(Wb: np.ndarray, N: int):
@@ -47,17 +46,18 @@ def mpo_exact(N: int, f, pairs, onsite=None, h: float = 0.0):
     nH = len(pairs)
     R = N - 1
     m = nH * R + 2
-    d = 2
+    d = np.asarray(pairs[0][1]).shape[0]
+    I = np.eye(d, dtype=np.complex128)
     Wb = np.zeros((m, m, d, d), dtype=np.complex128)
-    Wb[0, 0] = ID2
-    Wb[m - 1, m - 1] = ID2
+    Wb[0, 0] = I
+    Wb[m - 1, m - 1] = I
     if onsite is not None:
         Wb[0, m - 1] = h * onsite
     for a, (g, A, B) in enumerate(pairs):
         s = lambda r: 1 + a * R + (r - 1)  # state "A_a placed r-1 sites ago"
         Wb[0, s(1)] = A
         for r in range(1, R):
-            Wb[s(r), s(r + 1)] = ID2
+            Wb[s(r), s(r + 1)] = I
         for r in range(1, R + 1):
             fr = f(r) if callable(f) else f[r]
             Wb[s(r), m - 1] = g * fr * B
@@ -76,16 +76,18 @@ def mpo_exponentials(N: int, c, lam, pairs, onsite=None, h: float = 0.0):
     K = len(c)
     nH = len(pairs)
     m = nH * K + 2
-    Wb = np.zeros((m, m, 2, 2), dtype=np.complex128)
-    Wb[0, 0] = ID2
-    Wb[m - 1, m - 1] = ID2
+    d = np.asarray(pairs[0][1]).shape[0]
+    I = np.eye(d, dtype=np.complex128)
+    Wb = np.zeros((m, m, d, d), dtype=np.complex128)
+    Wb[0, 0] = I
+    Wb[m - 1, m - 1] = I
     if onsite is not None:
         Wb[0, m - 1] = h * onsite
     for a, (g, A, B) in enumerate(pairs):
         for k in range(K):
             s = 1 + a * K + k
             Wb[0, s] = A
-            Wb[s, s] = lam[k] * ID2
+            Wb[s, s] = lam[k] * I
             Wb[s, m - 1] = g * c[k] * lam[k] * B
     return _boundaries(Wb, N)
 

@@ -33,7 +33,8 @@ def longrange_hamiltonian(N: int, f, pairs, onsite=None, h: float = 0.0) -> np.n
     coupling (a callable or an array indexed by r).  Built by Kronecker
     products, independently of any MPO.
     """
-    dim = 2 ** N
+    d = np.asarray(pairs[0][1]).shape[0] if pairs else np.asarray(onsite).shape[0]
+    dim = d ** N
     H = sp.csr_matrix((dim, dim), dtype=np.complex128)
     ops_cache = {}
 

@@ -322,3 +322,22 @@ def test_tdvp2_truncated_norm_is_one_minus_wtotal():
     assert st.stats.w_total > 0
     assert abs(mps.norm2(st.T) - (1.0 - st.stats.w_total)) < 1e-12
     assert max(A.shape[2] for A in st.T) <= 6
+
+
+def test_spin_one_mpo_equals_kronecker_hamiltonian():
+    # local dimension d = 3: the MPO builders and the Kronecker Hamiltonian agree
+    Sz = np.diag([1.0, 0.0, -1.0]).astype(np.complex128)
+    Sx = (np.array([[0, 1, 0], [1, 0, 1], [0, 1, 0]]) / np.sqrt(2)).astype(np.complex128)
+    Sy = (np.array([[0, -1j, 0], [1j, 0, -1j], [0, 1j, 0]]) / np.sqrt(2)).astype(np.complex128)
+    pairs = [(1.0, Sx, Sx), (1.0, Sy, Sy), (1.0, Sz, Sz)]
+    N = 5
+    f = lambda r: 1.0 / r ** 2
+    Ws = mpo.mpo_exact(N, f, pairs, Sz, 0.3)
+    H = spin.longrange_hamiltonian(N, f, pairs, Sz, 0.3)
+    assert H.shape == (3 ** N, 3 ** N)
+    assert np.max(np.abs(mpo.mpo_to_dense(Ws) - H)) < 1e-13
+    c, lam, _ = mpo.fit_exponentials(1.0 / np.arange(1, 17) ** 2.0, 3)
+    g = mpo.eval_exponentials(c, lam, N - 1)
+    Ws2 = mpo.mpo_exponentials(N, c, lam, pairs, Sz, 0.3)
+    H2 = spin.longrange_hamiltonian(N, g, pairs, Sz, 0.3)
+    assert np.max(np.abs(mpo.mpo_to_dense(Ws2) - H2)) < 1e-12
