@@ -170,7 +170,7 @@ def sweep_timing(pkg, ctx, steps=40):
     return res
 
 
-def segments_timing(pkg, ctx, np):
+def segments_timing(pkg, ctx, np, graph=True):
     """Segment-parallel 2TDVP, N=201 long-range XY (alpha 1.5, K = 6, w = 14),
     32 segments (11 | 6 x 30 | 10), uneven bond profile (one seeded draw in
     [64, 1024] per segment), seeded random state, dt = 0.01, static shapes,
@@ -188,6 +188,7 @@ def segments_timing(pkg, ctx, np):
     c, lam, err = pkg.fit.fit_power_law(p["alpha"], p["K"], N - 1)
     sx, sy = (np.array(q, dtype=np.complex128) for q in (pkg.PAULI_X, pkg.PAULI_Y))
     mpo = pkg.MPO.longrange(ctx, N, [(0.5, sx, sx), (0.5, sy, sy)], c=c, lam=lam)
+    progress("segments: building the inverse canonical state")
     t0 = time.perf_counter()
     sg = pkg.Segments.init(ctx, mpo, T, sizes, compute="c64")
     ctx.sync()
@@ -195,8 +196,10 @@ def segments_timing(pkg, ctx, np):
     del T
     res = {"init_s": round(init_s, 2)}
     eager = pkg.SegmentOptions()
-    graph = pkg.SegmentOptions(use_graph=True)
+    graph_opts = pkg.SegmentOptions(use_graph=True)
+    progress("segments: warm-up step (tile tuning)")
     sg.step(mpo, p["dt"], eager)
+    progress("segments: timed eager step")
     ctx.profile(True)
     st = sg.step(mpo, p["dt"], eager)
     prof = ctx.profile_read()
@@ -212,12 +215,15 @@ def segments_timing(pkg, ctx, np):
     res["batched_expm_s"] = round(prof.get("seg_batched_expm", {}).get("ms", 0.0) * 1e-3, 3)
     res["splits_s"] = round(prof.get("seg_splits", {}).get("ms", 0.0) * 1e-3, 3)
     res["mpo_stage_s"] = round(sum(v["ms"] for k, v in prof.items() if k.startswith("wstage_grouped")) * 1e-3, 3)
-    sg.step(mpo, p["dt"], graph)
-    st = sg.step(mpo, p["dt"], graph)
-    res["s_per_step_graph"] = round(st["seconds"], 3)
+    if graph:
+        progress("segments: graph capture step")
+        sg.step(mpo, p["dt"], graph_opts)
+        progress("segments: graph replay step")
+        st = sg.step(mpo, p["dt"], graph_opts)
+        res["s_per_step_graph"] = round(st["seconds"], 3)
     res["matvecs_per_step"] = st["matvecs"]
     res["chi_max"] = max(chi)
-    res["w_total_after_4_steps"] = sg.w_total
+    res["w_total"] = sg.w_total
     sg.close()
     mpo.close()
     res["workload"] = ("segment-parallel 2TDVP, N=201 XY alpha=1.5 (K=6, w=14), 32 segments 11|6x30|10, "
@@ -295,6 +301,9 @@ def main():
     ap.add_argument("--sweep-steps", type=int, default=40)
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-segments", action="store_true", help="skip the segment-parallel N=201 step")
+    ap.add_argument("--only-segments", action="store_true",
+                    help="run only the segment-parallel N=201 workload and print its timings (for profiling)")
+    ap.add_argument("--segments-no-graph", action="store_true", help="segment workload: eager steps only")
     ap.add_argument("--grad-steps", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -309,6 +318,12 @@ def main():
 
     if args.copy_calibration:
         copy_calibration(torch)
+        return
+
+    if args.only_segments:
+        ctx = pkg.Context(0)
+        print(json.dumps({"segments": segments_timing(pkg, ctx, np, graph=not args.segments_no_graph)}))
+        ctx.close()
         return
 
     ctx = pkg.Context(0)
