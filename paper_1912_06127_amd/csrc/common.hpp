@@ -236,6 +236,12 @@ void vdot_multi(tdvp_ctx ctx, const double2* V, int64_t vstride, int nv, const d
 // doubles), V[k+1] = w / ||w|| (zero if w vanishes).  V holds n-element rows.
 constexpr int64_t kSmallLanczos = 8192;
 void lanczos_small_step(double2* V, int64_t n, int k, double2* w, double beta_prev, double* out, hipStream_t s);
+// Eigen-decomposition of a Hermitian n x n matrix G (row-major, n <= kJacobiMaxOrder) in
+// one workgroup (cyclic Jacobi): evals descending, vecs row c = conj of the
+// c-th eigenvector (row-major [n][n]), sweeps = Jacobi sweeps used (may be
+// null).  All device pointers.
+constexpr int kJacobiMaxOrder = 64;
+void jacobi_eigh_small(const double2* G, int n, double* evals, double2* vecs, int* sweeps, hipStream_t s);
 // w -= sum_j coef[j] V[j]   (coef device complex[nv])
 void axpy_multi(const double2* V, int64_t vstride, int nv, const double2* coef, double2* w,
                 int64_t n, hipStream_t s);
@@ -258,6 +264,8 @@ void conj_transpose(double2* dst, int64_t ldd, const double2* src, int64_t lds, 
 void scale_rows(double2* V, int64_t ld, const double* sv, int rows, int cols, hipStream_t s);
 // columns of U (row-major [rows][cols]) multiplied by real sv[c]
 void scale_cols(double2* U, int64_t ld, const double* sv, int rows, int cols, hipStream_t s);
+// out[c] = ||P row c||^2 (by_rows) or ||P column c||^2, c < count, vectors of len elements
+void vec_norms2(const double2* P, int64_t ld, int count, int len, bool by_rows, double* out, hipStream_t s);
 // c128 <-> c64 conversion
 void convert(void* dst, Dt ddt, const void* src, Dt sdt, int64_t n, hipStream_t s);
 // any NaN/Inf in n complex128 values -> flag[0] = 1 (flag must be zeroed)

@@ -273,6 +273,143 @@ __global__ void __launch_bounds__(kSmallThreads) lanczos_small_kernel(double2* V
     for (int64_t e = tid; e < n; e += kSmallThreads) vn[e] = make_double2(w[e].x * inv, w[e].y * inv);
 }
 
+// --------------------------------------------- small Hermitian eigensolver
+// Cyclic Jacobi for a Hermitian matrix of order n <= kJacobiMax in one
+// workgroup, matrix and eigenvectors resident in LDS.  Rounds follow the
+// round-robin (tournament) ordering: n/2 disjoint index pairs per round,
+// whose rotations commute, so all of them are applied together -- first to
+// the columns of A and V, then to the rows of A.  For a_pq = |a_pq| e^{i phi}
+// the rotation is U = [[c, s], [-s e^{-i phi}, c e^{-i phi}]] (a phase that
+// makes a_pq real, then the real Jacobi angle); A <- U^H A U, V <- V U.
+// |a_pq| is taken with hypot: sqrt(x^2 + y^2) loses its precision once the
+// squares are subnormal, and a phase e^{i phi} off the unit circle scales
+// an eigenvector instead of rotating it.  Entries at or below 1e-18 ||A||_F
+// (a rounding-level perturbation of A) are not rotated, so repeated sweeps
+// over a null space never push entries into the subnormal range.  Sweeps
+// stop when the off-diagonal mass is below 1e-30 of the diagonal mass, or
+// after 40 sweeps.  Outputs: eigenvalues in descending order and
+// the eigenvectors as conjugated rows (row c = conj of the c-th eigenvector).
+constexpr int kJacobiMax = kJacobiMaxOrder;
+constexpr int kJacobiThreads = 256;
+
+__global__ void __launch_bounds__(kJacobiThreads) jacobi_eigh_kernel(const double2* G, int n, double* evals,
+                                                                       double2* vecs, int* sweeps_out) {
+    __shared__ double2 A[kJacobiMax * kJacobiMax];
+    __shared__ double2 V[kJacobiMax * kJacobiMax];
+    __shared__ double rc[kJacobiMax / 2], rs[kJacobiMax / 2], rpr[kJacobiMax / 2], rpi[kJacobiMax / 2];
+    __shared__ int rp[kJacobiMax / 2], rq[kJacobiMax / 2];
+    __shared__ double red[kJacobiThreads], red2[kJacobiThreads];
+    __shared__ int done;
+    const int tid = threadIdx.x;
+    const int m = n + (n & 1);  // even order for the tournament (a padded index is a no-op)
+    for (int i = tid; i < m * m; i += kJacobiThreads) {
+        const int r = i / m, c = i % m;
+        // Hermitian part of G: a rounding-level anti-Hermitian remainder could
+        // never be rotated away and would hold the sweeps at their cap
+        double2 a = make_double2(0.0, 0.0);
+        if (r < n && c < n) {
+            const double2 x = G[r * n + c], y = G[c * n + r];
+            a = make_double2(0.5 * (x.x + y.x), 0.5 * (x.y - y.y));
+        }
+        A[i] = a;
+        V[i] = make_double2(r == c ? 1.0 : 0.0, 0.0);
+    }
+    if (tid == 0) done = 0;
+    __syncthreads();
+    const int half = m / 2;
+    int sweep = 0;
+    for (; sweep < 40; ++sweep) {
+        // convergence test: off-diagonal vs diagonal mass
+        double off = 0.0, dia = 0.0;
+        for (int i = tid; i < m * m; i += kJacobiThreads) {
+            const int r = i / m, c = i % m;
+            const double a2 = A[i].x * A[i].x + A[i].y * A[i].y;
+            if (r == c) dia += a2;
+            else off += a2;
+        }
+        red[tid] = off;
+        red2[tid] = dia;
+        __syncthreads();
+        for (int h = kJacobiThreads / 2; h > 0; h >>= 1) {
+            if (tid < h) {
+                red[tid] += red[tid + h];
+                red2[tid] += red2[tid + h];
+            }
+            __syncthreads();
+        }
+        if (tid == 0) done = (red[0] <= 1e-30 * red2[0] || red[0] == 0.0) ? 1 : 0;
+        __syncthreads();
+        if (done) break;
+        const double skip = 1e-18 * sqrt(red[0] + red2[0]);  // red[] is rewritten only in the next sweep
+        for (int round = 0; round < m - 1; ++round) {
+            // tournament pairs: position 0 fixed, the others rotate
+            if (tid < half) {
+                const int a = tid == 0 ? 0 : 1 + (tid - 1 + round) % (m - 1);
+                const int b = 1 + (m - 2 - tid + round) % (m - 1);
+                const int p = a < b ? a : b, q = a < b ? b : a;
+                rp[tid] = p;
+                rq[tid] = q;
+                const double2 apq = A[p * m + q];
+                const double mag = hypot(apq.x, apq.y);
+                double c = 1.0, sn = 0.0, er = 1.0, ei = 0.0;
+                if (mag > skip && mag > 1e-290) {
+                    const double tau = (A[q * m + q].x - A[p * m + p].x) / (2.0 * mag);
+                    const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                    c = 1.0 / sqrt(1.0 + t * t);
+                    sn = t * c;
+                    er = apq.x / mag;  // e^{i phi}
+                    ei = apq.y / mag;
+                }
+                rc[tid] = c;
+                rs[tid] = sn;
+                rpr[tid] = er;
+                rpi[tid] = ei;
+            }
+            __syncthreads();
+            // columns: col_p' = c col_p - s e^{-i phi} col_q, col_q' = s col_p + c e^{-i phi} col_q
+            for (int i = tid; i < half * m; i += kJacobiThreads) {
+                const int k = i / m, r = i % m;
+                const int p = rp[k], q = rq[k];
+                const double c = rc[k], sn = rs[k], er = rpr[k], ei = -rpi[k];  // e^{-i phi}
+                for (int which = 0; which < 2; ++which) {
+                    double2* M = which ? V : A;
+                    const double2 xp = M[r * m + p], xq = M[r * m + q];
+                    const double2 eq = make_double2(er * xq.x - ei * xq.y, er * xq.y + ei * xq.x);
+                    M[r * m + p] = make_double2(c * xp.x - sn * eq.x, c * xp.y - sn * eq.y);
+                    M[r * m + q] = make_double2(sn * xp.x + c * eq.x, sn * xp.y + c * eq.y);
+                }
+            }
+            __syncthreads();
+            // rows: row_p' = c row_p - s e^{i phi} row_q, row_q' = s row_p + c e^{i phi} row_q
+            for (int i = tid; i < half * m; i += kJacobiThreads) {
+                const int k = i / m, col = i % m;
+                const int p = rp[k], q = rq[k];
+                const double c = rc[k], sn = rs[k], er = rpr[k], ei = rpi[k];
+                const double2 xp = A[p * m + col], xq = A[q * m + col];
+                const double2 eq = make_double2(er * xq.x - ei * xq.y, er * xq.y + ei * xq.x);
+                A[p * m + col] = make_double2(c * xp.x - sn * eq.x, c * xp.y - sn * eq.y);
+                A[q * m + col] = make_double2(sn * xp.x + c * eq.x, sn * xp.y + c * eq.y);
+            }
+            __syncthreads();
+        }
+    }
+    // descending order by rank (ties broken by index)
+    for (int i = tid; i < n; i += kJacobiThreads) {
+        const double li = A[i * m + i].x;
+        int rank = 0;
+        for (int j = 0; j < n; ++j) {
+            const double lj = A[j * m + j].x;
+            rank += (lj > li) || (lj == li && j < i);
+        }
+        evals[rank] = li;
+        for (int r = 0; r < n; ++r) {
+            const double2 v = V[r * m + i];
+            vecs[(int64_t)rank * n + r] = make_double2(v.x, -v.y);
+        }
+    }
+    if (tid == 0 && sweeps_out) *sweeps_out = sweep;
+}
+
 // ------------------------------------------------------------ FP64 vectors
 
 __global__ void vdot_partial_kernel(const double2* V, int64_t vstride, int nv, const double2* w,
@@ -456,6 +593,25 @@ __global__ void scale_cols_kernel(double2* U, int64_t ld, const double* sv, int 
     const double s = sv[c];
     double2 v = U[(int64_t)r * ld + c];
     U[(int64_t)r * ld + c] = make_double2(s * v.x, s * v.y);
+}
+
+// out[c] = squared 2-norm of vector c of P: row c (by_rows) or column c,
+// each of len elements; one block per vector.
+__global__ void vec_norms2_kernel(const double2* P, int64_t ld, int len, int by_rows, double* out) {
+    __shared__ double red[kVecThreads];
+    const int c = blockIdx.x;
+    double acc = 0.0;
+    for (int k = threadIdx.x; k < len; k += kVecThreads) {
+        const double2 v = by_rows ? P[(int64_t)c * ld + k] : P[(int64_t)k * ld + c];
+        acc += v.x * v.x + v.y * v.y;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = kVecThreads / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[c] = red[0];
 }
 
 __global__ void convert_kernel(void* dst, int d128, const void* src, int s128, int64_t n) {
@@ -687,6 +843,12 @@ void lanczos_small_step(double2* V, int64_t n, int k, double2* w, double beta_pr
     TDVP_CHECK_HIP(hipGetLastError());
 }
 
+void jacobi_eigh_small(const double2* G, int n, double* evals, double2* vecs, int* sweeps, hipStream_t s) {
+    TDVP_REQUIRE(n >= 1 && n <= kJacobiMax, TDVP_E_ARG, "jacobi_eigh_small: order out of range");
+    hipLaunchKernelGGL(jacobi_eigh_kernel, dim3(1), dim3(kJacobiThreads), 0, s, G, n, evals, vecs, sweeps);
+    TDVP_CHECK_HIP(hipGetLastError());
+}
+
 void vdot_multi(tdvp_ctx ctx, const double2* V, int64_t vstride, int nv, const double2* w,
                 int64_t n, double2* out) {
     if (nv <= 0) return;
@@ -759,6 +921,13 @@ void scale_cols(double2* U, int64_t ld, const double* sv, int rows, int cols, hi
     if (rows == 0 || cols == 0) return;
     dim3 grid((cols + 127) / 128, rows);
     hipLaunchKernelGGL(scale_cols_kernel, grid, dim3(128), 0, s, U, ld, sv, rows, cols);
+    TDVP_CHECK_HIP(hipGetLastError());
+}
+
+void vec_norms2(const double2* P, int64_t ld, int count, int len, bool by_rows, double* out, hipStream_t s) {
+    if (count == 0) return;
+    TDVP_REQUIRE(count > 0 && len >= 0, TDVP_E_ARG, "vec_norms2: negative size");
+    hipLaunchKernelGGL(vec_norms2_kernel, dim3(count), dim3(kVecThreads), 0, s, P, ld, len, (int)by_rows, out);
     TDVP_CHECK_HIP(hipGetLastError());
 }
 

@@ -120,6 +120,41 @@ GramResult gram_eigen(tdvp_ctx ctx, const double2* M, int rows, int cols, bool l
         g.B.p = M; g.B.dt = Dt::C128; g.B.ld = cols; g.B.kcontig = false;
     }
     cgemm(ctx, g, true, 4);
+    if (n <= kJacobiMaxOrder) {
+        // small orders: one-workgroup Jacobi instead of the ~n-launch tridiagonalisation
+        r.vecs = static_cast<double2*>(ctx->workspace("gram_vecs", sizeof(double2) * (size_t)n * n));
+        jacobi_eigh_small(G, n, ev, r.vecs, nullptr, ctx->stream);
+        // The Jacobi eigenvalues carry ~n times the rounding of a tridiagonal
+        // solve (every rotation touches the diagonal).  sigma_c is taken instead
+        // as the norm of the projection u_c^dag Theta (left) or Theta v_c
+        // (right): absolute error ~eps ||Theta|| in sigma, not eps ||Theta||^2
+        // in sigma^2, so the discarded weight near w_max is that of an SVD.
+        const int len = left ? cols : rows;
+        double2* P = static_cast<double2*>(ctx->workspace("gram_P", sizeof(double2) * (size_t)n * len));
+        GemmDesc p;
+        p.cdt = Dt::C128;
+        p.C = P;
+        if (left) {  // P[c][k] = sum_i conj(u_c[i]) M[i][k]
+            p.M = n; p.N = cols; p.K = rows; p.ldc = cols;
+            p.A.p = r.vecs; p.A.dt = Dt::C128; p.A.ld = n; p.A.kcontig = true;
+            p.B.p = M; p.B.dt = Dt::C128; p.B.ld = cols; p.B.kcontig = false;
+        } else {     // P[i][c] = sum_k M[i][k] v_c[k]
+            p.M = rows; p.N = n; p.K = cols; p.ldc = n;
+            p.A.p = M; p.A.dt = Dt::C128; p.A.ld = cols; p.A.kcontig = true;
+            p.B.p = r.vecs; p.B.dt = Dt::C128; p.B.ld = n; p.B.kcontig = true; p.B.conj = true;
+        }
+        cgemm(ctx, p, true, 4);
+        vec_norms2(P, left ? cols : n, n, len, left, ev, ctx->stream);
+        std::vector<double> s2(n);
+        TDVP_CHECK_HIP(hipMemcpyAsync(s2.data(), ev, sizeof(double) * n, hipMemcpyDeviceToHost, ctx->stream));
+        TDVP_CHECK_HIP(hipStreamSynchronize(ctx->stream));
+        r.s.resize(n);
+        for (int c = 0; c < n; ++c) {
+            TDVP_REQUIRE(std::isfinite(s2[c]), TDVP_E_NUMERIC, "density-matrix split: non-finite singular value");
+            r.s[c] = std::sqrt(s2[c]);
+        }
+        return r;
+    }
     // row-major G is the column-major conj(G): its eigenvectors W give the
     // eigenvectors conj(W) of G with the same (ascending) eigenvalues
     check_rs(rocsolver_zheevd(ctx->blas, rocblas_evect_original, rocblas_fill_upper, n, rz(G), n, ev, E, dinfo),

@@ -115,10 +115,15 @@ def test_batched_equals_instance_by_instance(ctx):
     for _ in range(2):
         a.step(W, 0.02, pkg.SegmentOptions(compute="c128", batched=True))
         b.step(W, 0.02, pkg.SegmentOptions(compute="c128", batched=False))
-    # same splits up to the density-matrix split's ~1e-16 (s_1/s_i)^2 accuracy
-    for j in range(N):
-        x, y = a.psi(j), b.psi(j)
-        assert np.linalg.norm(x - y) <= 1e-9 * np.linalg.norm(y), j
+    # the site tensors themselves are gauge dependent (eigenvectors inside nearly
+    # degenerate groups may rotate); compare the state, its Schmidt values and
+    # the spin profile
+    Ta, Tb = a.tensors(), b.tensors()
+    ov = abs(omps.overlap(Ta, Tb)) / np.sqrt(omps.norm2(Ta) * omps.norm2(Tb))
+    assert abs(ov - 1.0) <= 1e-10
+    for j in range(N - 1):
+        assert np.allclose(np.sort(a.bond(j)), np.sort(b.bond(j)), rtol=1e-8, atol=0), j
+    assert np.max(np.abs(sz_profile(Ta) - sz_profile(Tb))) <= 1e-10
 
 
 @pytest.mark.parametrize("dt_", ["c64", "c128"])
