@@ -15,8 +15,11 @@
 // stored [outer][k] so that every lane reads its k-slice with one 16-byte
 // LDS load.  The k index inside a tile is permuted (lane group g handles
 // k = g*S + s for instruction step s): the sum over k is order-free, so A
-// and B only have to agree on the permutation.  Two LDS buffers with a
-// register prefetch of the next tile give one barrier per k-tile.
+// and B only have to agree on the permutation.  Two LDS buffers and two
+// register sets (the global loads run two k-tiles ahead of the MFMAs) give
+// one barrier per k-tile.  Output tiles go to the XCDs in contiguous ranges,
+// and inside a range runs of kGroupM m-tiles sweep the n-tiles, so the tiles
+// an XCD holds at one time share rows of A and columns of B in its L2.
 //
 // Inputs may be complex64 or complex128 in either precision (converted while
 // staging), optionally conjugated, with k or the outer index contiguous in
@@ -150,9 +153,14 @@ __device__ __forceinline__ void gemm_block(const KParams& p, TileSmem<T, BM, BN,
     const int g = lane / MT;
     const int r = lane % MT;
 
-    T ar[AE], ai[AE], br[BE], bi[BE];
+    // two register sets: the tile two steps ahead is fetched while the next
+    // one is written to LDS
+    T ar[2][AE], ai[2][AE], br[2][BE], bi[2][BE];
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
 
-    auto gload = [&](int k0) {
+    auto gload = [&](int k0, auto setc) {
+        constexpr int SET = decltype(setc)::value;
 #pragma unroll
         for (int i = 0; i < AE / 2; ++i) {  // pairs along the contiguous index
             const int e = 2 * (tid + NT * i);
@@ -162,8 +170,8 @@ __device__ __forceinline__ void gemm_block(const KParams& p, TileSmem<T, BM, BN,
             const int64_t idx = AK ? (int64_t)gm * p.A.ld + gk : (int64_t)gk * p.A.ld + gm;
             const bool v0 = gm < p.M && gk < kend;
             const bool v1 = AK ? (gm < p.M && gk + 1 < kend) : (gm + 1 < p.M && gk < kend);
-            load_elem<T>(p.A, zA + idx, v0, ar[2 * i], ai[2 * i]);
-            load_elem<T>(p.A, zA + idx + 1, v1, ar[2 * i + 1], ai[2 * i + 1]);
+            load_elem<T>(p.A, zA + idx, v0, ar[SET][2 * i], ai[SET][2 * i]);
+            load_elem<T>(p.A, zA + idx + 1, v1, ar[SET][2 * i + 1], ai[SET][2 * i + 1]);
         }
 #pragma unroll
         for (int i = 0; i < BE / 2; ++i) {
@@ -174,24 +182,25 @@ __device__ __forceinline__ void gemm_block(const KParams& p, TileSmem<T, BM, BN,
             const int64_t idx = BKC ? (int64_t)gn * p.B.ld + gk : (int64_t)gk * p.B.ld + gn;
             const bool v0 = gn < p.N && gk < kend;
             const bool v1 = BKC ? (gn < p.N && gk + 1 < kend) : (gn + 1 < p.N && gk < kend);
-            load_elem<T>(p.B, zB + idx, v0, br[2 * i], bi[2 * i]);
-            load_elem<T>(p.B, zB + idx + 1, v1, br[2 * i + 1], bi[2 * i + 1]);
+            load_elem<T>(p.B, zB + idx, v0, br[SET][2 * i], bi[SET][2 * i]);
+            load_elem<T>(p.B, zB + idx + 1, v1, br[SET][2 * i + 1], bi[SET][2 * i + 1]);
         }
     };
-    auto lstore = [&](int buf) {
+    auto lstore = [&](int buf, auto setc) {
+        constexpr int SET = decltype(setc)::value;
 #pragma unroll
         for (int i = 0; i < AE; ++i) {
             const int e = 2 * (tid + NT * (i / 2)) + (i & 1);
             const int off = AK ? (e / BK) * LDAk + e % BK : (e / BM) * LDAo + e % BM;
-            sA[buf][0][off] = ar[i];
-            sA[buf][1][off] = ai[i];
+            sA[buf][0][off] = ar[SET][i];
+            sA[buf][1][off] = ai[SET][i];
         }
 #pragma unroll
         for (int i = 0; i < BE; ++i) {
             const int e = 2 * (tid + NT * (i / 2)) + (i & 1);
             const int off = BKC ? (e / BK) * LDAk + e % BK : (e / BN) * LDBo + e % BN;
-            sB[buf][0][off] = br[i];
-            sB[buf][1][off] = bi[i];
+            sB[buf][0][off] = br[SET][i];
+            sB[buf][1][off] = bi[SET][i];
         }
     };
 
@@ -207,14 +216,18 @@ __device__ __forceinline__ void gemm_block(const KParams& p, TileSmem<T, BM, BN,
 
     const int nk = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
     if (nk > 0) {
-        gload(kbeg);
-        lstore(0);
+        gload(kbeg, I0{});
+        lstore(0, I0{});
     }
+    if (nk > 1) gload(kbeg + BK, I1{});
     __syncthreads();
 
-    for (int kt = 0; kt < nk; ++kt) {
-        const int cur = kt & 1;
-        if (kt + 1 < nk) gload(kbeg + (kt + 1) * BK);
+    // tile kt sits in register set kt & 1 and LDS buffer kt & 1
+    auto body = [&](int kt, auto setc) {
+        constexpr int SET = decltype(setc)::value;
+        using Other = std::integral_constant<int, 1 - SET>;
+        const int cur = SET;
+        if (kt + 2 < nk) gload(kbeg + (kt + 2) * BK, setc);
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             const int kk = g * S + s;  // permuted k inside the tile
@@ -254,9 +267,15 @@ __device__ __forceinline__ void gemm_block(const KParams& p, TileSmem<T, BM, BN,
                 }
             }
         }
-        if (kt + 1 < nk) lstore(cur ^ 1);
+        if (kt + 1 < nk) lstore(cur ^ 1, Other{});
         __syncthreads();
+    };
+    int kt = 0;
+    for (; kt + 1 < nk; kt += 2) {
+        body(kt, I0{});
+        body(kt + 1, I1{});
     }
+    if (kt < nk) body(kt, I0{});
 
 #pragma unroll
     for (int mi = 0; mi < TM; ++mi) {
@@ -287,14 +306,28 @@ __device__ __forceinline__ void gemm_block(const KParams& p, TileSmem<T, BM, BN,
     }
 }
 
+// Tile t (0 <= t < tiles_m * tiles_n) -> (tm, tn): runs of kGroupM m-tiles
+// sweep all n-tiles (the last run may be shorter); a bijection.
+constexpr int kGroupM = 4;
+__device__ __forceinline__ void grouped_tile(int t, int tiles_m, int tiles_n, int& tm, int& tn) {
+    const int per_group = kGroupM * tiles_n;
+    const int first_m = (t / per_group) * kGroupM;
+    const int gsz = min(tiles_m - first_m, kGroupM);
+    const int u = t % per_group;
+    tm = first_m + u % gsz;
+    tn = u / gsz;
+}
+
 template <typename T, int BM, int BN, int BK, int WM, int WN, bool M3, bool AK, bool BKC>
 __global__ void __launch_bounds__(64 * WM * WN) cgemm2_kernel(KParams p) {
     __shared__ __align__(16) TileSmem<T, BM, BN, BK, AK, BKC> sm;
     const int ntiles = p.tiles_m * p.tiles_n;
     int t = blockIdx.x;
     if ((ntiles & 7) == 0) t = (t & 7) * (ntiles >> 3) + (t >> 3);  // contiguous tile range per XCD
-    const int m0 = (t % p.tiles_m) * BM;
-    const int n0 = (t / p.tiles_m) * BN;
+    int tm, tn;
+    grouped_tile(t, p.tiles_m, p.tiles_n, tm, tn);
+    const int m0 = tm * BM;
+    const int n0 = tn * BN;
     const int z = blockIdx.z / p.ksplit;
     const int kbeg = (blockIdx.z % p.ksplit) * p.kchunk;
     const int kend = min(p.K, kbeg + p.kchunk);
@@ -324,8 +357,10 @@ __global__ void __launch_bounds__(64 * WM * WN) cgemm2_grouped_kernel(const GPro
     }
     const KParams p = probs[lo].p;
     const int tl = (int)(t - probs[lo].tile_begin);
-    const int m0 = (tl % p.tiles_m) * BM;
-    const int n0 = (tl / p.tiles_m) * BN;
+    int tm, tn;
+    grouped_tile(tl, p.tiles_m, p.tiles_n, tm, tn);
+    const int m0 = tm * BM;
+    const int n0 = tn * BN;
     gemm_block<T, BM, BN, BK, WM, WN, M3, AK, BKC>(p, sm, m0, n0, 0, 0, 0, 0, p.K);
 }
 
