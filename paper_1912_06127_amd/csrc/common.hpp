@@ -183,6 +183,25 @@ struct WStageDesc {
     bool fp64 = false;
 };
 void wstage(tdvp_ctx ctx, const WStageDesc& w);
+// Fused y = H_eff x for small bonds (all three stages in one launch, one
+// block per row a').  Layouts as in heff_apply: L[wl][chil][chil],
+// R[wr][chir][chir], x, y [chil][D][chir]; operator rows n*D + s', columns
+// k*D + s, values of the compute dtype.  x and y must not overlap.
+constexpr int kHeffSmallChi = 32;
+struct HeffSmallDesc {
+    const void* L = nullptr; Dt L_dt = Dt::C64;
+    const void* R = nullptr; Dt R_dt = Dt::C64;
+    const void* x = nullptr; Dt x_dt = Dt::C64;
+    void* y = nullptr; Dt y_dt = Dt::C64;
+    const int* row_ptr = nullptr;
+    const int* col = nullptr;
+    const void* val = nullptr;
+    int chil = 0, chir = 0, D = 1, wl = 1, wr = 1;
+    bool fp64 = false;
+    double flops = 0.0;
+};
+bool heff_small_fits(int chil, int chir, int D, int wl, int wr, bool fp64);
+void heff_small(tdvp_ctx ctx, const HeffSmallDesc& d);
 // Many MPO stages of one precision in one launch (see GroupedGemm).
 struct GroupedWStage {
     DevMem probs;

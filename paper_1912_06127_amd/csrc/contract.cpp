@@ -85,6 +85,26 @@ void heff_apply(tdvp_ctx ctx, const HeffArgs& a, const void* x, Dt x_dt, void* y
     const int64_t chil = a.chil, chir = a.chir;
     TDVP_REQUIRE(a.mop && a.mop->rows == a.wr * D && a.mop->cols == a.wl * D, TDVP_E_SHAPE,
                  "heff: MPO stage operator does not match the bond dimensions");
+    const size_t xbytes = elem_bytes(x_dt) * (size_t)chil * D * chir;
+    const size_t ybytes = elem_bytes(y_dt) * (size_t)chil * D * chir;
+    const char* xb = static_cast<const char*>(x);
+    const char* yb = static_cast<const char*>(y);
+    const bool overlap = xb < yb + ybytes && yb < xb + xbytes;
+    if (!overlap && heff_small_fits(a.chil, a.chir, D, a.wl, a.wr, a.fp64)) {
+        HeffSmallDesc h;
+        h.L = a.L; h.L_dt = a.env_dt;
+        h.R = a.R; h.R_dt = a.env_dt;
+        h.x = x; h.x_dt = x_dt;
+        h.y = y; h.y_dt = y_dt;
+        h.row_ptr = a.mop->row_ptr;
+        h.col = a.mop->col;
+        h.val = a.mop->val;
+        h.chil = a.chil; h.chir = a.chir; h.D = D; h.wl = a.wl; h.wr = a.wr;
+        h.fp64 = a.fp64;
+        h.flops = heff_flops(a.nsite, a.chil, a.chir, a.d, a.wl, a.wr);
+        heff_small(ctx, h);
+        return;
+    }
     void* T1 = ctx->workspace("heff_T1", elem_bytes(cdt) * (size_t)a.wl * chil * D * chir);
     void* T3 = ctx->workspace("heff_T3", elem_bytes(cdt) * (size_t)a.wr * chil * D * chir);
 

@@ -172,6 +172,133 @@ __global__ void __launch_bounds__(kWThreads) wstage_grouped_kernel(const GWProbl
     wstage_tile<T>(w, p, q0, xin, rp, cl, vl);
 }
 
+// ------------------------------------------- fused H_eff for small bonds
+// For small chi_l, chi_r the three stages of y = H_eff x (Sec. III A) have
+// only a few hundred points each and are bound by launch latency.  Here one
+// block per output row a' runs all of them with the intermediates in LDS:
+//   T1[k][s][b]   = sum_a L[k][a'][a] x[a][s][b]        (k < wl, s < D, b < chi_r)
+//   T3[r][b]      = sum_e M[r][c_e] T1[c_e][b]          (r = n D + s', sparse MPO stage)
+//   y[a'][s'][b'] = sum_n sum_b T3[n D + s'][b] R[n][b][b']
+// x and R are read from global memory (L2-resident at these sizes); the L
+// row of a' and the MPO operator are staged in LDS.  Stage B splits the sum
+// over n between thread groups and reduces the partial sums through LDS.
+struct HsParams {
+    const void* L; int L128;
+    const void* R; int R128;
+    const void* x; int x128;
+    void* y; int y128;
+    const int* row_ptr;
+    const int* col;
+    const void* val;
+    int chil, chir, D, wl, wr;
+};
+
+constexpr int kHsThreads = 256;
+constexpr int kHsKC = 8;  // stage-A accumulators (values of k) per thread
+
+template <typename T>
+size_t heff_small_smem(int chil, int chir, int D, int wl, int wr) {
+    const size_t nc = (size_t)D * chir;
+    const size_t red = nc > (size_t)kHsThreads ? nc : (size_t)kHsThreads;
+    return wstage_op_bytes<T>() + sizeof(typename cplx<T>::t) * ((wl + wr) * nc + red + (size_t)wl * chil);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kHsThreads) heff_small_kernel(HsParams h) {
+    using C = typename cplx<T>::t;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    WParams w;
+    w.row_ptr = h.row_ptr;
+    w.col = h.col;
+    w.val = h.val;
+    w.nout = h.wr * h.D;
+    const int* rp;
+    const int* cl;
+    const C* vl;
+    const int tid = threadIdx.x, ap = blockIdx.x;
+    const int NC = h.D * h.chir;
+    const int G = NC >= kHsThreads ? 1 : min(h.wr, kHsThreads / NC);  // stage-B groups over n
+    C* T1 = reinterpret_cast<C*>(smem_raw + wstage_op_bytes<T>());  // [wl][D][chir]
+    C* T3 = T1 + (size_t)h.wl * NC;                                  // [wr][D][chir]
+    C* red = T3 + (size_t)h.wr * NC;                                 // [max(NC, kHsThreads)]
+    C* Ls = red + (NC > kHsThreads ? NC : kHsThreads);               // [wl][chil]
+    for (int i = tid; i < h.wl * h.chil; i += kHsThreads) {
+        const int k = i / h.chil, a = i % h.chil;
+        T re, im;
+        ld<T>(h.L, h.L128, ((int64_t)k * h.chil + ap) * h.chil + a, re, im);
+        Ls[i] = C{re, im};
+    }
+    wstage_stage_op<T>(w, smem_raw, rp, cl, vl);  // contains the barrier that publishes Ls
+
+    // stage A: item = (column (s, b), chunk of kHsKC values of k)
+    const int kchunks = (h.wl + kHsKC - 1) / kHsKC;
+    for (int item = tid; item < NC * kchunks; item += kHsThreads) {
+        const int c = item % NC, k0 = (item / NC) * kHsKC;
+        T ar[kHsKC], ai[kHsKC];
+#pragma unroll
+        for (int j = 0; j < kHsKC; ++j) ar[j] = ai[j] = T(0);
+        for (int a = 0; a < h.chil; ++a) {
+            T xr, xi;
+            ld<T>(h.x, h.x128, (int64_t)a * NC + c, xr, xi);
+#pragma unroll
+            for (int j = 0; j < kHsKC; ++j) {
+                if (k0 + j < h.wl) {
+                    const C l = Ls[(k0 + j) * h.chil + a];
+                    ar[j] += l.x * xr - l.y * xi;
+                    ai[j] += l.x * xi + l.y * xr;
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kHsKC; ++j)
+            if (k0 + j < h.wl) T1[(size_t)(k0 + j) * NC + c] = C{ar[j], ai[j]};
+    }
+    __syncthreads();
+
+    // MPO stage: item = (row r = n D + s', b)
+    for (int item = tid; item < h.wr * NC; item += kHsThreads) {
+        const int r = item / h.chir, b = item % h.chir;
+        T ar = 0, ai = 0;
+        const int e1 = rp[r + 1];
+        for (int e = rp[r]; e < e1; ++e) {
+            const C v = vl[e];
+            const C t = T1[(size_t)cl[e] * h.chir + b];
+            ar += v.x * t.x - v.y * t.y;
+            ai += v.x * t.y + v.y * t.x;
+        }
+        T3[item] = C{ar, ai};
+    }
+    __syncthreads();
+
+    // stage B: item = (column (s', b'), group g of n = g, g + G, ...)
+    for (int item = tid; item < NC * G; item += kHsThreads) {
+        const int c = item % NC, g = item / NC;
+        const int sp = c / h.chir, bp = c % h.chir;
+        T ar = 0, ai = 0;
+        for (int n = g; n < h.wr; n += G) {
+            const C* t3 = T3 + (size_t)(n * h.D + sp) * h.chir;
+            for (int b = 0; b < h.chir; ++b) {
+                T rr, ri;
+                ld<T>(h.R, h.R128, ((int64_t)n * h.chir + b) * h.chir + bp, rr, ri);
+                const C t = t3[b];
+                ar += t.x * rr - t.y * ri;
+                ai += t.x * ri + t.y * rr;
+            }
+        }
+        red[item] = C{ar, ai};
+    }
+    __syncthreads();
+    for (int c = tid; c < NC; c += kHsThreads) {
+        T ar = 0, ai = 0;
+        for (int g = 0; g < G; ++g) {
+            const C v = red[g * NC + c];
+            ar += v.x;
+            ai += v.y;
+        }
+        st<T>(h.y, h.y128, (int64_t)ap * NC + c, ar, ai);
+    }
+}
+
 // ------------------------------------------------------- small Lanczos step
 // One Lanczos step for a short vector (n <= kSmallLanczos) in one workgroup:
 // alpha = Re<v_k, w>, w -= alpha v_k + beta v_{k-1}, two classical
@@ -834,6 +961,35 @@ void grouped_wstage_run(tdvp_ctx ctx, const GroupedWStage& g) {
     else
         hipLaunchKernelGGL(wstage_grouped_kernel<float>, dim3((unsigned)g.blocks), dim3(g.nt), g.shmem, ctx->stream,
                            pr, g.nprob);
+    TDVP_CHECK_HIP(hipGetLastError());
+}
+
+bool heff_small_fits(int chil, int chir, int D, int wl, int wr, bool fp64) {
+    if (chil < 1 || chir < 1 || chil > kHeffSmallChi || chir > kHeffSmallChi || wl < 1 || wr < 1) return false;
+    const size_t b = fp64 ? heff_small_smem<double>(chil, chir, D, wl, wr) : heff_small_smem<float>(chil, chir, D, wl, wr);
+    return b <= 120 * 1024;
+}
+
+void heff_small(tdvp_ctx ctx, const HeffSmallDesc& d) {
+    TDVP_REQUIRE(heff_small_fits(d.chil, d.chir, d.D, d.wl, d.wr, d.fp64), TDVP_E_SHAPE,
+                 "heff_small: shape outside the fused kernel's limits");
+    HsParams h;
+    h.L = d.L; h.L128 = d.L_dt == Dt::C128;
+    h.R = d.R; h.R128 = d.R_dt == Dt::C128;
+    h.x = d.x; h.x128 = d.x_dt == Dt::C128;
+    h.y = d.y; h.y128 = d.y_dt == Dt::C128;
+    h.row_ptr = d.row_ptr;
+    h.col = d.col;
+    h.val = d.val;
+    h.chil = d.chil; h.chir = d.chir; h.D = d.D; h.wl = d.wl; h.wr = d.wr;
+    const size_t shmem = d.fp64 ? heff_small_smem<double>(d.chil, d.chir, d.D, d.wl, d.wr)
+                                : heff_small_smem<float>(d.chil, d.chir, d.D, d.wl, d.wr);
+    const double nc = (double)d.D * d.chir;
+    ProfScope prof(ctx, d.fp64 ? "heff_small_f64" : "heff_small_f32", d.flops,
+                   elem_bytes(d.x_dt) * d.chil * nc + elem_bytes(d.y_dt) * d.chil * nc +
+                       elem_bytes(d.L_dt) * (double)d.wl * d.chil * d.chil + elem_bytes(d.R_dt) * (double)d.wr * d.chir * d.chir);
+    if (d.fp64) hipLaunchKernelGGL(heff_small_kernel<double>, dim3(d.chil), dim3(kHsThreads), shmem, ctx->stream, h);
+    else hipLaunchKernelGGL(heff_small_kernel<float>, dim3(d.chil), dim3(kHsThreads), shmem, ctx->stream, h);
     TDVP_CHECK_HIP(hipGetLastError());
 }
 
