@@ -81,6 +81,7 @@ struct tdvp_ctx_s {
     uint64_t ws_gen = 0;                        // bumped whenever a workspace moves
     bool prof_on = false;                       // HIP event pair around every launch
     bool autotune = true;                       // time GEMM tiles per shape bucket
+    std::map<int64_t, int> krylov_hint;         // Lanczos iterations last used per vector length
     std::vector<tdvp_prof_rec> prof_pending;
     std::map<std::string, tdvp_prof_total> prof_total;
 
@@ -254,7 +255,11 @@ void vdot_multi(tdvp_ctx ctx, const double2* V, int64_t vstride, int nv, const d
 // Gram-Schmidt passes against V[0..k], out[0] = alpha, out[1] = ||w||^2 (device
 // doubles), V[k+1] = w / ||w|| (zero if w vanishes).  V holds n-element rows.
 constexpr int64_t kSmallLanczos = 8192;
-void lanczos_small_step(double2* V, int64_t n, int k, double2* w, double beta_prev, double* out, hipStream_t s);
+// beta_{k-1} is beta_prev, or sqrt(*nn_prev) when nn_prev (device, the
+// previous step's ||w||^2) is not null, so that steps can be queued
+// without reading anything back.
+void lanczos_small_step(double2* V, int64_t n, int k, double2* w, double beta_prev, const double* nn_prev,
+                        double* out, hipStream_t s);
 // Eigen-decomposition of a Hermitian n x n matrix G (row-major, n <= kJacobiMaxOrder) in
 // one workgroup (cyclic Jacobi): evals descending, vecs row c = conj of the
 // c-th eigenvector (row-major [n][n]), sweeps = Jacobi sweeps used (may be

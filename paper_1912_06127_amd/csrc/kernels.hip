@@ -315,7 +315,10 @@ __device__ inline double wave_sum(double v) {
 }
 
 __global__ void __launch_bounds__(kSmallThreads) lanczos_small_kernel(double2* V, int64_t n, int k, double2* w,
-                                                                      double beta_prev, double* out) {
+                                                                      double beta_prev, const double* nn_prev,
+                                                                      double* out) {
+    // beta_{k-1} from the previous step's ||w||^2 when it is still on the device
+    if (nn_prev) beta_prev = sqrt(fmax(0.0, *nn_prev));
     __shared__ double sre[kSmallMaxK + 1][kSmallWaves], sim[kSmallMaxK + 1][kSmallWaves];
     __shared__ double coef_re[kSmallMaxK + 1], coef_im[kSmallMaxK + 1];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -993,9 +996,10 @@ void heff_small(tdvp_ctx ctx, const HeffSmallDesc& d) {
     TDVP_CHECK_HIP(hipGetLastError());
 }
 
-void lanczos_small_step(double2* V, int64_t n, int k, double2* w, double beta_prev, double* out, hipStream_t s) {
+void lanczos_small_step(double2* V, int64_t n, int k, double2* w, double beta_prev, const double* nn_prev,
+                        double* out, hipStream_t s) {
     TDVP_REQUIRE(n <= kSmallLanczos && k < kSmallMaxK, TDVP_E_ARG, "lanczos_small_step: vector or basis too large");
-    hipLaunchKernelGGL(lanczos_small_kernel, dim3(1), dim3(kSmallThreads), 0, s, V, n, k, w, beta_prev, out);
+    hipLaunchKernelGGL(lanczos_small_kernel, dim3(1), dim3(kSmallThreads), 0, s, V, n, k, w, beta_prev, nn_prev, out);
     TDVP_CHECK_HIP(hipGetLastError());
 }
 

@@ -5,11 +5,22 @@
 // only alpha_k and ||w||^2.  The k x k tridiagonal matrix is diagonalised on
 // the host; the iteration stops when beta_k |e_k^T exp(-i tau T_k) e_1| <= tol
 // (a-posteriori estimate) or on a happy breakdown.
+//
+// Short vectors (one-workgroup recurrence step) queue several iterations
+// before reading their scalars back: each step takes beta_{k-1} from the
+// device, so the host synchronises once per batch instead of once per
+// iteration.  Iterations queued past the stopping point only touch Krylov
+// vectors that are never combined.
 #include "internal.hpp"
 
 #include <cmath>
 
 namespace tdvp {
+
+namespace {
+constexpr int kFirstBatch = 8;  // first batch when no earlier run of this length is known
+constexpr int kNextBatch = 2;
+}  // namespace
 
 void tridiag_eigen(const std::vector<double>& alpha, const std::vector<double>& beta,
                    std::vector<double>& evals, std::vector<double>& evecs) {
@@ -79,34 +90,11 @@ KrylovInfo expm_krylov(tdvp_ctx ctx, const MatVec& op, double2* theta, int64_t n
     std::vector<double> alphas, betas, evals, evecs;
     std::vector<double2> y;
     int k_used = 0;
-    const bool small = n <= kSmallLanczos && kmax < 64;
-    for (int k = 0; k < kmax; ++k) {
-        double2* vk = V + (size_t)k * n;
-        op(vk, w);
+    // Consumes iteration k's alpha_k and ||w||^2; returns true when the
+    // iteration stops here.
+    auto consume = [&](int k, double a, double nn) -> bool {
+        const double b = std::sqrt(std::max(0.0, nn));
         ++info.matvecs;
-        double a, b;
-        if (small) {  // the whole recurrence step in one workgroup; writes v_{k+1} too
-            double* sc = reinterpret_cast<double*>(scal);
-            lanczos_small_step(V, n, k, w, k > 0 ? betas.back() : 0.0, sc, s);
-            double hs[2];
-            TDVP_CHECK_HIP(hipMemcpyAsync(hs, sc, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-            TDVP_CHECK_HIP(hipStreamSynchronize(s));
-            a = hs[0];
-            b = std::sqrt(std::max(0.0, hs[1]));
-        } else {
-            vdot_multi(ctx, vk, 0, 1, w, n, scal);  // alpha_k = <v_k, H v_k>
-            lanczos_3term(w, vk, k > 0 ? V + (size_t)(k - 1) * n : nullptr, scal,
-                          k > 0 ? betas.back() : 0.0, n, s);
-            for (int pass = 0; pass < 2; ++pass) {  // classical Gram-Schmidt, twice
-                vdot_multi(ctx, V, n, k + 1, w, n, coef);
-                axpy_multi(V, n, k + 1, coef, w, n, s);
-            }
-            vdot_multi(ctx, w, 0, 1, w, n, scal + 1);
-            TDVP_CHECK_HIP(hipMemcpyAsync(host, scal, 2 * sizeof(double2), hipMemcpyDeviceToHost, s));
-            TDVP_CHECK_HIP(hipStreamSynchronize(s));
-            a = host[0].x;
-            b = std::sqrt(std::max(0.0, host[1].x));
-        }
         TDVP_REQUIRE(std::isfinite(a) && std::isfinite(b), TDVP_E_NUMERIC,
                      "Krylov: non-finite value in H_eff application");
         alphas.push_back(a);
@@ -127,13 +115,56 @@ KrylovInfo expm_krylov(tdvp_ctx ctx, const MatVec& op, double2* theta, int64_t n
         for (double v : alphas) scale = std::max(scale, std::fabs(v));
         for (double v : betas) scale = std::max(scale, v);
         const double est = b * std::hypot(y[kk - 1].x, y[kk - 1].y);
-        if (est <= tol || b <= 1e-14 * scale || scale == 0.0) break;
+        if (est <= tol || b <= 1e-14 * scale || scale == 0.0) return true;
         if (k + 1 == kmax) {
             info.converged = false;
-            break;
+            return true;
         }
         betas.push_back(b);
-        if (!small) scale_copy(V + (size_t)(k + 1) * n, w, 1.0 / b, n, s);
+        return false;
+    };
+    const bool small = n <= kSmallLanczos && kmax < 64;
+    if (small) {
+        // the whole recurrence step in one workgroup (it writes v_{k+1});
+        // scalars of iteration k at sc[2k], sc[2k+1]
+        double* sc = static_cast<double*>(ctx->workspace("kry_small_sc", sizeof(double) * 2 * (size_t)kmax));
+        std::vector<double> hs(2 * (size_t)kmax);
+        // consecutive exponentials of one vector length need similar
+        // iteration counts: the first batch is the count of the last one
+        int& hint = ctx->krylov_hint[n];
+        const int first = hint > 0 ? std::max(2, hint) : kFirstBatch;
+        int queued = 0;
+        bool stop = false;
+        while (!stop) {
+            const int end = std::min(kmax, queued + (queued == 0 ? first : kNextBatch));
+            for (int k = queued; k < end; ++k) {
+                op(V + (size_t)k * n, w);
+                lanczos_small_step(V, n, k, w, 0.0, k > 0 ? sc + 2 * (k - 1) + 1 : nullptr, sc + 2 * k, s);
+            }
+            TDVP_CHECK_HIP(hipMemcpyAsync(hs.data() + 2 * queued, sc + 2 * queued, sizeof(double) * 2 * (end - queued),
+                                          hipMemcpyDeviceToHost, s));
+            TDVP_CHECK_HIP(hipStreamSynchronize(s));
+            for (int k = queued; k < end && !stop; ++k) stop = consume(k, hs[2 * k], hs[2 * k + 1]);
+            queued = end;
+        }
+        hint = k_used;
+    } else {
+        for (int k = 0; k < kmax; ++k) {
+            double2* vk = V + (size_t)k * n;
+            op(vk, w);
+            vdot_multi(ctx, vk, 0, 1, w, n, scal);  // alpha_k = <v_k, H v_k>
+            lanczos_3term(w, vk, k > 0 ? V + (size_t)(k - 1) * n : nullptr, scal,
+                          k > 0 ? betas.back() : 0.0, n, s);
+            for (int pass = 0; pass < 2; ++pass) {  // classical Gram-Schmidt, twice
+                vdot_multi(ctx, V, n, k + 1, w, n, coef);
+                axpy_multi(V, n, k + 1, coef, w, n, s);
+            }
+            vdot_multi(ctx, w, 0, 1, w, n, scal + 1);
+            TDVP_CHECK_HIP(hipMemcpyAsync(host, scal, 2 * sizeof(double2), hipMemcpyDeviceToHost, s));
+            TDVP_CHECK_HIP(hipStreamSynchronize(s));
+            if (consume(k, host[0].x, host[1].x)) break;
+            scale_copy(V + (size_t)(k + 1) * n, w, 1.0 / betas.back(), n, s);
+        }
     }
     for (auto& c : y) {
         c.x *= beta0;
