@@ -82,6 +82,8 @@ struct tdvp_ctx_s {
     bool prof_on = false;                       // HIP event pair around every launch
     bool autotune = true;                       // time GEMM tiles per shape bucket
     std::map<int64_t, int> krylov_hint;         // Lanczos iterations last used per vector length
+    void* pinned = nullptr;                     // page-locked host staging (pinned_host)
+    size_t pinned_bytes = 0;
     std::vector<tdvp_prof_rec> prof_pending;
     std::map<std::string, tdvp_prof_total> prof_total;
 
@@ -89,6 +91,9 @@ struct tdvp_ctx_s {
     void dev_free(void* p, size_t bytes);
     // Named workspace of at least `bytes` bytes; contents not preserved on growth.
     void* workspace(const std::string& name, size_t bytes);
+    // Page-locked host buffer of at least `bytes` bytes (grow-only; growing
+    // synchronises the stream first).
+    void* pinned_host(size_t bytes);
     void release_all();
 };
 
@@ -260,6 +265,8 @@ constexpr int64_t kSmallLanczos = 8192;
 // without reading anything back.
 void lanczos_small_step(double2* V, int64_t n, int k, double2* w, double beta_prev, const double* nn_prev,
                         double* out, hipStream_t s);
+// nn[0] = ||x||^2 and v = x / ||x|| (zero if x vanishes) in one workgroup, n <= kSmallLanczos.
+void small_normalize(const double2* x, double2* v, int64_t n, double* nn, hipStream_t s);
 // Eigen-decomposition of a Hermitian n x n matrix G (row-major, n <= kJacobiMaxOrder) in
 // one workgroup (cyclic Jacobi): evals descending, vecs row c = conj of the
 // c-th eigenvector (row-major [n][n]), sweeps = Jacobi sweeps used (may be

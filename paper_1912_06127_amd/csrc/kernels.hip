@@ -403,6 +403,23 @@ __global__ void __launch_bounds__(kSmallThreads) lanczos_small_kernel(double2* V
     for (int64_t e = tid; e < n; e += kSmallThreads) vn[e] = make_double2(w[e].x * inv, w[e].y * inv);
 }
 
+__global__ void __launch_bounds__(kSmallThreads) small_normalize_kernel(const double2* x, double2* v, int64_t n,
+                                                                        double* nn_out) {
+    __shared__ double part[kSmallWaves];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    double nn = 0.0;
+    for (int64_t e = tid; e < n; e += kSmallThreads) nn += x[e].x * x[e].x + x[e].y * x[e].y;
+    nn = wave_sum(nn);
+    if (lane == 0) part[wave] = nn;
+    __syncthreads();
+    double t = 0.0;
+    for (int i = 0; i < kSmallWaves; ++i) t += part[i];  // every thread forms the same sum
+    if (tid == 0) nn_out[0] = t;
+    const double inv = t > 0.0 ? 1.0 / sqrt(t) : 0.0;
+    for (int64_t e = tid; e < n; e += kSmallThreads) v[e] = make_double2(x[e].x * inv, x[e].y * inv);
+}
+
+
 // --------------------------------------------- small Hermitian eigensolver
 // Cyclic Jacobi for a Hermitian matrix of order n <= kJacobiMax in one
 // workgroup, matrix and eigenvectors resident in LDS.  Rounds follow the
@@ -1000,6 +1017,12 @@ void lanczos_small_step(double2* V, int64_t n, int k, double2* w, double beta_pr
                         double* out, hipStream_t s) {
     TDVP_REQUIRE(n <= kSmallLanczos && k < kSmallMaxK, TDVP_E_ARG, "lanczos_small_step: vector or basis too large");
     hipLaunchKernelGGL(lanczos_small_kernel, dim3(1), dim3(kSmallThreads), 0, s, V, n, k, w, beta_prev, nn_prev, out);
+    TDVP_CHECK_HIP(hipGetLastError());
+}
+
+void small_normalize(const double2* x, double2* v, int64_t n, double* nn, hipStream_t s) {
+    TDVP_REQUIRE(n <= kSmallLanczos, TDVP_E_ARG, "small_normalize: vector too long");
+    hipLaunchKernelGGL(small_normalize_kernel, dim3(1), dim3(kSmallThreads), 0, s, x, v, n, nn);
     TDVP_CHECK_HIP(hipGetLastError());
 }
 

@@ -13,6 +13,7 @@
 // vectors that are never combined.
 #include "internal.hpp"
 
+#include <algorithm>
 #include <cmath>
 
 namespace tdvp {
@@ -78,14 +79,20 @@ KrylovInfo expm_krylov(tdvp_ctx ctx, const MatVec& op, double2* theta, int64_t n
     double2* scal = static_cast<double2*>(ctx->workspace("kry_scal", sizeof(double2) * 4));
     double2* coef = static_cast<double2*>(ctx->workspace("kry_coef", sizeof(double2) * (size_t)(kmax + 2)));
     double2 host[2];
-
-    vdot_multi(ctx, theta, 0, 1, theta, n, scal + 1);
-    TDVP_CHECK_HIP(hipMemcpyAsync(host, scal + 1, sizeof(double2), hipMemcpyDeviceToHost, s));
-    TDVP_CHECK_HIP(hipStreamSynchronize(s));
-    const double beta0 = std::sqrt(std::max(0.0, host[0].x));
-    TDVP_REQUIRE(std::isfinite(beta0), TDVP_E_NUMERIC, "Krylov: non-finite input norm");
-    if (beta0 == 0.0) return info;
-    scale_copy(V, theta, 1.0 / beta0, n, s);
+    const bool small = n <= kSmallLanczos && kmax < 64;
+    double beta0 = 0.0;
+    auto check_beta0 = [&](double nn0) {
+        beta0 = std::sqrt(std::max(0.0, nn0));
+        TDVP_REQUIRE(std::isfinite(beta0), TDVP_E_NUMERIC, "Krylov: non-finite input norm");
+    };
+    if (!small) {
+        vdot_multi(ctx, theta, 0, 1, theta, n, scal + 1);
+        TDVP_CHECK_HIP(hipMemcpyAsync(host, scal + 1, sizeof(double2), hipMemcpyDeviceToHost, s));
+        TDVP_CHECK_HIP(hipStreamSynchronize(s));
+        check_beta0(host[0].x);
+        if (beta0 == 0.0) return info;
+        scale_copy(V, theta, 1.0 / beta0, n, s);
+    }
 
     std::vector<double> alphas, betas, evals, evecs;
     std::vector<double2> y;
@@ -123,12 +130,12 @@ KrylovInfo expm_krylov(tdvp_ctx ctx, const MatVec& op, double2* theta, int64_t n
         betas.push_back(b);
         return false;
     };
-    const bool small = n <= kSmallLanczos && kmax < 64;
     if (small) {
         // the whole recurrence step in one workgroup (it writes v_{k+1});
-        // scalars of iteration k at sc[2k], sc[2k+1]
-        double* sc = static_cast<double*>(ctx->workspace("kry_small_sc", sizeof(double) * 2 * (size_t)kmax));
-        std::vector<double> hs(2 * (size_t)kmax);
+        // ||theta||^2 at sc[0], scalars of iteration k at sc[1 + 2k], sc[2 + 2k]
+        double* sc = static_cast<double*>(ctx->workspace("kry_small_sc", sizeof(double) * (1 + 2 * (size_t)kmax)));
+        std::vector<double> hs(1 + 2 * (size_t)kmax);
+        small_normalize(theta, V, n, sc, s);  // read back with the first batch
         // consecutive exponentials of one vector length need similar
         // iteration counts: the first batch is the count of the last one
         int& hint = ctx->krylov_hint[n];
@@ -139,12 +146,17 @@ KrylovInfo expm_krylov(tdvp_ctx ctx, const MatVec& op, double2* theta, int64_t n
             const int end = std::min(kmax, queued + (queued == 0 ? first : kNextBatch));
             for (int k = queued; k < end; ++k) {
                 op(V + (size_t)k * n, w);
-                lanczos_small_step(V, n, k, w, 0.0, k > 0 ? sc + 2 * (k - 1) + 1 : nullptr, sc + 2 * k, s);
+                lanczos_small_step(V, n, k, w, 0.0, k > 0 ? sc + 2 * k : nullptr, sc + 1 + 2 * k, s);
             }
-            TDVP_CHECK_HIP(hipMemcpyAsync(hs.data() + 2 * queued, sc + 2 * queued, sizeof(double) * 2 * (end - queued),
+            const int lo = queued == 0 ? 0 : 1 + 2 * queued;
+            TDVP_CHECK_HIP(hipMemcpyAsync(hs.data() + lo, sc + lo, sizeof(double) * (1 + 2 * end - lo),
                                           hipMemcpyDeviceToHost, s));
             TDVP_CHECK_HIP(hipStreamSynchronize(s));
-            for (int k = queued; k < end && !stop; ++k) stop = consume(k, hs[2 * k], hs[2 * k + 1]);
+            if (queued == 0) {
+                check_beta0(hs[0]);
+                if (beta0 == 0.0) return info;  // the queued steps ran on zero vectors
+            }
+            for (int k = queued; k < end && !stop; ++k) stop = consume(k, hs[1 + 2 * k], hs[2 + 2 * k]);
             queued = end;
         }
         hint = k_used;
@@ -170,9 +182,12 @@ KrylovInfo expm_krylov(tdvp_ctx ctx, const MatVec& op, double2* theta, int64_t n
         c.x *= beta0;
         c.y *= beta0;
     }
-    TDVP_CHECK_HIP(hipMemcpyAsync(coef, y.data(), sizeof(double2) * k_used, hipMemcpyHostToDevice, s));
+    // Pinned staging: the copy runs asynchronously, and every call
+    // synchronises the stream before it writes the staging buffer again.
+    double2* pin = static_cast<double2*>(ctx->pinned_host(sizeof(double2) * (size_t)k_used));
+    std::copy(y.begin(), y.begin() + k_used, pin);
+    TDVP_CHECK_HIP(hipMemcpyAsync(coef, pin, sizeof(double2) * k_used, hipMemcpyHostToDevice, s));
     combine(theta, V, n, k_used, coef, n, s);
-    TDVP_CHECK_HIP(hipStreamSynchronize(s));  // y lives on the host stack frame
     info.k = k_used;
     return info;
 }

@@ -1,6 +1,8 @@
 // Context: device, stream, allocator, rocBLAS handle and named workspaces.
 #include "internal.hpp"
 
+#include <algorithm>
+
 #include <rocsolver/rocsolver.h>
 
 void* tdvp_ctx_s::dev_alloc(size_t bytes) {
@@ -41,7 +43,25 @@ void* tdvp_ctx_s::workspace(const std::string& name, size_t bytes) {
     return b.ptr;
 }
 
+void* tdvp_ctx_s::pinned_host(size_t bytes) {
+    if (pinned_bytes < bytes) {
+        if (pinned) {
+            TDVP_CHECK_HIP(hipStreamSynchronize(stream));  // a queued copy may still read it
+            (void)hipHostFree(pinned);
+            pinned = nullptr;
+            pinned_bytes = 0;
+        }
+        const size_t cap = std::max<size_t>(bytes, 4096);
+        TDVP_CHECK_HIP(hipHostMalloc(&pinned, cap, hipHostMallocDefault));
+        pinned_bytes = cap;
+    }
+    return pinned;
+}
+
 void tdvp_ctx_s::release_all() {
+    if (pinned) (void)hipHostFree(pinned);
+    pinned = nullptr;
+    pinned_bytes = 0;
     for (auto& kv : work) dev_free(kv.second.ptr, kv.second.bytes);
     work.clear();
 }
