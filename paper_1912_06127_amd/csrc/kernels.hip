@@ -4,6 +4,8 @@
 // solvers.
 #include "common.hpp"
 
+#include <algorithm>
+
 namespace tdvp {
 namespace {
 
@@ -179,9 +181,11 @@ __global__ void __launch_bounds__(kWThreads) wstage_grouped_kernel(const GWProbl
 //   T1[k][s][b]   = sum_a L[k][a'][a] x[a][s][b]        (k < wl, s < D, b < chi_r)
 //   T3[r][b]      = sum_e M[r][c_e] T1[c_e][b]          (r = n D + s', sparse MPO stage)
 //   y[a'][s'][b'] = sum_n sum_b T3[n D + s'][b] R[n][b][b']
-// x and R are read from global memory (L2-resident at these sizes); the L
-// row of a' and the MPO operator are staged in LDS.  Stage B splits the sum
-// over n between thread groups and reduces the partial sums through LDS.
+// The L row of a' and the MPO operator are staged in LDS once; x passes
+// through LDS kHsRows rows at a time and R one slice R[n] per thread group
+// at a time, each with coalesced loads, so the inner loops read only LDS.
+// Stage B splits the sum over n between thread groups and reduces the
+// partial sums through LDS.
 struct HsParams {
     const void* L; int L128;
     const void* R; int R128;
@@ -194,13 +198,20 @@ struct HsParams {
 };
 
 constexpr int kHsThreads = 256;
-constexpr int kHsKC = 8;  // stage-A accumulators (values of k) per thread
+constexpr int kHsKC = 8;    // stage-A accumulators (values of k) per thread
+constexpr int kHsRows = 8;  // rows of x staged in LDS per stage-A chunk
+
+__host__ __device__ inline int heff_small_groups(int NC, int wr) {  // stage-B groups over n
+    return NC >= kHsThreads ? 1 : min(wr, kHsThreads / NC);
+}
 
 template <typename T>
 size_t heff_small_smem(int chil, int chir, int D, int wl, int wr) {
     const size_t nc = (size_t)D * chir;
     const size_t red = nc > (size_t)kHsThreads ? nc : (size_t)kHsThreads;
-    return wstage_op_bytes<T>() + sizeof(typename cplx<T>::t) * ((wl + wr) * nc + red + (size_t)wl * chil);
+    const size_t g = (size_t)heff_small_groups((int)nc, wr);
+    const size_t buf = std::max((size_t)kHsRows * nc, g * chir * chir);
+    return wstage_op_bytes<T>() + sizeof(typename cplx<T>::t) * ((wl + wr) * nc + red + (size_t)wl * chil + buf);
 }
 
 template <typename T>
@@ -217,43 +228,60 @@ __global__ void __launch_bounds__(kHsThreads) heff_small_kernel(HsParams h) {
     const C* vl;
     const int tid = threadIdx.x, ap = blockIdx.x;
     const int NC = h.D * h.chir;
-    const int G = NC >= kHsThreads ? 1 : min(h.wr, kHsThreads / NC);  // stage-B groups over n
+    const int G = heff_small_groups(NC, h.wr);
+    const int NR = NC > kHsThreads ? NC : kHsThreads;
     C* T1 = reinterpret_cast<C*>(smem_raw + wstage_op_bytes<T>());  // [wl][D][chir]
     C* T3 = T1 + (size_t)h.wl * NC;                                  // [wr][D][chir]
-    C* red = T3 + (size_t)h.wr * NC;                                 // [max(NC, kHsThreads)]
-    C* Ls = red + (NC > kHsThreads ? NC : kHsThreads);               // [wl][chil]
+    C* red = T3 + (size_t)h.wr * NC;                                 // [NR]
+    C* Ls = red + NR;                                                // [wl][chil]
+    C* buf = Ls + (size_t)h.wl * h.chil;                             // x rows or R slices
     for (int i = tid; i < h.wl * h.chil; i += kHsThreads) {
         const int k = i / h.chil, a = i % h.chil;
         T re, im;
         ld<T>(h.L, h.L128, ((int64_t)k * h.chil + ap) * h.chil + a, re, im);
         Ls[i] = C{re, im};
     }
-    wstage_stage_op<T>(w, smem_raw, rp, cl, vl);  // contains the barrier that publishes Ls
+    for (int i = tid; i < h.wl * NC; i += kHsThreads) T1[i] = C{T(0), T(0)};
+    for (int i = tid; i < NR; i += kHsThreads) red[i] = C{T(0), T(0)};
+    wstage_stage_op<T>(w, smem_raw, rp, cl, vl);  // its barrier publishes Ls and the zeroed T1, red
 
-    // stage A: item = (column (s, b), chunk of kHsKC values of k)
+    // stage A over chunks of kHsRows rows of x; item = (column (s, b), chunk of kHsKC values of k)
     const int kchunks = (h.wl + kHsKC - 1) / kHsKC;
-    for (int item = tid; item < NC * kchunks; item += kHsThreads) {
-        const int c = item % NC, k0 = (item / NC) * kHsKC;
-        T ar[kHsKC], ai[kHsKC];
+    for (int a0 = 0; a0 < h.chil; a0 += kHsRows) {
+        const int na = min(kHsRows, h.chil - a0);
+        for (int i = tid; i < na * NC; i += kHsThreads) {
+            T re, im;
+            ld<T>(h.x, h.x128, (int64_t)a0 * NC + i, re, im);
+            buf[i] = C{re, im};
+        }
+        __syncthreads();
+        for (int item = tid; item < NC * kchunks; item += kHsThreads) {
+            const int c = item % NC, k0 = (item / NC) * kHsKC;
+            T ar[kHsKC], ai[kHsKC];
 #pragma unroll
-        for (int j = 0; j < kHsKC; ++j) ar[j] = ai[j] = T(0);
-        for (int a = 0; a < h.chil; ++a) {
-            T xr, xi;
-            ld<T>(h.x, h.x128, (int64_t)a * NC + c, xr, xi);
+            for (int j = 0; j < kHsKC; ++j) ar[j] = ai[j] = T(0);
+            for (int a = 0; a < na; ++a) {
+                const C xv = buf[a * NC + c];
+#pragma unroll
+                for (int j = 0; j < kHsKC; ++j) {
+                    if (k0 + j < h.wl) {
+                        const C l = Ls[(k0 + j) * h.chil + a0 + a];
+                        ar[j] += l.x * xv.x - l.y * xv.y;
+                        ai[j] += l.x * xv.y + l.y * xv.x;
+                    }
+                }
+            }
 #pragma unroll
             for (int j = 0; j < kHsKC; ++j) {
                 if (k0 + j < h.wl) {
-                    const C l = Ls[(k0 + j) * h.chil + a];
-                    ar[j] += l.x * xr - l.y * xi;
-                    ai[j] += l.x * xi + l.y * xr;
+                    C& t = T1[(size_t)(k0 + j) * NC + c];
+                    t.x += ar[j];
+                    t.y += ai[j];
                 }
             }
         }
-#pragma unroll
-        for (int j = 0; j < kHsKC; ++j)
-            if (k0 + j < h.wl) T1[(size_t)(k0 + j) * NC + c] = C{ar[j], ai[j]};
+        __syncthreads();  // buf is rewritten by the next chunk
     }
-    __syncthreads();
 
     // MPO stage: item = (row r = n D + s', b)
     for (int item = tid; item < h.wr * NC; item += kHsThreads) {
@@ -268,24 +296,33 @@ __global__ void __launch_bounds__(kHsThreads) heff_small_kernel(HsParams h) {
         }
         T3[item] = C{ar, ai};
     }
-    __syncthreads();
 
-    // stage B: item = (column (s', b'), group g of n = g, g + G, ...)
-    for (int item = tid; item < NC * G; item += kHsThreads) {
-        const int c = item % NC, g = item / NC;
-        const int sp = c / h.chir, bp = c % h.chir;
-        T ar = 0, ai = 0;
-        for (int n = g; n < h.wr; n += G) {
-            const C* t3 = T3 + (size_t)(n * h.D + sp) * h.chir;
-            for (int b = 0; b < h.chir; ++b) {
-                T rr, ri;
-                ld<T>(h.R, h.R128, ((int64_t)n * h.chir + b) * h.chir + bp, rr, ri);
-                const C t = t3[b];
-                ar += t.x * rr - t.y * ri;
-                ai += t.x * ri + t.y * rr;
-            }
+    // stage B over chunks of G slices R[n]; item = (column (s', b'), group g: n = n0 + g)
+    const int rs = h.chir * h.chir;
+    for (int n0 = 0; n0 < h.wr; n0 += G) {
+        const int ng = min(G, h.wr - n0);
+        __syncthreads();  // T3 complete (first chunk) / buf free (later chunks)
+        for (int i = tid; i < ng * rs; i += kHsThreads) {
+            T re, im;
+            ld<T>(h.R, h.R128, (int64_t)n0 * rs + i, re, im);
+            buf[i] = C{re, im};
         }
-        red[item] = C{ar, ai};
+        __syncthreads();
+        for (int item = tid; item < NC * ng; item += kHsThreads) {
+            const int c = item % NC, g = item / NC;
+            const int sp = c / h.chir, bp = c % h.chir;
+            const C* t3 = T3 + (size_t)((n0 + g) * h.D + sp) * h.chir;
+            const C* rr = buf + (size_t)g * rs;
+            T ar = 0, ai = 0;
+            for (int b = 0; b < h.chir; ++b) {
+                const C t = t3[b];
+                const C r = rr[b * h.chir + bp];
+                ar += t.x * r.x - t.y * r.y;
+                ai += t.x * r.y + t.y * r.x;
+            }
+            red[item].x += ar;
+            red[item].y += ai;
+        }
     }
     __syncthreads();
     for (int c = tid; c < NC; c += kHsThreads) {
@@ -301,8 +338,9 @@ __global__ void __launch_bounds__(kHsThreads) heff_small_kernel(HsParams h) {
 
 // ------------------------------------------------------- small Lanczos step
 // One Lanczos step for a short vector (n <= kSmallLanczos) in one workgroup:
-// alpha = Re<v_k, w>, w -= alpha v_k + beta v_{k-1}, two classical
-// Gram-Schmidt passes against v_0..v_k, then ||w||^2 and v_{k+1} = w/||w||.
+// alpha = Re<v_k, w>, w -= alpha v_k + beta v_{k-1}, classical Gram-Schmidt
+// against v_0..v_k (a second pass when the first removed more than half of
+// ||w||^2), then ||w||^2 and v_{k+1} = w/||w||.
 // Replaces about a dozen launches of the general path when every launch
 // costs more than the arithmetic (small bond dimensions).
 constexpr int kSmallThreads = 1024;
@@ -314,6 +352,18 @@ __device__ inline double wave_sum(double v) {
     return v;
 }
 
+// Sum over the workgroup, the same value in every thread; part holds
+// kSmallWaves doubles and may be reused right after the call.
+__device__ inline double block_sum_small(double v, double* part) {
+    v = wave_sum(v);
+    __syncthreads();  // earlier readers of part are done
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int i = 0; i < kSmallWaves; ++i) t += part[i];
+    return t;
+}
+
 __global__ void __launch_bounds__(kSmallThreads) lanczos_small_kernel(double2* V, int64_t n, int k, double2* w,
                                                                       double beta_prev, const double* nn_prev,
                                                                       double* out) {
@@ -321,21 +371,15 @@ __global__ void __launch_bounds__(kSmallThreads) lanczos_small_kernel(double2* V
     if (nn_prev) beta_prev = sqrt(fmax(0.0, *nn_prev));
     __shared__ double sre[kSmallMaxK + 1][kSmallWaves], sim[kSmallMaxK + 1][kSmallWaves];
     __shared__ double coef_re[kSmallMaxK + 1], coef_im[kSmallMaxK + 1];
+    __shared__ double part[kSmallWaves];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const double2* vk = V + (int64_t)k * n;
     // alpha_k = Re <v_k, w>
     double a = 0.0;
     for (int64_t e = tid; e < n; e += kSmallThreads) a += vk[e].x * w[e].x + vk[e].y * w[e].y;
-    a = wave_sum(a);
-    if (lane == 0) sre[0][wave] = a;
-    __syncthreads();
-    if (tid == 0) {
-        double t = 0.0;
-        for (int i = 0; i < kSmallWaves; ++i) t += sre[0][i];
-        coef_re[0] = t;
-    }
-    __syncthreads();
-    const double alpha = coef_re[0];
+    const double alpha = block_sum_small(a, part);
+    // three-term recurrence, with ||w||^2 of the result
+    double nb = 0.0;
     for (int64_t e = tid; e < n; e += kSmallThreads) {
         double2 x = w[e];
         x.x -= alpha * vk[e].x;
@@ -346,8 +390,14 @@ __global__ void __launch_bounds__(kSmallThreads) lanczos_small_kernel(double2* V
             x.y -= beta_prev * u.y;
         }
         w[e] = x;
+        nb += x.x * x.x + x.y * x.y;
     }
-    __syncthreads();
+    nb = block_sum_small(nb, part);
+    // Classical Gram-Schmidt against v_0..v_k; a second pass only when the
+    // first removed more than half of ||w||^2 (the DGKS criterion with
+    // eta = 1/sqrt(2): otherwise one pass already leaves w orthogonal to
+    // working precision).
+    double nn = nb;
     for (int pass = 0; pass < 2; ++pass) {
         for (int j = 0; j <= k; ++j) {  // c_j = <v_j, w>
             const double2* v = V + (int64_t)j * n;
@@ -374,6 +424,7 @@ __global__ void __launch_bounds__(kSmallThreads) lanczos_small_kernel(double2* V
             coef_im[tid] = im;
         }
         __syncthreads();
+        double na = 0.0;
         for (int64_t e = tid; e < n; e += kSmallThreads) {  // w -= sum_j c_j v_j
             double2 x = w[e];
             for (int j = 0; j <= k; ++j) {
@@ -382,23 +433,17 @@ __global__ void __launch_bounds__(kSmallThreads) lanczos_small_kernel(double2* V
                 x.y -= coef_re[j] * v.y + coef_im[j] * v.x;
             }
             w[e] = x;
+            na += x.x * x.x + x.y * x.y;
         }
-        __syncthreads();
+        const double before = nn;
+        nn = block_sum_small(na, part);  // also orders the w updates before the next pass
+        if (nn >= 0.5 * before) break;   // uniform: every thread holds the same sums
     }
-    double nn = 0.0;
-    for (int64_t e = tid; e < n; e += kSmallThreads) nn += w[e].x * w[e].x + w[e].y * w[e].y;
-    nn = wave_sum(nn);
-    if (lane == 0) sre[0][wave] = nn;
-    __syncthreads();
     if (tid == 0) {
-        double t = 0.0;
-        for (int i = 0; i < kSmallWaves; ++i) t += sre[0][i];
-        coef_re[0] = t;
         out[0] = alpha;
-        out[1] = t;
+        out[1] = nn;
     }
-    __syncthreads();
-    const double inv = coef_re[0] > 0.0 ? 1.0 / sqrt(coef_re[0]) : 0.0;
+    const double inv = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
     double2* vn = V + (int64_t)(k + 1) * n;
     for (int64_t e = tid; e < n; e += kSmallThreads) vn[e] = make_double2(w[e].x * inv, w[e].y * inv);
 }
@@ -987,7 +1032,7 @@ void grouped_wstage_run(tdvp_ctx ctx, const GroupedWStage& g) {
 bool heff_small_fits(int chil, int chir, int D, int wl, int wr, bool fp64) {
     if (chil < 1 || chir < 1 || chil > kHeffSmallChi || chir > kHeffSmallChi || wl < 1 || wr < 1) return false;
     const size_t b = fp64 ? heff_small_smem<double>(chil, chir, D, wl, wr) : heff_small_smem<float>(chil, chir, D, wl, wr);
-    return b <= 120 * 1024;
+    return b <= 150 * 1024;
 }
 
 void heff_small(tdvp_ctx ctx, const HeffSmallDesc& d) {
