@@ -177,15 +177,17 @@ __global__ void __launch_bounds__(kWThreads) wstage_grouped_kernel(const GWProbl
 // ------------------------------------------- fused H_eff for small bonds
 // For small chi_l, chi_r the three stages of y = H_eff x (Sec. III A) have
 // only a few hundred points each and are bound by launch latency.  Here one
-// block per output row a' runs all of them with the intermediates in LDS:
-//   T1[k][s][b]   = sum_a L[k][a'][a] x[a][s][b]        (k < wl, s < D, b < chi_r)
-//   T3[r][b]      = sum_e M[r][c_e] T1[c_e][b]          (r = n D + s', sparse MPO stage)
-//   y[a'][s'][b'] = sum_n sum_b T3[n D + s'][b] R[n][b][b']
-// The L row of a' and the MPO operator are staged in LDS once; x passes
-// through LDS kHsRows rows at a time and R one slice R[n] per thread group
-// at a time, each with coalesced loads, so the inner loops read only LDS.
-// Stage B splits the sum over n between thread groups and reduces the
-// partial sums through LDS.
+// block per output row a' and output index s' runs all of them with the
+// intermediates in LDS:
+//   T1[k][s][b] = sum_a L[k][a'][a] x[a][s][b]          (k < wl, s < D, b < chi_r)
+//   T3[n][b]    = sum_e M[n D + s'][c_e] T1[c_e][b]     (sparse MPO stage, row s' only)
+//   y[a'][s'][b'] = sum_n sum_b T3[n][b] R[n][b][b']
+// The L row of a' and the MPO operator are staged in LDS, x passes through
+// LDS in chunks of `rows` rows (all of x when it fits) with coalesced loads.
+// Stage B gives each of G thread groups every G-th n and reads R straight
+// from L2 (coalesced along b'); the partial sums meet in LDS.  Stage A is
+// repeated by the D blocks of one a', which is cheap next to the latency
+// it hides.
 struct HsParams {
     const void* L; int L128;
     const void* R; int R128;
@@ -194,24 +196,23 @@ struct HsParams {
     const int* row_ptr;
     const int* col;
     const void* val;
-    int chil, chir, D, wl, wr;
+    int chil, chir, D, wl, wr, rows;
 };
 
 constexpr int kHsThreads = 256;
 constexpr int kHsKC = 8;    // stage-A accumulators (values of k) per thread
-constexpr int kHsRows = 8;  // rows of x staged in LDS per stage-A chunk
+constexpr int kHsRows = 8;  // x rows per chunk when the whole of x does not fit
 
-__host__ __device__ inline int heff_small_groups(int NC, int wr) {  // stage-B groups over n
-    return NC >= kHsThreads ? 1 : min(wr, kHsThreads / NC);
+__host__ __device__ inline int heff_small_groups(int chir, int wr) {  // stage-B groups over n
+    return min(wr, kHsThreads / chir);
 }
 
 template <typename T>
-size_t heff_small_smem(int chil, int chir, int D, int wl, int wr) {
+size_t heff_small_smem(int chil, int chir, int D, int wl, int wr, int rows) {
     const size_t nc = (size_t)D * chir;
-    const size_t red = nc > (size_t)kHsThreads ? nc : (size_t)kHsThreads;
-    const size_t g = (size_t)heff_small_groups((int)nc, wr);
-    const size_t buf = std::max((size_t)kHsRows * nc, g * chir * chir);
-    return wstage_op_bytes<T>() + sizeof(typename cplx<T>::t) * ((wl + wr) * nc + red + (size_t)wl * chil + buf);
+    const size_t red = std::max((size_t)kHsThreads, (size_t)heff_small_groups(chir, wr) * chir);
+    return wstage_op_bytes<T>() +
+           sizeof(typename cplx<T>::t) * (wl * nc + (size_t)wr * chir + red + (size_t)wl * chil + (size_t)rows * nc);
 }
 
 template <typename T>
@@ -226,15 +227,15 @@ __global__ void __launch_bounds__(kHsThreads) heff_small_kernel(HsParams h) {
     const int* rp;
     const int* cl;
     const C* vl;
-    const int tid = threadIdx.x, ap = blockIdx.x;
+    const int tid = threadIdx.x, ap = blockIdx.x, sp = blockIdx.y;
     const int NC = h.D * h.chir;
-    const int G = heff_small_groups(NC, h.wr);
-    const int NR = NC > kHsThreads ? NC : kHsThreads;
+    const int G = heff_small_groups(h.chir, h.wr);
+    const int NR = max(kHsThreads, G * h.chir);
     C* T1 = reinterpret_cast<C*>(smem_raw + wstage_op_bytes<T>());  // [wl][D][chir]
-    C* T3 = T1 + (size_t)h.wl * NC;                                  // [wr][D][chir]
-    C* red = T3 + (size_t)h.wr * NC;                                 // [NR]
+    C* T3 = T1 + (size_t)h.wl * NC;                                  // [wr][chir], row s' = sp
+    C* red = T3 + (size_t)h.wr * h.chir;                             // [NR]
     C* Ls = red + NR;                                                // [wl][chil]
-    C* buf = Ls + (size_t)h.wl * h.chil;                             // x rows or R slices
+    C* xb = Ls + (size_t)h.wl * h.chil;                              // [rows][NC]
     for (int i = tid; i < h.wl * h.chil; i += kHsThreads) {
         const int k = i / h.chil, a = i % h.chil;
         T re, im;
@@ -242,26 +243,26 @@ __global__ void __launch_bounds__(kHsThreads) heff_small_kernel(HsParams h) {
         Ls[i] = C{re, im};
     }
     for (int i = tid; i < h.wl * NC; i += kHsThreads) T1[i] = C{T(0), T(0)};
-    for (int i = tid; i < NR; i += kHsThreads) red[i] = C{T(0), T(0)};
-    wstage_stage_op<T>(w, smem_raw, rp, cl, vl);  // its barrier publishes Ls and the zeroed T1, red
 
-    // stage A over chunks of kHsRows rows of x; item = (column (s, b), chunk of kHsKC values of k)
+    // stage A over chunks of x rows; item = (column (s, b), kHsKC values of k)
     const int kchunks = (h.wl + kHsKC - 1) / kHsKC;
-    for (int a0 = 0; a0 < h.chil; a0 += kHsRows) {
-        const int na = min(kHsRows, h.chil - a0);
+    for (int a0 = 0; a0 < h.chil; a0 += h.rows) {
+        const int na = min(h.rows, h.chil - a0);
+        if (a0 > 0) __syncthreads();  // the previous chunk is consumed
         for (int i = tid; i < na * NC; i += kHsThreads) {
             T re, im;
             ld<T>(h.x, h.x128, (int64_t)a0 * NC + i, re, im);
-            buf[i] = C{re, im};
+            xb[i] = C{re, im};
         }
-        __syncthreads();
+        if (a0 == 0) wstage_stage_op<T>(w, smem_raw, rp, cl, vl);  // its barrier also publishes Ls, T1, xb
+        else __syncthreads();
         for (int item = tid; item < NC * kchunks; item += kHsThreads) {
             const int c = item % NC, k0 = (item / NC) * kHsKC;
             T ar[kHsKC], ai[kHsKC];
 #pragma unroll
             for (int j = 0; j < kHsKC; ++j) ar[j] = ai[j] = T(0);
             for (int a = 0; a < na; ++a) {
-                const C xv = buf[a * NC + c];
+                const C xv = xb[a * NC + c];
 #pragma unroll
                 for (int j = 0; j < kHsKC; ++j) {
                     if (k0 + j < h.wl) {
@@ -280,12 +281,13 @@ __global__ void __launch_bounds__(kHsThreads) heff_small_kernel(HsParams h) {
                 }
             }
         }
-        __syncthreads();  // buf is rewritten by the next chunk
     }
+    __syncthreads();
 
-    // MPO stage: item = (row r = n D + s', b)
-    for (int item = tid; item < h.wr * NC; item += kHsThreads) {
-        const int r = item / h.chir, b = item % h.chir;
+    // MPO stage for output index s': item = (n, b)
+    for (int item = tid; item < h.wr * h.chir; item += kHsThreads) {
+        const int n = item / h.chir, b = item % h.chir;
+        const int r = n * h.D + sp;
         T ar = 0, ai = 0;
         const int e1 = rp[r + 1];
         for (int e = rp[r]; e < e1; ++e) {
@@ -296,43 +298,34 @@ __global__ void __launch_bounds__(kHsThreads) heff_small_kernel(HsParams h) {
         }
         T3[item] = C{ar, ai};
     }
+    __syncthreads();
 
-    // stage B over chunks of G slices R[n]; item = (column (s', b'), group g: n = n0 + g)
-    const int rs = h.chir * h.chir;
-    for (int n0 = 0; n0 < h.wr; n0 += G) {
-        const int ng = min(G, h.wr - n0);
-        __syncthreads();  // T3 complete (first chunk) / buf free (later chunks)
-        for (int i = tid; i < ng * rs; i += kHsThreads) {
-            T re, im;
-            ld<T>(h.R, h.R128, (int64_t)n0 * rs + i, re, im);
-            buf[i] = C{re, im};
-        }
-        __syncthreads();
-        for (int item = tid; item < NC * ng; item += kHsThreads) {
-            const int c = item % NC, g = item / NC;
-            const int sp = c / h.chir, bp = c % h.chir;
-            const C* t3 = T3 + (size_t)((n0 + g) * h.D + sp) * h.chir;
-            const C* rr = buf + (size_t)g * rs;
-            T ar = 0, ai = 0;
+    // stage B: item = (b', group g over n = g, g + G, ...)
+    for (int item = tid; item < G * h.chir; item += kHsThreads) {
+        const int bp = item % h.chir, g = item / h.chir;
+        T ar = 0, ai = 0;
+        for (int n = g; n < h.wr; n += G) {
+            const C* t3 = T3 + (size_t)n * h.chir;
+            const int64_t rbase = (int64_t)n * h.chir * h.chir + bp;
             for (int b = 0; b < h.chir; ++b) {
+                T rr, ri;
+                ld<T>(h.R, h.R128, rbase + (int64_t)b * h.chir, rr, ri);
                 const C t = t3[b];
-                const C r = rr[b * h.chir + bp];
-                ar += t.x * r.x - t.y * r.y;
-                ai += t.x * r.y + t.y * r.x;
+                ar += t.x * rr - t.y * ri;
+                ai += t.x * ri + t.y * rr;
             }
-            red[item].x += ar;
-            red[item].y += ai;
         }
+        red[item] = C{ar, ai};
     }
     __syncthreads();
-    for (int c = tid; c < NC; c += kHsThreads) {
+    for (int bp = tid; bp < h.chir; bp += kHsThreads) {
         T ar = 0, ai = 0;
         for (int g = 0; g < G; ++g) {
-            const C v = red[g * NC + c];
+            const C v = red[g * h.chir + bp];
             ar += v.x;
             ai += v.y;
         }
-        st<T>(h.y, h.y128, (int64_t)ap * NC + c, ar, ai);
+        st<T>(h.y, h.y128, ((int64_t)ap * h.D + sp) * h.chir + bp, ar, ai);
     }
 }
 
@@ -1029,10 +1022,24 @@ void grouped_wstage_run(tdvp_ctx ctx, const GroupedWStage& g) {
     TDVP_CHECK_HIP(hipGetLastError());
 }
 
+namespace {
+constexpr size_t kHsSmemCap = 150 * 1024;
+
+// x rows per stage-A chunk: all of x when the LDS holds it, else kHsRows
+int heff_small_rows(int chil, int chir, int D, int wl, int wr, bool fp64) {
+    auto bytes = [&](int rows) {
+        return fp64 ? heff_small_smem<double>(chil, chir, D, wl, wr, rows)
+                    : heff_small_smem<float>(chil, chir, D, wl, wr, rows);
+    };
+    if (bytes(chil) <= kHsSmemCap) return chil;
+    return bytes(std::min(kHsRows, chil)) <= kHsSmemCap ? std::min(kHsRows, chil) : 0;
+}
+}  // namespace
+
 bool heff_small_fits(int chil, int chir, int D, int wl, int wr, bool fp64) {
     if (chil < 1 || chir < 1 || chil > kHeffSmallChi || chir > kHeffSmallChi || wl < 1 || wr < 1) return false;
-    const size_t b = fp64 ? heff_small_smem<double>(chil, chir, D, wl, wr) : heff_small_smem<float>(chil, chir, D, wl, wr);
-    return b <= 150 * 1024;
+    if (D < 1 || D > 65535) return false;
+    return heff_small_rows(chil, chir, D, wl, wr, fp64) > 0;
 }
 
 void heff_small(tdvp_ctx ctx, const HeffSmallDesc& d) {
@@ -1047,14 +1054,16 @@ void heff_small(tdvp_ctx ctx, const HeffSmallDesc& d) {
     h.col = d.col;
     h.val = d.val;
     h.chil = d.chil; h.chir = d.chir; h.D = d.D; h.wl = d.wl; h.wr = d.wr;
-    const size_t shmem = d.fp64 ? heff_small_smem<double>(d.chil, d.chir, d.D, d.wl, d.wr)
-                                : heff_small_smem<float>(d.chil, d.chir, d.D, d.wl, d.wr);
+    h.rows = heff_small_rows(d.chil, d.chir, d.D, d.wl, d.wr, d.fp64);
+    const size_t shmem = d.fp64 ? heff_small_smem<double>(d.chil, d.chir, d.D, d.wl, d.wr, h.rows)
+                                : heff_small_smem<float>(d.chil, d.chir, d.D, d.wl, d.wr, h.rows);
     const double nc = (double)d.D * d.chir;
     ProfScope prof(ctx, d.fp64 ? "heff_small_f64" : "heff_small_f32", d.flops,
                    elem_bytes(d.x_dt) * d.chil * nc + elem_bytes(d.y_dt) * d.chil * nc +
                        elem_bytes(d.L_dt) * (double)d.wl * d.chil * d.chil + elem_bytes(d.R_dt) * (double)d.wr * d.chir * d.chir);
-    if (d.fp64) hipLaunchKernelGGL(heff_small_kernel<double>, dim3(d.chil), dim3(kHsThreads), shmem, ctx->stream, h);
-    else hipLaunchKernelGGL(heff_small_kernel<float>, dim3(d.chil), dim3(kHsThreads), shmem, ctx->stream, h);
+    const dim3 grid(d.chil, d.D);
+    if (d.fp64) hipLaunchKernelGGL(heff_small_kernel<double>, grid, dim3(kHsThreads), shmem, ctx->stream, h);
+    else hipLaunchKernelGGL(heff_small_kernel<float>, grid, dim3(kHsThreads), shmem, ctx->stream, h);
     TDVP_CHECK_HIP(hipGetLastError());
 }
 
