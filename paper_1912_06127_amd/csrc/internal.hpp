@@ -72,10 +72,11 @@ struct KrylovInfo {
 // theta <- exp(-i tau H) theta with H Hermitian (Sec. III A, Lanczos).
 KrylovInfo expm_krylov(tdvp_ctx ctx, const MatVec& op, double2* theta, int64_t n, double tau,
                        int kmax, double tol);
-// eigen-decomposition of a symmetric tridiagonal k x k matrix (host):
-// evals[k], evecs row-major [k][k] with columns the eigenvectors.
-void tridiag_eigen(const std::vector<double>& alpha, const std::vector<double>& beta,
-                   std::vector<double>& evals, std::vector<double>& evecs);
+// Eigen-decomposition of the symmetric tridiagonal k x k matrix with
+// diagonal alpha and off-diagonal beta (host): evals[k] (unordered) and
+// z[r*k + c] = entry rows[r] of the c-th eigenvector, for the listed rows.
+void tridiag_eigen(const std::vector<double>& alpha, const std::vector<double>& beta, const std::vector<int>& rows,
+                   std::vector<double>& evals, std::vector<double>& z);
 
 // Truncation rule of a two-site split (Sec. III C, Eq. discweight; Sec. III D
 // relative cut): chi_w = smallest rank whose discarded weight is <= w_max,

@@ -15,6 +15,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <limits>
 
 namespace tdvp {
 
@@ -23,49 +24,65 @@ constexpr int kFirstBatch = 8;  // first batch when no earlier run of this lengt
 constexpr int kNextBatch = 2;
 }  // namespace
 
-void tridiag_eigen(const std::vector<double>& alpha, const std::vector<double>& beta,
-                   std::vector<double>& evals, std::vector<double>& evecs) {
-    // Cyclic Jacobi rotations on the dense symmetric matrix (k <= a few dozen).
+void tridiag_eigen(const std::vector<double>& alpha, const std::vector<double>& beta, const std::vector<int>& rows,
+                   std::vector<double>& evals, std::vector<double>& z) {
+    // Implicit QL iterations with Wilkinson shifts (Golub & Van Loan,
+    // Sec. 8.3): each sweep chases a bulge from the bottom of the active
+    // block to its top with plane rotations, which are also applied to the
+    // requested rows of the eigenvector matrix.  O(k^2) work for a fixed
+    // number of rows instead of the O(k^3) per sweep of dense rotations.
     const int k = (int)alpha.size();
-    std::vector<double> A((size_t)k * k, 0.0);
-    for (int i = 0; i < k; ++i) A[i * k + i] = alpha[i];
-    for (int i = 0; i + 1 < k; ++i) A[i * k + i + 1] = A[(i + 1) * k + i] = beta[i];
-    evecs.assign((size_t)k * k, 0.0);
-    for (int i = 0; i < k; ++i) evecs[i * k + i] = 1.0;
-    double scale = 0.0;
-    for (double v : A) scale = std::max(scale, std::fabs(v));
-    for (int sweep = 0; sweep < 100 && k > 1; ++sweep) {
-        double off = 0.0;
-        for (int p = 0; p < k; ++p)
-            for (int q = p + 1; q < k; ++q) off = std::max(off, std::fabs(A[p * k + q]));
-        if (off <= 1e-300 || off <= 1e-18 * scale) break;
-        for (int p = 0; p < k; ++p) {
-            for (int q = p + 1; q < k; ++q) {
-                const double apq = A[p * k + q];
-                if (std::fabs(apq) <= 1e-300) continue;
-                const double tau = (A[q * k + q] - A[p * k + p]) / (2.0 * apq);
-                const double t = (tau >= 0 ? 1.0 : -1.0) / (std::fabs(tau) + std::sqrt(1.0 + tau * tau));
-                const double c = 1.0 / std::sqrt(1.0 + t * t), s = t * c;
-                for (int r = 0; r < k; ++r) {  // columns p, q
-                    const double arp = A[r * k + p], arq = A[r * k + q];
-                    A[r * k + p] = c * arp - s * arq;
-                    A[r * k + q] = s * arp + c * arq;
+    const int nr = (int)rows.size();
+    std::vector<double> d = alpha;
+    std::vector<double> e(k, 0.0);
+    for (int i = 0; i + 1 < k; ++i) e[i] = beta[i];
+    z.assign((size_t)nr * k, 0.0);
+    for (int r = 0; r < nr; ++r) z[(size_t)r * k + rows[r]] = 1.0;
+    const double eps = std::numeric_limits<double>::epsilon();
+    for (int l = 0; l < k; ++l) {
+        for (int iter = 0;; ++iter) {
+            int m = l;
+            for (; m + 1 < k; ++m)  // first negligible coupling at or after l
+                if (std::fabs(e[m]) <= eps * (std::fabs(d[m]) + std::fabs(d[m + 1]))) break;
+            if (m == l) break;
+            TDVP_REQUIRE(iter < 60, TDVP_E_NUMERIC, "Krylov: tridiagonal eigen-solver did not converge");
+            // shift: the eigenvalue of the leading 2 x 2 block nearer to d[l]
+            double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+            double r = std::hypot(g, 1.0);
+            g = d[m] - d[l] + e[l] / (g + std::copysign(r, g));
+            double s = 1.0, c = 1.0, p = 0.0;
+            bool split = false;
+            for (int i = m - 1; i >= l; --i) {
+                const double f = s * e[i], b = c * e[i];
+                r = std::sqrt(f * f + g * g);  // entries are of the order of ||T||
+                e[i + 1] = r;
+                if (r == 0.0) {  // exact zero: the block splits at i
+                    d[i + 1] -= p;
+                    e[m] = 0.0;
+                    split = true;
+                    break;
                 }
-                for (int r = 0; r < k; ++r) {  // rows p, q
-                    const double apr = A[p * k + r], aqr = A[q * k + r];
-                    A[p * k + r] = c * apr - s * aqr;
-                    A[q * k + r] = s * apr + c * aqr;
-                }
-                for (int r = 0; r < k; ++r) {
-                    const double vrp = evecs[r * k + p], vrq = evecs[r * k + q];
-                    evecs[r * k + p] = c * vrp - s * vrq;
-                    evecs[r * k + q] = s * vrp + c * vrq;
+                s = f / r;
+                c = g / r;
+                g = d[i + 1] - p;
+                r = (d[i] - g) * s + 2.0 * c * b;
+                p = s * r;
+                d[i + 1] = g + p;
+                g = c * r - b;
+                for (int q = 0; q < nr; ++q) {  // the same rotation on columns i, i + 1
+                    double* zq = &z[(size_t)q * k];
+                    const double zi1 = zq[i + 1];
+                    zq[i + 1] = s * zq[i] + c * zi1;
+                    zq[i] = c * zq[i] - s * zi1;
                 }
             }
+            if (split) continue;
+            d[l] -= p;
+            e[l] = g;
+            e[m] = 0.0;
         }
     }
-    evals.resize(k);
-    for (int i = 0; i < k; ++i) evals[i] = A[i * k + i];
+    evals = d;
 }
 
 KrylovInfo expm_krylov(tdvp_ctx ctx, const MatVec& op, double2* theta, int64_t n, double tau,
@@ -94,7 +111,7 @@ KrylovInfo expm_krylov(tdvp_ctx ctx, const MatVec& op, double2* theta, int64_t n
         scale_copy(V, theta, 1.0 / beta0, n, s);
     }
 
-    std::vector<double> alphas, betas, evals, evecs;
+    std::vector<double> alphas, betas, evals, z;
     std::vector<double2> y;
     int k_used = 0;
     // Consumes iteration k's alpha_k and ||w||^2; returns true when the
@@ -105,30 +122,44 @@ KrylovInfo expm_krylov(tdvp_ctx ctx, const MatVec& op, double2* theta, int64_t n
         TDVP_REQUIRE(std::isfinite(a) && std::isfinite(b), TDVP_E_NUMERIC,
                      "Krylov: non-finite value in H_eff application");
         alphas.push_back(a);
-        tridiag_eigen(alphas, betas, evals, evecs);
         const int kk = (int)alphas.size();
-        y.assign(kk, double2{0.0, 0.0});
+        // e_{kk-1}^T exp(-i tau T) e_0 needs the first and last eigenvector rows only
+        tridiag_eigen(alphas, betas, {0, kk - 1}, evals, z);
+        double yr = 0.0, yi = 0.0;
         for (int i = 0; i < kk; ++i) {
-            const double ph = -tau * evals[i];
-            const double w0 = evecs[0 * kk + i];
-            for (int j = 0; j < kk; ++j) {
-                const double f = evecs[j * kk + i] * w0;
-                y[j].x += f * std::cos(ph);
-                y[j].y += f * std::sin(ph);
-            }
+            const double f = z[(size_t)kk + i] * z[i], ph = -tau * evals[i];
+            yr += f * std::cos(ph);
+            yi += f * std::sin(ph);
         }
-        k_used = k + 1;
         double scale = 0.0;
         for (double v : alphas) scale = std::max(scale, std::fabs(v));
         for (double v : betas) scale = std::max(scale, v);
-        const double est = b * std::hypot(y[kk - 1].x, y[kk - 1].y);
-        if (est <= tol || b <= 1e-14 * scale || scale == 0.0) return true;
-        if (k + 1 == kmax) {
+        const double est = b * std::hypot(yr, yi);
+        bool stop = est <= tol || b <= 1e-14 * scale || scale == 0.0;
+        if (!stop && k + 1 == kmax) {
             info.converged = false;
-            return true;
+            stop = true;
         }
-        betas.push_back(b);
-        return false;
+        if (!stop) {
+            betas.push_back(b);
+            return false;
+        }
+        // y = exp(-i tau T) e_0 in full
+        std::vector<int> all(kk);
+        for (int j = 0; j < kk; ++j) all[j] = j;
+        tridiag_eigen(alphas, betas, all, evals, z);
+        y.assign(kk, double2{0.0, 0.0});
+        for (int i = 0; i < kk; ++i) {
+            const double ph = -tau * evals[i], c0 = std::cos(ph), s0 = std::sin(ph);
+            const double w0 = z[i];  // row 0
+            for (int j = 0; j < kk; ++j) {
+                const double f = z[(size_t)j * kk + i] * w0;
+                y[j].x += f * c0;
+                y[j].y += f * s0;
+            }
+        }
+        k_used = kk;
+        return true;
     };
     if (small) {
         // the whole recurrence step in one workgroup (it writes v_{k+1});
