@@ -15,9 +15,10 @@
 // stored [outer][k] so that every lane reads its k-slice with one 16-byte
 // LDS load.  The k index inside a tile is permuted (lane group g handles
 // k = g*S + s for instruction step s): the sum over k is order-free, so A
-// and B only have to agree on the permutation.  Two LDS buffers and two
-// register sets (the global loads run two k-tiles ahead of the MFMAs) give
-// one barrier per k-tile.  Output tiles go to the XCDs in contiguous ranges,
+// and B only have to agree on the permutation.  Two LDS buffers give one
+// barrier per k-tile; the global loads run two k-tiles ahead of the MFMAs
+// (two register sets) in the single-problem kernel and one ahead in the
+// grouped kernel, whose many small products measured faster that way.  Output tiles go to the XCDs in contiguous ranges,
 // and inside a range runs of kGroupM m-tiles sweep the n-tiles, so the tiles
 // an XCD holds at one time share rows of A and columns of B in its L2.
 //
@@ -119,7 +120,8 @@ struct TileSmem {
 };
 
 // One output tile (m0, n0) of batch entry z over k in [kbeg, kend).
-template <typename T, int BM, int BN, int BK, int WM, int WN, bool M3, bool AK, bool BKC>
+// PF: k-tiles the global loads run ahead of the MFMAs (1 or 2).
+template <typename T, int BM, int BN, int BK, int WM, int WN, bool M3, bool AK, bool BKC, int PF>
 __device__ __forceinline__ void gemm_block(const KParams& p, TileSmem<T, BM, BN, BK, AK, BKC>& sm, int m0, int n0,
                                            int64_t zA, int64_t zB, int64_t zC, int kbeg, int kend) {
     using F = Mfma<T>;
@@ -153,9 +155,10 @@ __device__ __forceinline__ void gemm_block(const KParams& p, TileSmem<T, BM, BN,
     const int g = lane / MT;
     const int r = lane % MT;
 
-    // two register sets: the tile two steps ahead is fetched while the next
-    // one is written to LDS
-    T ar[2][AE], ai[2][AE], br[2][BE], bi[2][BE];
+    // PF register sets: with two, the tile two steps ahead is fetched while
+    // the next one is written to LDS
+    static_assert(PF == 1 || PF == 2, "prefetch distance");
+    T ar[PF][AE], ai[PF][AE], br[PF][BE], bi[PF][BE];
     using I0 = std::integral_constant<int, 0>;
     using I1 = std::integral_constant<int, 1>;
 
@@ -219,15 +222,17 @@ __device__ __forceinline__ void gemm_block(const KParams& p, TileSmem<T, BM, BN,
         gload(kbeg, I0{});
         lstore(0, I0{});
     }
-    if (nk > 1) gload(kbeg + BK, I1{});
+    if (PF == 2 && nk > 1) gload(kbeg + BK, std::integral_constant<int, PF - 1>{});
     __syncthreads();
 
-    // tile kt sits in register set kt & 1 and LDS buffer kt & 1
+    // tile kt sits in LDS buffer kt & 1; with PF = 2 it was loaded into
+    // register set kt & 1, with PF = 1 the single set holds the next tile
     auto body = [&](int kt, auto setc) {
-        constexpr int SET = decltype(setc)::value;
-        using Other = std::integral_constant<int, 1 - SET>;
-        const int cur = SET;
-        if (kt + 2 < nk) gload(kbeg + (kt + 2) * BK, setc);
+        constexpr int SET = PF == 2 ? decltype(setc)::value : 0;
+        using Other = std::integral_constant<int, PF == 2 ? 1 - SET : 0>;
+        const int cur = kt & 1;
+        if (PF == 2 && kt + 2 < nk) gload(kbeg + (kt + 2) * BK, std::integral_constant<int, SET>{});
+        if (PF == 1 && kt + 1 < nk) gload(kbeg + (kt + 1) * BK, std::integral_constant<int, 0>{});
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             const int kk = g * S + s;  // permuted k inside the tile
@@ -331,7 +336,7 @@ __global__ void __launch_bounds__(64 * WM * WN) cgemm2_kernel(KParams p) {
     const int z = blockIdx.z / p.ksplit;
     const int kbeg = (blockIdx.z % p.ksplit) * p.kchunk;
     const int kend = min(p.K, kbeg + p.kchunk);
-    gemm_block<T, BM, BN, BK, WM, WN, M3, AK, BKC>(p, sm, m0, n0, (int64_t)z * p.A.stride, (int64_t)z * p.B.stride,
+    gemm_block<T, BM, BN, BK, WM, WN, M3, AK, BKC, 2>(p, sm, m0, n0, (int64_t)z * p.A.stride, (int64_t)z * p.B.stride,
                                                    (int64_t)blockIdx.z * p.strideC, kbeg, kend);
 }
 
@@ -361,7 +366,7 @@ __global__ void __launch_bounds__(64 * WM * WN) cgemm2_grouped_kernel(const GPro
     grouped_tile(tl, p.tiles_m, p.tiles_n, tm, tn);
     const int m0 = tm * BM;
     const int n0 = tn * BN;
-    gemm_block<T, BM, BN, BK, WM, WN, M3, AK, BKC>(p, sm, m0, n0, 0, 0, 0, 0, p.K);
+    gemm_block<T, BM, BN, BK, WM, WN, M3, AK, BKC, 1>(p, sm, m0, n0, 0, 0, 0, 0, p.K);  // measured faster here
 }
 
 // Sum of split-K partials in a fixed order (deterministic), converted to
