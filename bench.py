@@ -304,6 +304,8 @@ def main():
     ap.add_argument("--only-segments", action="store_true",
                     help="run only the segment-parallel N=201 workload and print its timings (for profiling)")
     ap.add_argument("--segments-no-graph", action="store_true", help="segment workload: eager steps only")
+    ap.add_argument("--only-sweep", action="store_true",
+                    help="run only the N=64 2TDVP quench sweep and print its timings (for profiling)")
     ap.add_argument("--grad-steps", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -318,6 +320,12 @@ def main():
 
     if args.copy_calibration:
         copy_calibration(torch)
+        return
+
+    if args.only_sweep:
+        ctx = pkg.Context(0)
+        print(json.dumps({"sweep": sweep_timing(pkg, ctx, args.sweep_steps)}))
+        ctx.close()
         return
 
     if args.only_segments:
