@@ -86,6 +86,12 @@ CASES = [
     (1, 1, 2, 2, 1, 0, 5),
     (0, 96, 96, 2, 8, 0, 8),
     (0, 33, 17, 2, 3, 0, 3),
+    # bonds up to 32 run the fused single-launch kernel; these sit on its edges
+    (2, 32, 32, 2, 20, 20, 20),   # largest fused two-site shape at the quench's w
+    (2, 23, 19, 3, 6, 5, 4),      # d = 3: D = 9 output indices per row
+    (2, 32, 33, 2, 4, 4, 4),      # one past the limit: three-stage pipeline
+    (1, 32, 1, 2, 9, 0, 2),
+    (0, 7, 32, 2, 5, 0, 5),
 ]
 
 
@@ -183,6 +189,15 @@ def test_apply_heff_rejects_bad_arguments(ctx):
     with pytest.raises(pkg.TDVPError) as e:  # zero-site needs wl == wr
         pkg.apply_heff(ctx, L, R, theta)
     assert e.value.status == 2
+    # out must not alias an input (the fused small-bond kernel reads every row
+    # of theta while writing rows of out); small and large shapes alike
+    for chi in (4, 40):
+        L = torch.zeros((3, chi, chi), dtype=torch.complex128, device="cuda")
+        R = torch.zeros((3, chi, chi), dtype=torch.complex128, device="cuda")
+        theta = torch.zeros((chi, chi), dtype=torch.complex128, device="cuda")
+        with pytest.raises(pkg.TDVPError) as e:
+            pkg.apply_heff(ctx, L, R, theta, out=theta)
+        assert e.value.status == 1  # TDVP_E_ARG
 
 
 TILE_CFGS = {"c64": [2, 9, 10, 12, 13, 14, 15, 16], "c128": [2, 9, 12, 15, 16]}
