@@ -124,6 +124,38 @@ def cpu_baseline(wl, W, D=1024, budget_s=15.0, max_reps=10):
     }
 
 
+def ising_timing(pkg, ctx, wl):
+    """1TDVP quench of the N=10 long-range Ising chain (exact MPO, w = 11).
+
+    H = sum_{i<j} |i-j|^-3 sigma^z_i sigma^z_j + sum_i sigma^x_i from all spins
+    up, padded to chi = (1, 2, 4, 8, 16, 32, 16, 8, 4, 2, 1); dt = 0.01, 100
+    steps, complex128 and complex64.  Per step median time; <sigma^z_5>,
+    <sigma^z_6> and the energy at the end, compared between the precisions.
+    """
+    import numpy as np
+    p = wl.ISING_N10
+    N = p["N"]
+    sx, sz = (np.array(q, dtype=np.complex128) for q in (pkg.PAULI_X, pkg.PAULI_Z))
+    mpo = pkg.MPO.longrange(ctx, N, [(p["J"], sz, sz)], coupling=[r ** -p["alpha"] for r in range(1, N)],
+                            onsite=sx, h=p["h"])
+    res, obs = {}, {}
+    for comp in ("c128", "c64"):
+        mps = pkg.MPS.init(ctx, N, 2, wl.full_rank_bonds(N, 2, p["chi_cap"]), basis_state=[0] * N)
+        opts = pkg.TDVPOptions(compute=comp)
+        times = []
+        for _ in range(p["steps"]):
+            times.append(pkg.tdvp1_step(ctx, mps, mpo, p["dt"], opts)["seconds"])
+        z = pkg.expect(ctx, mps, [4, 5], sz).real
+        obs[comp] = np.array([z[0], z[1], pkg.energy(ctx, mps, mpo).real])
+        res[comp] = {"s_per_step_median": round(float(np.median(times)), 5),
+                     "sz5": float(z[0]), "sz6": float(z[1]), "energy": float(obs[comp][2])}
+        mps.close()
+    mpo.close()
+    res["max_abs_obs_diff_c64_vs_c128"] = float(np.max(np.abs(obs["c64"] - obs["c128"])))
+    res["workload"] = "1TDVP, N=10 long-range Ising (alpha=3, J=h=1, exact MPO w=11), chi<=32, dt=0.01, 100 steps"
+    return res
+
+
 def sweep_timing(pkg, ctx, steps=40):
     """2TDVP quench of the N=64 1/r^2 XXX chain (K = 6 exponentials, w = 20).
 
@@ -393,6 +425,14 @@ def main():
                         "kernel": k128, "kernel_tflops": round(a128, 2),
                         "kernel_frac_of_fp64_peak": round(a128 / PEAK_FP64_MFMA_TFLOPS, 4)}
         line["speedup_fp32_vs_fp64"] = round(ms128 / ms64, 2)
+        progress("complex64 in the 4M form")
+        x4 = device_inputs(torch, wl, W, D, w, torch.complex64)
+        ctx.set_gemm_form(4)
+        ms4m, _, _ = time_heff(pkg, ctx, torch, x4, max(3, args.steps // 2), 1)
+        ctx.set_gemm_form(0)
+        del x4
+        line["c64_4m"] = {"gflops": round(F / (ms4m * 1e-3) * 1e-9, 1), "ms_per_step": round(ms4m, 4),
+                          "speedup_3m_vs_4m": round(ms4m / ms64, 2)}
         progress("D sweep")
         byD = {}
         for Dx in (128, 256, 512):
@@ -405,6 +445,8 @@ def main():
             byD[str(Dx)] = r
         byD["1024"] = {"c64": line["value"], "c128": line["fp64"]["gflops"]}
         line["gflops_by_D"] = byD
+        progress("1TDVP N=10 Ising timing")
+        line["ising_n10"] = ising_timing(pkg, ctx, wl)
         if args.sweep_steps > 0:
             progress("2TDVP sweep timing")
             line["sweep"] = sweep_timing(pkg, ctx, args.sweep_steps)

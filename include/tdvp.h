@@ -88,6 +88,12 @@ const char* tdvp_version(void);
  * bytes = summed algorithmic work (8 real flops per complex multiply-add;
  * compulsory operand bytes), count = launches; *n_out = entries written. */
 int tdvp_profile_enable(tdvp_ctx ctx, int on);
+/* Real-GEMM form of the complex products in apply_heff, env_update and
+ * apply_heff_batched on this context: 0 = default (3M for TDVP_C64, 4M for
+ * TDVP_C128), 3 = three real products (C64 only; C128 always uses 4M),
+ * 4 = four real products.  TDVP_E_ARG for any other value.  Time steps take
+ * the form from their options. */
+int tdvp_ctx_set_gemm_form(tdvp_ctx ctx, int form);
 int tdvp_profile_read(tdvp_ctx ctx, int max_entries, char* names, double* ms, double* flops,
                       double* bytes, long* count, int* n_out);
 

@@ -112,6 +112,11 @@ class Context:
         """Bracket every library kernel launch with HIP events."""
         _check(self.handle, _lib.load().tdvp_profile_enable(self.handle, int(on)))
 
+    def set_gemm_form(self, form: int):
+        """Complex-GEMM form of apply_heff / env_update / apply_heff_batched on
+        this context: 0 default (3M for complex64), 3 or 4."""
+        _check(self.handle, _lib.load().tdvp_ctx_set_gemm_form(self.handle, int(form)))
+
     def profile_read(self) -> dict:
         """{kernel: {ms, flops, bytes, count}} since the last read (synchronises)."""
         n = 256

@@ -39,7 +39,7 @@ struct AdjointArgs {
 
 void heff_adjoint(tdvp_ctx ctx, const AdjointArgs& a) {
     const bool fp64 = a.dt == Dt::C128;
-    const int form = fp64 ? 4 : 3;
+    const int form = raw_gemm_form(ctx, fp64);
     const int D = a.nsite == 0 ? 1 : (a.nsite == 1 ? a.d : a.d * a.d);
     const size_t esz = elem_bytes(a.dt);
     const int64_t chil = a.chil, chir = a.chir;

@@ -18,6 +18,16 @@ GemmOperand op(const void* p, Dt dt, int64_t ld, bool kcontig, bool conj = false
     return o;
 }
 
+}  // namespace
+
+// Complex-GEMM form of the raw-pointer entry points (tdvp_ctx_set_gemm_form).
+int raw_gemm_form(tdvp_ctx ctx, bool fp64) {
+    if (fp64) return 4;
+    return ctx->gemm_form == 0 ? 3 : ctx->gemm_form;
+}
+
+namespace {
+
 int pow_int(int b, int e) {
     int r = 1;
     for (int i = 0; i < e; ++i) r *= b;
@@ -300,7 +310,7 @@ int apply_heff(tdvp_ctx ctx, int nsite, tdvp_dtype dtype, int chil, int chir, in
         Mop m;
         const int kind = nsite == 0 ? 0 : (nsite == 1 ? 1 : 2);
         mop_make(ctx, m, kind, W1, W2, dt, wl, nsite == 2 ? wm : wl, wr, d, fp64, false);
-        HeffArgs a{nsite, chil, chir, d, wl, wr, L, R, dt, &m, fp64, fp64 ? 4 : 3};
+        HeffArgs a{nsite, chil, chir, d, wl, wr, L, R, dt, &m, fp64, raw_gemm_form(ctx, fp64)};
         heff_apply(ctx, a, theta, dt, out, dt);
     });
 }
@@ -374,9 +384,9 @@ int apply_heff_batched(tdvp_ctx ctx, tdvp_dtype dtype, int n, const tdvp_heff_de
         }
         GroupedGemm A, B;
         GroupedWStage W;
-        grouped_gemm_plan(ctx, ga, fp64, fp64 ? 4 : 3, A);
+        grouped_gemm_plan(ctx, ga, fp64, raw_gemm_form(ctx, fp64), A);
         grouped_wstage_plan(ctx, ws, W);
-        grouped_gemm_plan(ctx, gb, fp64, fp64 ? 4 : 3, B);
+        grouped_gemm_plan(ctx, gb, fp64, raw_gemm_form(ctx, fp64), B);
         grouped_gemm_run(ctx, A);
         grouped_wstage_run(ctx, W);
         grouped_gemm_run(ctx, B);
@@ -398,7 +408,7 @@ int env_update(tdvp_ctx ctx, int dir, tdvp_dtype dtype, int chil, int chir, int 
         const bool fp64 = dt == Dt::C128;
         Mop m;
         mop_make(ctx, m, dir == 1 ? 1 : 3, W, nullptr, dt, wl, wl, wr, d, fp64, false);
-        EnvArgs a{chil, chir, chil, chir, d, wl, wr, A, A, dt, &m, fp64, fp64 ? 4 : 3};
+        EnvArgs a{chil, chir, chil, chir, d, wl, wr, A, A, dt, &m, fp64, raw_gemm_form(ctx, fp64)};
         if (dir == 1) env_left(ctx, a, env_in, dt, env_out, dt);
         else env_right(ctx, a, env_in, dt, env_out, dt);
     });

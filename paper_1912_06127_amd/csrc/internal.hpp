@@ -40,6 +40,8 @@ struct HeffArgs {
     int form;
 };
 void heff_apply(tdvp_ctx ctx, const HeffArgs& a, const void* x, Dt x_dt, void* y, Dt y_dt);
+// GEMM form of the raw-pointer entry points: 4 for FP64, else the context's choice (default 3).
+int raw_gemm_form(tdvp_ctx ctx, bool fp64);
 double heff_flops(int nsite, int chil, int chir, int d, int wl, int wr);
 
 // Left environment update with separate bra and ket tensors (Sec. III A):

@@ -186,6 +186,12 @@ int tdvp_profile_enable(tdvp_ctx ctx, int on) {
     return TDVP_OK;
 }
 
+int tdvp_ctx_set_gemm_form(tdvp_ctx ctx, int form) {
+    if (!ctx || (form != 0 && form != 3 && form != 4)) return TDVP_E_ARG;
+    ctx->gemm_form = form;
+    return TDVP_OK;
+}
+
 int tdvp_profile_read(tdvp_ctx ctx, int max_entries, char* names, double* ms, double* flops,
                       double* bytes, long* count, int* n_out) {
     if (!ctx || !n_out || (max_entries > 0 && (!names || !ms || !flops || !bytes || !count))) return TDVP_E_ARG;

@@ -107,6 +107,25 @@ def test_apply_heff_matches_oracle(ctx, dt, case):
     assert rel_err(y, ref) <= TOL[dt]
 
 
+def test_gemm_form_option_matches_oracle(ctx):
+    """complex64 in the 4M form (four real products) against the oracle, for
+    the fused small-bond path and the GEMM pipeline; bad forms are refused."""
+    import paper_1912_06127_amd as pkg
+    for case in [(2, 12, 9, 2, 5, 4, 6), (2, 70, 66, 2, 5, 4, 6), (1, 90, 80, 2, 6, 0, 5)]:
+        print(f"apply_heff 4M {case}", flush=True)
+        beta, W1, W2, gamma, theta = random_case(23, *case)
+        ref = oracle_heff(case[0], beta, W1, W2, gamma, theta)
+        ctx.set_gemm_form(4)
+        try:
+            y = run_gpu(ctx, "c64", beta, W1, W2, gamma, theta)
+        finally:
+            ctx.set_gemm_form(0)
+        assert rel_err(y, ref) <= TOL["c64"]
+    with pytest.raises(pkg.TDVPError) as e:
+        ctx.set_gemm_form(5)
+    assert e.value.status == 1
+
+
 @pytest.mark.parametrize("dt", ["c128", "c64"])
 def test_apply_heff_multi_tile_shape(ctx, dt):
     # 512-wide bond: the large-tile GEMM configuration of both precisions
