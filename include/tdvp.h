@@ -206,6 +206,15 @@ int tdvp1_step(tdvp_ctx ctx, tdvp_mps mps, tdvp_mpo mpo, double dt,
  * evolved once by the full dt.  Same canonical-form contract as tdvp1_step. */
 int tdvp2_step(tdvp_ctx ctx, tdvp_mps mps, tdvp_mpo mpo, double dt,
                const tdvp_opts* opts, tdvp_stats* stats);
+/* One step of the hybrid scheme the paper's Discussion proposes: a two-site
+ * step while the bond dimensions can still grow, a one-site step once
+ * chi_max is saturated, i.e. once every bond j = 1..N-1 holds
+ * min(opts->chi_max, d^min(j, N-j)) (the largest dimension the truncation
+ * and the Hilbert space allow; one-site steps keep it so).  *one_site
+ * (nullable) is set to 1 when the one-site step ran, else 0.  Same
+ * canonical-form contract and errors as tdvp1_step / tdvp2_step. */
+int tdvp_hybrid_step(tdvp_ctx ctx, tdvp_mps mps, tdvp_mpo mpo, double dt,
+                     const tdvp_opts* opts, tdvp_stats* stats, int* one_site);
 
 /* ------------------------------------- segment-parallel two-site TDVP ---- */
 /* Sec. III B (Fig. partitioning) on one device.  The state is held in the

@@ -173,3 +173,21 @@ def tdvp2_step(st: MPSState, dt: float, tr: Truncation, kmax: int = 40, tol: flo
         st.gamma[j] = update_right(st.gamma[j + 1], T[j + 1], st.W[j + 1])
     st.stats.chi_peak = max(st.stats.chi_peak, max(A.shape[2] for A in T))
     return st
+
+
+def chi_saturated(tensors, chi_max: int) -> bool:
+    """True when every bond j = 1..N-1 holds min(chi_max, d^min(j, N-j)):
+    the bond dimensions can grow no further (Sec. Discussion, hybrid scheme)."""
+    N, d = len(tensors), tensors[0].shape[1]
+    return all(tensors[j - 1].shape[2] >= min(chi_max, d ** min(j, N - j)) for j in range(1, N))
+
+
+def hybrid_step(st: MPSState, dt: float, tr: Truncation, kmax: int = 40, tol: float = 1e-13):
+    """The hybrid scheme proposed in the paper's Discussion: a two-site step
+    while chi_max is not saturated, a one-site step once it is.  Returns
+    True when the one-site step ran."""
+    if chi_saturated(st.T, tr.chi_max):
+        tdvp1_step(st, dt, kmax, tol)
+        return True
+    tdvp2_step(st, dt, tr, kmax, tol)
+    return False

@@ -89,6 +89,7 @@ SIGNATURES = {
     "tdvp_opts_default": (_I, [C.POINTER(Opts)]),
     "tdvp1_step": (_I, [_P, _P, _P, _D, C.POINTER(Opts), C.POINTER(Stats)]),
     "tdvp2_step": (_I, [_P, _P, _P, _D, C.POINTER(Opts), C.POINTER(Stats)]),
+    "tdvp_hybrid_step": (_I, [_P, _P, _P, _D, C.POINTER(Opts), C.POINTER(Stats), C.POINTER(_I)]),
     "apply_heff": (_I, [_P, _I, _I, _I, _I, _I, _I, _I, _I, _P, _P, _P, _P, _P, _P]),
     "apply_heff_batched": (_I, [_P, _I, _I, C.POINTER(HeffDesc)]),
     "env_update": (_I, [_P, _I, _I, _I, _I, _I, _I, _I, _P, _P, _P, _P]),

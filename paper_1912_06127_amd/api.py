@@ -444,6 +444,20 @@ def tdvp2_step(ctx: Context, mps: MPS, mpo: MPO, dt: float, opts: TDVPOptions | 
     return st.as_dict()
 
 
+def tdvp_hybrid_step(ctx: Context, mps: MPS, mpo: MPO, dt: float, opts: TDVPOptions | None = None) -> dict:
+    """Two-site step until chi_max is saturated on every bond, one-site step
+    after that (the hybrid scheme of the paper's Discussion).  The returned
+    statistics carry "one_site": True when the one-site step ran."""
+    o = (opts or TDVPOptions()).to_c()
+    st = Stats()
+    one = C.c_int(0)
+    _check(ctx.handle, _lib.load().tdvp_hybrid_step(ctx.handle, mps.handle, mpo.handle, float(dt), C.byref(o),
+                                                    C.byref(st), C.byref(one)))
+    d = st.as_dict()
+    d["one_site"] = bool(one.value)
+    return d
+
+
 @dataclass
 class SegmentOptions:
     compute: str = "c64"         # matvec / environment precision (fixed at construction)

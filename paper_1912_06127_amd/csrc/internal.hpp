@@ -80,6 +80,9 @@ KrylovInfo expm_krylov(tdvp_ctx ctx, const MatVec& op, double2* theta, int64_t n
 void tridiag_eigen(const std::vector<double>& alpha, const std::vector<double>& beta, const std::vector<int>& rows,
                    std::vector<double>& evals, std::vector<double>& z);
 
+// True when every bond j = 1..N-1 of chi[0..N] holds min(chi_max, d^min(j, N-j)).
+bool chi_saturated(const std::vector<int>& chi, int d, int chi_max);
+
 // Truncation rule of a two-site split (Sec. III C, Eq. discweight; Sec. III D
 // relative cut): chi_w = smallest rank whose discarded weight is <= w_max,
 // chi_eps = count of s >= eps s_1, chi = max(1, min(chi_w, chi_max, chi_eps)),

@@ -10,6 +10,16 @@
 
 using namespace tdvp;
 
+bool tdvp::chi_saturated(const std::vector<int>& chi, int d, int chi_max) {
+    const int N = (int)chi.size() - 1;
+    for (int j = 1; j < N; ++j) {
+        int64_t cap = 1;  // min(chi_max, d^min(j, N - j)) without overflow
+        for (int e = 0; e < std::min(j, N - j) && cap < chi_max; ++e) cap *= d;
+        if (chi[j] < std::min<int64_t>(cap, chi_max)) return false;
+    }
+    return true;
+}
+
 int tdvp::truncation_rank(const std::vector<double>& s, const TruncRule& r, double& w) {
     const int full = (int)s.size();
     std::vector<double> tail(full + 1, 0.0);
@@ -395,6 +405,20 @@ int tdvp2_step(tdvp_ctx ctx, tdvp_mps mps, tdvp_mpo mpo, double dt, const tdvp_o
         }
         s.finish(t0);
     });
+}
+
+int tdvp_hybrid_step(tdvp_ctx ctx, tdvp_mps mps, tdvp_mpo mpo, double dt, const tdvp_opts* opts,
+                     tdvp_stats* stats, int* one_site) {
+    if (!ctx) return TDVP_E_ARG;
+    bool saturated = false;
+    const int rc = guarded(ctx, [&] {
+        TDVP_REQUIRE(mps && mpo && opts, TDVP_E_ARG, "tdvp_hybrid_step: null argument");
+        TDVP_REQUIRE(opts->chi_max >= 1, TDVP_E_ARG, "chi_max must be >= 1");
+        saturated = chi_saturated(mps->chi, mps->d, opts->chi_max);
+    });
+    if (rc != TDVP_OK) return rc;
+    if (one_site) *one_site = saturated ? 1 : 0;
+    return saturated ? tdvp1_step(ctx, mps, mpo, dt, opts, stats) : tdvp2_step(ctx, mps, mpo, dt, opts, stats);
 }
 
 int norm2(tdvp_ctx ctx, tdvp_mps mps, double* out) {

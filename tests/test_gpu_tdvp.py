@@ -194,6 +194,33 @@ def test_tdvp2_neel_quench_tracks_oracle_over_many_steps(ctx, dt_):
         assert st_o.stats.w_total > 1e-7  # truncation is active
 
 
+@pytest.mark.parametrize("dt_", ["c128", "c64"])
+def test_hybrid_step_matches_oracle(ctx, dt_):
+    """Hybrid scheme (two-site until chi_max is saturated, then one-site):
+    same switch step as the oracle and observables to the bar every step."""
+    import paper_1912_06127_amd as pkg
+    N = 10
+    print(f"hybrid XXX N={N} {dt_}", flush=True)
+    c, lam = xxx_fit(N, 3)
+    Ws = ompo.mpo_exponentials(N, c, lam, spin.xxx_pairs())
+    bits = [i % 2 for i in range(N)]
+    bits[N // 2 - 1] ^= 1
+    st_o = otdvp.MPSState(omps.padded_product_state(bits, [1] * (N + 1)), Ws)
+    tr = otdvp.Truncation(chi_max=4, w_max=0.0, eps=1e-14)
+    W = pkg.MPO.longrange(ctx, N, spin.xxx_pairs(), c=c, lam=lam)
+    m = pkg.MPS.init(ctx, N, 2, [1] * (N + 1), basis_state=bits)
+    opts = pkg.TDVPOptions(compute=dt_, chi_max=4, w_max=0.0, eps_rel=1e-14)
+    kinds_o, kinds_g = [], []
+    for s in range(16):
+        kinds_o.append(otdvp.hybrid_step(st_o, 0.05, tr))
+        kinds_g.append(pkg.tdvp_hybrid_step(ctx, m, W, 0.05, opts)["one_site"])
+        z = pkg.expect(ctx, m, list(range(N)), spin.SZ).real
+        zref = omps.expect_sites(st_o.T, spin.SZ).real
+        assert np.max(np.abs(z - zref)) <= OBS_TOL[dt_], (s, np.max(np.abs(z - zref)))
+    assert kinds_g == kinds_o and any(kinds_o) and not kinds_o[0]
+    assert m.chi == [1] + [A.shape[2] for A in st_o.T]
+
+
 def test_tdvp2_full_rank_matches_exact_evolution(ctx):
     import paper_1912_06127_amd as pkg
     N = 8

@@ -341,3 +341,56 @@ def test_spin_one_mpo_equals_kronecker_hamiltonian():
     Ws2 = mpo.mpo_exponentials(N, c, lam, pairs, Sz, 0.3)
     H2 = spin.longrange_hamiltonian(N, g, pairs, Sz, 0.3)
     assert np.max(np.abs(mpo.mpo_to_dense(Ws2) - H2)) < 1e-12
+
+
+def test_chi_saturation_rule():
+    """Saturated means every bond at min(chi_max, d^min(j, N-j)) (hybrid scheme)."""
+    full = [np.zeros((a, 2, b)) for a, b in zip(wl.full_rank_bonds(6, 2)[:-1], wl.full_rank_bonds(6, 2)[1:])]
+    assert tdvp.chi_saturated(full, 1 << 30)            # 1 2 4 8 4 2 1
+    capped = [np.zeros((a, 2, b)) for a, b in zip(wl.full_rank_bonds(6, 2, 3)[:-1], wl.full_rank_bonds(6, 2, 3)[1:])]
+    assert tdvp.chi_saturated(capped, 3) and not tdvp.chi_saturated(capped, 4)
+    product = [np.zeros((1, 2, 1)) for _ in range(6)]
+    assert not tdvp.chi_saturated(product, 2)
+    assert tdvp.chi_saturated(product, 1)
+
+
+def test_hybrid_saturated_start_is_one_site_and_exact():
+    """A product state padded to full bond dimension is saturated from the
+    start: every hybrid step is one-site, and one-site TDVP at full rank is
+    exact, so the run equals exact evolution."""
+    N = 8
+    c, lam, g = fitted_xxx(N, 3)
+    Ws = mpo.mpo_exponentials(N, c, lam, spin.xxx_pairs())
+    H = spin.longrange_hamiltonian(N, g, spin.xxx_pairs())
+    bits = [i % 2 for i in range(N)]
+    T = mps.padded_product_state(bits, wl.full_rank_bonds(N, 2))
+    psi0 = mps.to_dense(T)
+    st = tdvp.MPSState(T, Ws)
+    kinds = [tdvp.hybrid_step(st, 0.05, tdvp.Truncation()) for _ in range(6)]
+    assert all(kinds)
+    psi = spin.ExactEvolution(H).evolve(psi0, 0.3)
+    assert np.linalg.norm(mps.to_dense(st.T) - psi) < 1e-9
+
+
+def test_hybrid_truncated_keeps_chi_max_and_conserves_energy_after_switch():
+    """Under truncation the switch happens when every bond reaches chi_max;
+    after it the bond dimensions stay fixed and, as 1TDVP is a projected
+    Hamiltonian flow, the energy and norm are conserved (up to Lanczos error)."""
+    N = 10
+    c, lam, _ = fitted_xxx(N, 3)
+    Ws = mpo.mpo_exponentials(N, c, lam, spin.xxx_pairs())
+    bits = [i % 2 for i in range(N)]
+    bits[N // 2 - 1] ^= 1
+    st = tdvp.MPSState(mps.padded_product_state(bits, [1] * (N + 1)), Ws)
+    tr = tdvp.Truncation(chi_max=4, w_max=0.0, eps=1e-14)
+    kinds, energies, norms = [], [], []
+    for _ in range(16):
+        kinds.append(tdvp.hybrid_step(st, 0.05, tr))
+        energies.append(mps.mpo_expectation(st.T, Ws).real / mps.norm2(st.T))
+        norms.append(mps.norm2(st.T))
+    first = kinds.index(True)
+    assert first > 0 and all(kinds[first:])
+    chi = [A.shape[2] for A in st.T[:-1]]
+    assert chi == [min(4, 2 ** min(j, N - j)) for j in range(1, N)]
+    assert max(abs(e - energies[first]) for e in energies[first:]) < 1e-10
+    assert max(abs(n - norms[first]) for n in norms[first:]) < 1e-12
