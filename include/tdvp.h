@@ -215,6 +215,19 @@ int tdvp2_step(tdvp_ctx ctx, tdvp_mps mps, tdvp_mpo mpo, double dt,
  * canonical-form contract and errors as tdvp1_step / tdvp2_step. */
 int tdvp_hybrid_step(tdvp_ctx ctx, tdvp_mps mps, tdvp_mpo mpo, double dt,
                      const tdvp_opts* opts, tdvp_stats* stats, int* one_site);
+/* One sweep of two-site DMRG for the ground state (the quench experiments of
+ * Sec. IV start from two-site DMRG ground states; the sweep uses the same
+ * environments, effective Hamiltonian and truncated splits as a 2TDVP step,
+ * Sec. III A): each pair in a left-to-right and a right-to-left pass is
+ * replaced by the lowest Ritz vector of its H_eff (Lanczos with full
+ * reorthogonalisation, stopped when the Ritz residual is <= krylov_tol or
+ * after krylov_max vectors) and split with the truncation of opts.  The
+ * state is renormalised at the end; *energy (nullable) = the last Ritz
+ * value, the variational energy of the state after the sweep.  Same
+ * canonical-form contract as tdvp2_step; stats as for a time step (flags
+ * bit 0: a Lanczos run hit krylov_max; TDVP_E_NOCONV with strict). */
+int dmrg2_sweep(tdvp_ctx ctx, tdvp_mps mps, tdvp_mpo mpo, const tdvp_opts* opts,
+                tdvp_stats* stats, double* energy);
 
 /* ------------------------------------- segment-parallel two-site TDVP ---- */
 /* Sec. III B (Fig. partitioning) on one device.  The state is held in the

@@ -90,6 +90,7 @@ SIGNATURES = {
     "tdvp1_step": (_I, [_P, _P, _P, _D, C.POINTER(Opts), C.POINTER(Stats)]),
     "tdvp2_step": (_I, [_P, _P, _P, _D, C.POINTER(Opts), C.POINTER(Stats)]),
     "tdvp_hybrid_step": (_I, [_P, _P, _P, _D, C.POINTER(Opts), C.POINTER(Stats), C.POINTER(_I)]),
+    "dmrg2_sweep": (_I, [_P, _P, _P, C.POINTER(Opts), C.POINTER(Stats), C.POINTER(_D)]),
     "apply_heff": (_I, [_P, _I, _I, _I, _I, _I, _I, _I, _I, _P, _P, _P, _P, _P, _P]),
     "apply_heff_batched": (_I, [_P, _I, _I, C.POINTER(HeffDesc)]),
     "env_update": (_I, [_P, _I, _I, _I, _I, _I, _I, _I, _P, _P, _P, _P]),

@@ -444,6 +444,20 @@ def tdvp2_step(ctx: Context, mps: MPS, mpo: MPO, dt: float, opts: TDVPOptions | 
     return st.as_dict()
 
 
+def dmrg2_sweep(ctx: Context, mps: MPS, mpo: MPO, opts: TDVPOptions | None = None) -> dict:
+    """One two-site DMRG sweep towards the ground state; the statistics carry
+    "energy", the variational energy after the sweep (the state is
+    renormalised)."""
+    o = (opts or TDVPOptions()).to_c()
+    st = Stats()
+    e = C.c_double(0.0)
+    _check(ctx.handle, _lib.load().dmrg2_sweep(ctx.handle, mps.handle, mpo.handle, C.byref(o), C.byref(st),
+                                               C.byref(e)))
+    d = st.as_dict()
+    d["energy"] = e.value
+    return d
+
+
 def tdvp_hybrid_step(ctx: Context, mps: MPS, mpo: MPO, dt: float, opts: TDVPOptions | None = None) -> dict:
     """Two-site step until chi_max is saturated on every bond, one-site step
     after that (the hybrid scheme of the paper's Discussion).  The returned

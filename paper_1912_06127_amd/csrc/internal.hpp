@@ -74,6 +74,12 @@ struct KrylovInfo {
 // theta <- exp(-i tau H) theta with H Hermitian (Sec. III A, Lanczos).
 KrylovInfo expm_krylov(tdvp_ctx ctx, const MatVec& op, double2* theta, int64_t n, double tau,
                        int kmax, double tol);
+// theta <- normalised Ritz vector of the lowest Ritz value of H in the
+// Krylov space of theta (Lanczos with full reorthogonalisation); stops when
+// the residual norm of that Ritz pair is <= tol.  *energy (nullable) = the
+// Ritz value.  theta must not vanish for a meaningful result.
+KrylovInfo ground_krylov(tdvp_ctx ctx, const MatVec& op, double2* theta, int64_t n, int kmax, double tol,
+                         double* energy);
 // Eigen-decomposition of the symmetric tridiagonal k x k matrix with
 // diagonal alpha and off-diagonal beta (host): evals[k] (unordered) and
 // z[r*k + c] = entry rows[r] of the c-th eigenvector, for the listed rows.

@@ -85,8 +85,14 @@ void tridiag_eigen(const std::vector<double>& alpha, const std::vector<double>& 
     evals = d;
 }
 
-KrylovInfo expm_krylov(tdvp_ctx ctx, const MatVec& op, double2* theta, int64_t n, double tau,
-                       int kmax, double tol) {
+namespace {
+
+enum class KrylovMode { Exp, Ground };
+
+// Lanczos driver.  Exp: theta <- exp(-i tau H) theta.  Ground: theta <- the
+// normalised Ritz vector of the lowest Ritz value, *energy = that value.
+KrylovInfo krylov_run(tdvp_ctx ctx, const MatVec& op, double2* theta, int64_t n, double tau, int kmax, double tol,
+                      KrylovMode mode, double* energy) {
     KrylovInfo info;
     TDVP_REQUIRE(kmax >= 1, TDVP_E_ARG, "krylov_max must be >= 1");
     if (n == 0) return info;
@@ -114,6 +120,37 @@ KrylovInfo expm_krylov(tdvp_ctx ctx, const MatVec& op, double2* theta, int64_t n
     std::vector<double> alphas, betas, evals, z;
     std::vector<double2> y;
     int k_used = 0;
+    // Ground mode: the residual norm of the lowest Ritz pair is
+    // beta_k |e_{kk-1}^T z_min| (z_min its eigenvector of T_kk).
+    auto consume_ground = [&](int k, double b, int kk) -> bool {
+        tridiag_eigen(alphas, betas, {kk - 1}, evals, z);
+        int imin = 0;
+        for (int i = 1; i < kk; ++i)
+            if (evals[i] < evals[imin]) imin = i;
+        double scale = 0.0;
+        for (double v : alphas) scale = std::max(scale, std::fabs(v));
+        for (double v : betas) scale = std::max(scale, v);
+        bool stop = b * std::fabs(z[imin]) <= tol || b <= 1e-14 * scale || scale == 0.0;
+        if (!stop && k + 1 == kmax) {
+            info.converged = false;
+            stop = true;
+        }
+        if (!stop) {
+            betas.push_back(b);
+            return false;
+        }
+        std::vector<int> all(kk);
+        for (int j = 0; j < kk; ++j) all[j] = j;
+        tridiag_eigen(alphas, betas, all, evals, z);
+        imin = 0;
+        for (int i = 1; i < kk; ++i)
+            if (evals[i] < evals[imin]) imin = i;
+        if (energy) *energy = evals[imin];
+        y.assign(kk, double2{0.0, 0.0});
+        for (int j = 0; j < kk; ++j) y[j].x = z[(size_t)j * kk + imin];
+        k_used = kk;
+        return true;
+    };
     // Consumes iteration k's alpha_k and ||w||^2; returns true when the
     // iteration stops here.
     auto consume = [&](int k, double a, double nn) -> bool {
@@ -123,6 +160,7 @@ KrylovInfo expm_krylov(tdvp_ctx ctx, const MatVec& op, double2* theta, int64_t n
                      "Krylov: non-finite value in H_eff application");
         alphas.push_back(a);
         const int kk = (int)alphas.size();
+        if (mode == KrylovMode::Ground) return consume_ground(k, b, kk);
         // e_{kk-1}^T exp(-i tau T) e_0 needs the first and last eigenvector rows only
         tridiag_eigen(alphas, betas, {0, kk - 1}, evals, z);
         double yr = 0.0, yi = 0.0;
@@ -169,7 +207,7 @@ KrylovInfo expm_krylov(tdvp_ctx ctx, const MatVec& op, double2* theta, int64_t n
         small_normalize(theta, V, n, sc, s);  // read back with the first batch
         // consecutive exponentials of one vector length need similar
         // iteration counts: the first batch is the count of the last one
-        int& hint = ctx->krylov_hint[n];
+        int& hint = ctx->krylov_hint[mode == KrylovMode::Exp ? n : -n];
         const int first = hint > 0 ? std::max(2, hint) : kFirstBatch;
         int queued = 0;
         bool stop = false;
@@ -209,9 +247,11 @@ KrylovInfo expm_krylov(tdvp_ctx ctx, const MatVec& op, double2* theta, int64_t n
             scale_copy(V + (size_t)(k + 1) * n, w, 1.0 / betas.back(), n, s);
         }
     }
-    for (auto& c : y) {
-        c.x *= beta0;
-        c.y *= beta0;
+    if (mode == KrylovMode::Exp) {  // the Ritz vector of Ground mode stays normalised
+        for (auto& c : y) {
+            c.x *= beta0;
+            c.y *= beta0;
+        }
     }
     // Pinned staging: the copy runs asynchronously, and every call
     // synchronises the stream before it writes the staging buffer again.
@@ -221,6 +261,17 @@ KrylovInfo expm_krylov(tdvp_ctx ctx, const MatVec& op, double2* theta, int64_t n
     combine(theta, V, n, k_used, coef, n, s);
     info.k = k_used;
     return info;
+}
+
+}  // namespace
+
+KrylovInfo expm_krylov(tdvp_ctx ctx, const MatVec& op, double2* theta, int64_t n, double tau, int kmax, double tol) {
+    return krylov_run(ctx, op, theta, n, tau, kmax, tol, KrylovMode::Exp, nullptr);
+}
+
+KrylovInfo ground_krylov(tdvp_ctx ctx, const MatVec& op, double2* theta, int64_t n, int kmax, double tol,
+                         double* energy) {
+    return krylov_run(ctx, op, theta, n, 0.0, kmax, tol, KrylovMode::Ground, energy);
 }
 
 }  // namespace tdvp

@@ -131,6 +131,24 @@ struct Stepper {
         }
     }
 
+    // theta <- lowest Ritz vector of the local operator (normalised); returns its Ritz value.
+    double ground(const HeffArgs& a, double2* theta) {
+        const int D = a.nsite == 0 ? 1 : (a.nsite == 1 ? m->d : m->d * m->d);
+        const int64_t n = (int64_t)a.chil * D * a.chir;
+        const double f = heff_flops(a.nsite, a.chil, a.chir, m->d, a.wl, a.wr);
+        MatVec op = [&](const double2* x, double2* y) { heff_apply(ctx, a, x, Dt::C128, y, Dt::C128); };
+        double e = 0.0;
+        KrylovInfo ki = ground_krylov(ctx, op, theta, n, o.krylov_max, o.krylov_tol, &e);
+        st.matvecs += ki.matvecs;
+        st.flops += f * ki.matvecs;
+        st.krylov_max_used = std::max(st.krylov_max_used, ki.k);
+        if (!ki.converged) {
+            st.flags |= 1;
+            TDVP_REQUIRE(!o.strict, TDVP_E_NOCONV, "Lanczos ground state did not converge within krylov_max");
+        }
+        return e;
+    }
+
     HeffArgs h1(int j) {
         return HeffArgs{1, m->chi[j], m->chi[j + 1], m->d, W->w[j], W->w[j + 1], m->L[j].ptr, m->R[j].ptr,
                         edt, &W->mop(1, j, fp64), fp64, form};
@@ -281,6 +299,47 @@ struct Stepper {
         }
     }
 
+    // ------------------------------------------------------- two-site DMRG
+    // One sweep of two-site DMRG (left to right, then right to left, the
+    // right-most pair once at the turn), with the same environments, effective
+    // Hamiltonian and truncated splits as the two-site TDVP step (Sec. III A).
+    // The state is renormalised at the end.  Returns the last Ritz value.
+    double dmrg2() {
+        const int N = m->N;
+        TDVP_REQUIRE(N >= 2, TDVP_E_SHAPE, "dmrg2_sweep needs at least two sites");
+        ensure_envs();
+        double e = 0.0;
+        for (int j = 0; j + 2 < N; ++j) {
+            double2* th = form_theta(j);
+            e = ground(h2(j), th);
+            split(j, th, false);
+            update_left(j);
+        }
+        {
+            const int j = N - 2;
+            double2* th = form_theta(j);
+            e = ground(h2(j), th);
+            split(j, th, true);
+            update_right(j + 1);
+        }
+        for (int j = N - 3; j >= 0; --j) {
+            double2* th = form_theta(j);
+            e = ground(h2(j), th);
+            split(j, th, true);
+            update_right(j + 1);
+        }
+        // the centre tensor carries the norm (1 - discarded weight of the last split)
+        const int64_t n0 = (int64_t)m->chi[0] * m->d * m->chi[1];
+        double2* nn = static_cast<double2*>(ctx->workspace("dmrg_nn", sizeof(double2)));
+        vdot_multi(ctx, A(0), 0, 1, A(0), n0, nn);
+        double2 h{0.0, 0.0};
+        TDVP_CHECK_HIP(hipMemcpyAsync(&h, nn, sizeof(double2), hipMemcpyDeviceToHost, ctx->stream));
+        TDVP_CHECK_HIP(hipStreamSynchronize(ctx->stream));
+        TDVP_REQUIRE(std::isfinite(h.x) && h.x > 0.0, TDVP_E_NUMERIC, "dmrg2_sweep: state vanished");
+        scale_copy(A(0), A(0), 1.0 / std::sqrt(h.x), n0, ctx->stream);
+        return e;
+    }
+
     void finish(double t0) {
         TDVP_CHECK_HIP(hipStreamSynchronize(ctx->stream));
         st.chi_peak = 0;
@@ -419,6 +478,28 @@ int tdvp_hybrid_step(tdvp_ctx ctx, tdvp_mps mps, tdvp_mpo mpo, double dt, const 
     if (rc != TDVP_OK) return rc;
     if (one_site) *one_site = saturated ? 1 : 0;
     return saturated ? tdvp1_step(ctx, mps, mpo, dt, opts, stats) : tdvp2_step(ctx, mps, mpo, dt, opts, stats);
+}
+
+int dmrg2_sweep(tdvp_ctx ctx, tdvp_mps mps, tdvp_mpo mpo, const tdvp_opts* opts, tdvp_stats* stats,
+                double* energy) {
+    if (!ctx) return TDVP_E_ARG;
+    return guarded(ctx, [&] {
+        TDVP_REQUIRE(mps && mpo && opts, TDVP_E_ARG, "dmrg2_sweep: null argument");
+        tdvp_stats local{};
+        tdvp_stats& st = stats ? *stats : local;
+        st = tdvp_stats{};
+        const double t0 = now_s();
+        Stepper s(ctx, mps, mpo, *opts, st);
+        double e = 0.0;
+        try {
+            e = s.dmrg2();
+        } catch (...) {
+            mps->env_valid = false;
+            throw;
+        }
+        s.finish(t0);
+        if (energy) *energy = e;
+    });
 }
 
 int norm2(tdvp_ctx ctx, tdvp_mps mps, double* out) {

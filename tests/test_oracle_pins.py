@@ -394,3 +394,50 @@ def test_hybrid_truncated_keeps_chi_max_and_conserves_energy_after_switch():
     assert chi == [min(4, 2 ** min(j, N - j)) for j in range(1, N)]
     assert max(abs(e - energies[first]) for e in energies[first:]) < 1e-10
     assert max(abs(n - norms[first]) for n in norms[first:]) < 1e-12
+
+
+def _ground(H):
+    w, V = np.linalg.eigh(H)
+    return w[0], V[:, 0], w[1] - w[0]
+
+
+@pytest.mark.parametrize("model", ["xxx", "ising"])
+def test_dmrg_reaches_the_exact_ground_state(model):
+    """Two-site DMRG at full bond dimension converges to the lowest eigenpair
+    of the Kronecker-built Hamiltonian (non-degenerate here)."""
+    from oracle import dmrg
+    N = 8
+    if model == "xxx":
+        c, lam, g = fitted_xxx(N, 3)
+        Ws = mpo.mpo_exponentials(N, c, lam, spin.xxx_pairs(), spin.SZ, 0.1)
+        H = spin.longrange_hamiltonian(N, g, spin.xxx_pairs(), spin.SZ, 0.1)
+    else:
+        f = lambda r: 1.0 / r ** 3
+        Ws = mpo.mpo_exact(N, f, spin.ising_pairs(), spin.SX, 1.0)
+        H = spin.longrange_hamiltonian(N, f, spin.ising_pairs(), spin.SX, 1.0)
+    E0, psi0, gap = _ground(H)
+    assert gap > 1e-3
+    st = tdvp.MPSState(random_canonical(N, 3, 4), Ws)
+    energies = [dmrg.dmrg2_sweep(st, tdvp.Truncation(eps=1e-14)) for _ in range(4)]
+    assert abs(energies[-1] - E0) < 1e-10
+    assert abs(abs(np.vdot(psi0, mps.to_dense(st.T))) - 1.0) < 1e-10
+    assert abs(mps.norm2(st.T) - 1.0) < 1e-12
+
+
+def test_dmrg_truncated_is_variational_and_monotone():
+    """Under truncation (chi_max = 3) every sweep's energy is an upper bound
+    of the exact ground energy and does not increase from sweep to sweep."""
+    from oracle import dmrg
+    N = 10
+    c, lam, g = fitted_xxx(N, 3)
+    Ws = mpo.mpo_exponentials(N, c, lam, spin.xxx_pairs())
+    H = spin.longrange_hamiltonian(N, g, spin.xxx_pairs())
+    E0 = np.linalg.eigvalsh(H)[0]
+    st = tdvp.MPSState(random_canonical(N, 4, 3), Ws)
+    es = []
+    for _ in range(4):
+        dmrg.dmrg2_sweep(st, tdvp.Truncation(chi_max=3))
+        es.append(mps.mpo_expectation(st.T, Ws).real / mps.norm2(st.T))
+    assert all(e >= E0 - 1e-12 for e in es)
+    assert all(b <= a + 1e-10 for a, b in zip(es, es[1:]))
+    assert es[-1] - E0 < 0.05 * abs(E0)
