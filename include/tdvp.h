@@ -155,6 +155,12 @@ int mps_set_tensor(tdvp_mps mps, int site, const double* host, int chil, int chi
  * norm stays in site 1. */
 int mps_right_canonicalize(tdvp_ctx ctx, tdvp_mps mps);
 int mps_destroy(tdvp_mps mps);
+/* Apply the d x d operator op (host, complex128, op[s'][s] row-major) to
+ * the physical index of one site: A[a][s'][b] <- sum_s op[s'][s] A[a][s][b]
+ * (the sigma^z_k(0) of the correlation function of Sec. IV).  A unitary op
+ * keeps the canonical form; for any other the norm and gauge are the
+ * caller's.  d <= 16; cached environments of the MPS are invalidated. */
+int mps_apply_site(tdvp_ctx ctx, tdvp_mps mps, int site, const double* op);
 
 /* ------------------------------------------------------------- time steps */
 
@@ -369,6 +375,14 @@ int env_update(tdvp_ctx ctx, int dir, tdvp_dtype dtype, int chil, int chir, int 
                void* env_out);
 
 /* ------------------------------------------------------------ observables */
+
+/* <bra|O_i|ket> for n (site, O) pairs, not normalised (sites 0-based, ops
+ * [n][d][d] complex128 host, out [n] complex128 host).  bra and ket need the
+ * same N and d; their bond dimensions may differ.  With ket = e^{-iHt}
+ * sigma_k |psi_0> and bra = |psi_0> this gives the dynamical correlation
+ * function of Sec. IV (Eq. HaldaneCorrelation) up to the phase e^{i E_0 t}. */
+int transition_expect(tdvp_ctx ctx, tdvp_mps bra, tdvp_mps ket, int n, const int* sites,
+                      const double* ops, double* out);
 
 /* <psi|O_i|psi>/<psi|psi> for n (site, O) pairs; sites 0-based, ops
  * [n][d][d] complex128 host, out [n] complex128 host (Sec. IV). */

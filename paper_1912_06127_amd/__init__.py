@@ -5,7 +5,7 @@ The compute path lives in the HIP library ``libtdvp.so`` (C ABI in
 """
 from .api import (  # noqa: F401
     MPO, MPS, Context, SegmentOptions, Segments, TDVPError, TDVPOptions, apply_heff, apply_heff_adjoint, apply_heff_batched, energy, env_update, expect, expect2,
-    infidelity, norm2, overlap, segment_schedule, tdvp1_step, tdvp2_step, tdvp_hybrid_step, dmrg2_sweep,
+    infidelity, norm2, overlap, segment_schedule, transition_expect, tdvp1_step, tdvp2_step, tdvp_hybrid_step, dmrg2_sweep,
 )
 from ._lib import lib_path, load  # noqa: F401
 from . import fit  # noqa: F401

@@ -96,6 +96,8 @@ SIGNATURES = {
     "env_update": (_I, [_P, _I, _I, _I, _I, _I, _I, _I, _P, _P, _P, _P]),
     "apply_heff_adjoint": (_I, [_P, _I, _I, _I, _I, _I, _I, _I, _I] + [_P] * 11),
     "expect": (_I, [_P, _P, _I, _PI, _PD, _PD]),
+    "transition_expect": (_I, [_P, _P, _P, _I, _PI, _PD, _PD]),
+    "mps_apply_site": (_I, [_P, _P, _I, _PD]),
     "expect2": (_I, [_P, _P, _I, _PI, _PI, _PD, _PD, _PD]),
     "energy": (_I, [_P, _P, _P, _PD]),
     "norm2": (_I, [_P, _P, _PD]),

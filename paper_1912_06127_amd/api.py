@@ -386,6 +386,16 @@ class MPS:
         chil, _, chir = np.asarray(T).view(np.complex128).shape
         _check(self.ctx.handle, _lib.load().mps_set_tensor(self.handle, site, _dptr(T), chil, chir))
 
+    def apply_site(self, site: int, op):
+        """Site tensor <- op acting on its physical index (op [d][d]); a unitary op
+        keeps the canonical form."""
+        o = _c128(np.asarray(op, dtype=np.complex128))
+        _check(self.ctx.handle, _lib.load().mps_apply_site(self.ctx.handle, self.handle, int(site), _dptr(o)))
+
+    def copy(self) -> "MPS":
+        """An independent MPS with the same tensors (through host memory)."""
+        return MPS.from_tensors(self.ctx, self.tensors())
+
     def right_canonicalize(self):
         _check(self.ctx.handle, _lib.load().mps_right_canonicalize(self.ctx.handle, self.handle))
 
@@ -606,6 +616,20 @@ def expect(ctx: Context, mps: MPS, sites, ops) -> np.ndarray:
     out = np.zeros(n, dtype=np.complex128)
     _check(ctx.handle, _lib.load().expect(ctx.handle, mps.handle, n, _iptr(sites), _dptr(ops),
                                           _dptr(out.view(np.float64))))
+    return out
+
+
+def transition_expect(ctx: Context, bra: MPS, ket: MPS, sites, ops) -> np.ndarray:
+    """<bra|O_i|ket> for each site (not normalised)."""
+    sites = np.ascontiguousarray(sites, dtype=np.int32)
+    n = len(sites)
+    ops = np.asarray(ops, dtype=np.complex128)
+    if ops.ndim == 2:
+        ops = np.broadcast_to(ops, (n,) + ops.shape)
+    ops = _c128(ops)
+    out = np.zeros(n, dtype=np.complex128)
+    _check(ctx.handle, _lib.load().transition_expect(ctx.handle, bra.handle, ket.handle, n, _iptr(sites), _dptr(ops),
+                                                     _dptr(out.view(np.float64))))
     return out
 
 

@@ -323,4 +323,8 @@ void wgrad(const void* T1, const void* Z, Dt dt, int wl, int wr, int d, int chil
            hipStream_t s);
 // out[0] = sum_{i,j} X[i][j] Y[j][i] for n x n complex128 matrices.
 void trace_xyT(tdvp_ctx ctx, const double2* X, const double2* Y, int n, double2* out);
+// out = tr(X Y) for X [rows][cols], Y [cols][rows] (device)
+void trace_xy(tdvp_ctx ctx, const double2* X, const double2* Y, int rows, int cols, double2* out);
+// A[a][s'][b] <- sum_s O[s'][s] A[a][s][b], A [chil][d][chir], O [d][d] (device), d <= 16
+void apply_site(double2* A, const double2* O, int chil, int d, int chir, hipStream_t s);
 }  // namespace tdvp

@@ -814,6 +814,27 @@ __global__ void nan_check_kernel(const double2* x, int64_t n, int* flag) {
     if (!isfinite(v.x) || !isfinite(v.y)) atomicOr(flag, 1);
 }
 
+// ------------------------------------------------- local operator on a site
+// A[a][s'][b] <- sum_s O[s'][s] A[a][s][b]; one thread per (a, b).
+constexpr int kApplyMaxD = 16;
+
+__global__ void apply_site_kernel(double2* A, const double2* O, int chil, int d, int chir) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)chil * chir) return;
+    const int64_t a = t / chir, b = t % chir;
+    double2 x[kApplyMaxD];
+    for (int s = 0; s < d; ++s) x[s] = A[(a * d + s) * chir + b];
+    for (int sp = 0; sp < d; ++sp) {
+        double re = 0.0, im = 0.0;
+        for (int s = 0; s < d; ++s) {
+            const double2 o = O[sp * d + s];
+            re += o.x * x[s].x - o.y * x[s].y;
+            im += o.x * x[s].y + o.y * x[s].x;
+        }
+        A[(a * d + sp) * chir + b] = make_double2(re, im);
+    }
+}
+
 // --------------------------------------------- MPO stage operator (device)
 // Dense operator M[row][col] of the sparse MPO stage, built in FP64 from the
 // device MPO tensors (kind as in MopKind).
@@ -895,14 +916,15 @@ __global__ void mop_csr_kernel(const double2* M, int rows, int cols, int* row_pt
 }
 
 // out[block] = partial sums of X[i][j] * Y[j][i] (no conjugation)
-__global__ void trace_xyT_partial_kernel(const double2* X, const double2* Y, int n, double2* partial) {
+// partial sums of tr(X Y) for X [rows][cols], Y [cols][rows]
+__global__ void trace_xyT_partial_kernel(const double2* X, const double2* Y, int rows, int cols, double2* partial) {
     __shared__ double sre[kVecThreads], sim[kVecThreads];
     double re = 0.0, im = 0.0;
-    const int64_t nn = (int64_t)n * n;
+    const int64_t nn = (int64_t)rows * cols;
     for (int64_t t = (int64_t)blockIdx.x * kVecThreads + threadIdx.x; t < nn;
          t += (int64_t)gridDim.x * kVecThreads) {
-        const int64_t i = t / n, j = t % n;
-        const double2 a = X[t], b = Y[j * n + i];
+        const int64_t i = t / cols, j = t % cols;
+        const double2 a = X[t], b = Y[j * rows + i];
         re += a.x * b.x - a.y * b.y;
         im += a.x * b.y + a.y * b.x;
     }
@@ -1213,10 +1235,24 @@ void wgrad(const void* T1, const void* Z, Dt dt, int wl, int wr, int d, int chil
     TDVP_CHECK_HIP(hipGetLastError());
 }
 
+void apply_site(double2* A, const double2* O, int chil, int d, int chir, hipStream_t s) {
+    TDVP_REQUIRE(d >= 1 && d <= kApplyMaxD, TDVP_E_ARG, "apply_site: local dimension out of range");
+    const int64_t n = (int64_t)chil * chir;
+    if (n == 0) return;
+    hipLaunchKernelGGL(apply_site_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, A, O, chil, d, chir);
+    TDVP_CHECK_HIP(hipGetLastError());
+}
+
 void trace_xyT(tdvp_ctx ctx, const double2* X, const double2* Y, int n, double2* out) {
+    trace_xy(ctx, X, Y, n, n, out);
+}
+
+void trace_xy(tdvp_ctx ctx, const double2* X, const double2* Y, int rows, int cols, double2* out) {
     double2* partial = static_cast<double2*>(ctx->workspace("trace_partial", sizeof(double2) * kDotBlocks));
-    int nb = (int)std::min<int64_t>(kDotBlocks, std::max<int64_t>(1, ((int64_t)n * n + kVecThreads - 1) / kVecThreads));
-    hipLaunchKernelGGL(trace_xyT_partial_kernel, dim3(nb), dim3(kVecThreads), 0, ctx->stream, X, Y, n, partial);
+    const int64_t nn = (int64_t)rows * cols;
+    int nb = (int)std::min<int64_t>(kDotBlocks, std::max<int64_t>(1, (nn + kVecThreads - 1) / kVecThreads));
+    hipLaunchKernelGGL(trace_xyT_partial_kernel, dim3(nb), dim3(kVecThreads), 0, ctx->stream, X, Y, rows, cols,
+                       partial);
     hipLaunchKernelGGL(reduce_partial_kernel, dim3(1), dim3(kVecThreads), 0, ctx->stream, partial, nb, out);
     TDVP_CHECK_HIP(hipGetLastError());
 }

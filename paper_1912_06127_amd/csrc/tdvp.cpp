@@ -598,6 +598,65 @@ int expect(tdvp_ctx ctx, tdvp_mps mps, int n, const int* sites, const double* op
     });
 }
 
+int mps_apply_site(tdvp_ctx ctx, tdvp_mps mps, int site, const double* op) {
+    if (!ctx) return TDVP_E_ARG;
+    return guarded(ctx, [&] {
+        TDVP_REQUIRE(mps && op, TDVP_E_ARG, "mps_apply_site: null argument");
+        TDVP_REQUIRE(site >= 0 && site < mps->N, TDVP_E_ARG, "mps_apply_site: site out of range");
+        const int d = mps->d;
+        double2* O = static_cast<double2*>(ctx->workspace("apply_site_op", sizeof(double2) * d * d));
+        TDVP_CHECK_HIP(hipMemcpyAsync(O, op, sizeof(double2) * d * d, hipMemcpyHostToDevice, ctx->stream));
+        apply_site(mps->A[site].as<double2>(), O, mps->chi[site], d, mps->chi[site + 1], ctx->stream);
+        TDVP_CHECK_HIP(hipStreamSynchronize(ctx->stream));  // op lives in caller memory
+        mps->env_valid = false;
+    });
+}
+
+int transition_expect(tdvp_ctx ctx, tdvp_mps bra, tdvp_mps ket, int n, const int* sites, const double* ops,
+                      double* out) {
+    if (!ctx) return TDVP_E_ARG;
+    return guarded(ctx, [&] {
+        TDVP_REQUIRE(bra && ket && n >= 0 && (n == 0 || (sites && ops && out)), TDVP_E_ARG,
+                     "transition_expect: bad argument");
+        TDVP_REQUIRE(bra->N == ket->N && bra->d == ket->d, TDVP_E_SHAPE, "transition_expect: sizes differ");
+        const int N = ket->N, d = ket->d;
+        for (int i = 0; i < n; ++i)
+            TDVP_REQUIRE(sites[i] >= 0 && sites[i] < N, TDVP_E_ARG, "transition_expect: site out of range");
+        Transfer tr(ctx, d);
+        DevMem idd;
+        tr.make_op(tr.mop_id, idd, identity_host(d).data(), 1);
+        // mixed transfers: EL[j] [chi_bra_j][chi_ket_j], ER[j] [chi_ket_{j+1}][chi_bra_{j+1}]
+        std::vector<DevMem> EL(N + 1), ER(N);
+        set_one(ctx, EL[0]);
+        for (int j = 0; j < N; ++j) {
+            EL[j + 1] = DevMem(ctx, sizeof(double2) * (size_t)bra->chi[j + 1] * ket->chi[j + 1]);
+            tr.left(EL[j].ptr, bra->A[j].ptr, bra->chi[j], bra->chi[j + 1], ket->A[j].ptr, ket->chi[j],
+                    ket->chi[j + 1], tr.mop_id, EL[j + 1].ptr);
+        }
+        set_one(ctx, ER[N - 1]);
+        for (int j = N - 1; j >= 1; --j) {
+            ER[j - 1] = DevMem(ctx, sizeof(double2) * (size_t)ket->chi[j] * bra->chi[j]);
+            EnvArgs a{ket->chi[j], ket->chi[j + 1], bra->chi[j], bra->chi[j + 1], d, 1, 1,
+                      bra->A[j].ptr, ket->A[j].ptr, Dt::C128, &tr.mop_id, true, 4};
+            env_right(ctx, a, ER[j].ptr, Dt::C128, ER[j - 1].ptr, Dt::C128);
+        }
+        DevMem res(ctx, sizeof(double2));
+        for (int i = 0; i < n; ++i) {
+            const int j = sites[i];
+            Mop mo;
+            DevMem od;
+            tr.make_op(mo, od, ops + (size_t)i * d * d * 2, 1);
+            DevMem X(ctx, sizeof(double2) * (size_t)bra->chi[j + 1] * ket->chi[j + 1]);
+            tr.left(EL[j].ptr, bra->A[j].ptr, bra->chi[j], bra->chi[j + 1], ket->A[j].ptr, ket->chi[j],
+                    ket->chi[j + 1], mo, X.ptr);
+            trace_xy(ctx, X.as<double2>(), ER[j].as<double2>(), bra->chi[j + 1], ket->chi[j + 1], res.as<double2>());
+            const double2 v = read1(ctx, res.ptr);
+            out[2 * i] = v.x;
+            out[2 * i + 1] = v.y;
+        }
+    });
+}
+
 int expect2(tdvp_ctx ctx, tdvp_mps mps, int n, const int* ii, const int* jj, const double* Oi,
             const double* Oj, double* out) {
     if (!ctx) return TDVP_E_ARG;
