@@ -182,6 +182,11 @@ typedef struct {
                             (or Theta^dag Theta; eigenvalues = squared singular values,
                             absolute accuracy ~1e-16 ||Theta||^2), 0 = automatic:
                             density matrix when w_max >= 1e-13, else SVD */
+    int imaginary;       /* 1: imaginary time (the paper's Discussion): the local
+                            steps apply exp(-tau H_eff) instead of exp(-i tau H_eff)
+                            (backward steps exp(+tau H_eff)) and the state is
+                            renormalised after the step; dt is then the
+                            imaginary-time step.  0: real time. */
 } tdvp_opts;
 
 typedef struct {
@@ -196,7 +201,8 @@ typedef struct {
 } tdvp_stats;
 
 /* Fill opts with defaults: C128, krylov_max 40, tol 1e-13, chi_max
- * 1<<30, w_max 0, eps_rel 0, guard on, strict off, gemm_form 0, svd_mode 0. */
+ * 1<<30, w_max 0, eps_rel 0, guard on, strict off, gemm_form 0, svd_mode 0,
+ * real time. */
 int tdvp_opts_default(tdvp_opts* opts);
 
 /* One symmetric one-site TDVP step of size dt (Sec. II D, Eq. proj1site):

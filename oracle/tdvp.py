@@ -191,3 +191,18 @@ def hybrid_step(st: MPSState, dt: float, tr: Truncation, kmax: int = 40, tol: fl
         return True
     tdvp2_step(st, dt, tr, kmax, tol)
     return False
+
+
+def imaginary_time_step(st: MPSState, dtau: float, tr: Truncation | None = None, kmax: int = 40,
+                        tol: float = 1e-13):
+    """One imaginary-time step exp(-dtau H) (the paper's Discussion notes that
+    p2TDVP applies to imaginary time): the TDVP step with dt = -i dtau, so that
+    forward local steps apply exp(-tau H_eff) and backward ones exp(+tau H_eff),
+    followed by renormalisation of the centre tensor (the evolution is not
+    unitary).  tr = None: one-site step, else two-site with truncation tr."""
+    if tr is None:
+        tdvp1_step(st, -1j * dtau, kmax, tol)
+    else:
+        tdvp2_step(st, -1j * dtau, tr, kmax, tol)
+    st.T[0] = st.T[0] / np.linalg.norm(st.T[0])
+    return st

@@ -424,6 +424,7 @@ class TDVPOptions:
     strict: bool = False
     gemm_form: int = 0
     svd_mode: int = 0           # 1 SVD, 2 density-matrix eigen-decomposition, 0 automatic
+    imaginary: bool = False     # imaginary time: exp(-dt H), state renormalised after each step
 
     def to_c(self) -> Opts:
         o = Opts()
@@ -437,6 +438,7 @@ class TDVPOptions:
         o.strict = int(self.strict)
         o.gemm_form = self.gemm_form
         o.svd_mode = self.svd_mode
+        o.imaginary = int(self.imaginary)
         return o
 
 

@@ -72,8 +72,9 @@ struct KrylovInfo {
     bool converged = true;
 };
 // theta <- exp(-i tau H) theta with H Hermitian (Sec. III A, Lanczos).
+// imaginary = true: theta <- exp(-tau H) theta instead.
 KrylovInfo expm_krylov(tdvp_ctx ctx, const MatVec& op, double2* theta, int64_t n, double tau,
-                       int kmax, double tol);
+                       int kmax, double tol, bool imaginary = false);
 // theta <- normalised Ritz vector of the lowest Ritz value of H in the
 // Krylov space of theta (Lanczos with full reorthogonalisation); stops when
 // the residual norm of that Ritz pair is <= tol.  *energy (nullable) = the

@@ -92,7 +92,11 @@ enum class KrylovMode { Exp, Ground };
 // Lanczos driver.  Exp: theta <- exp(-i tau H) theta.  Ground: theta <- the
 // normalised Ritz vector of the lowest Ritz value, *energy = that value.
 KrylovInfo krylov_run(tdvp_ctx ctx, const MatVec& op, double2* theta, int64_t n, double tau, int kmax, double tol,
-                      KrylovMode mode, double* energy) {
+                      KrylovMode mode, double* energy, bool imaginary) {
+    // exp(-i tau lambda), or exp(-tau lambda) in imaginary time
+    auto phase = [&](double lam) {
+        return imaginary ? double2{std::exp(-tau * lam), 0.0} : double2{std::cos(-tau * lam), std::sin(-tau * lam)};
+    };
     KrylovInfo info;
     TDVP_REQUIRE(kmax >= 1, TDVP_E_ARG, "krylov_max must be >= 1");
     if (n == 0) return info;
@@ -165,9 +169,10 @@ KrylovInfo krylov_run(tdvp_ctx ctx, const MatVec& op, double2* theta, int64_t n,
         tridiag_eigen(alphas, betas, {0, kk - 1}, evals, z);
         double yr = 0.0, yi = 0.0;
         for (int i = 0; i < kk; ++i) {
-            const double f = z[(size_t)kk + i] * z[i], ph = -tau * evals[i];
-            yr += f * std::cos(ph);
-            yi += f * std::sin(ph);
+            const double f = z[(size_t)kk + i] * z[i];
+            const double2 e = phase(evals[i]);
+            yr += f * e.x;
+            yi += f * e.y;
         }
         double scale = 0.0;
         for (double v : alphas) scale = std::max(scale, std::fabs(v));
@@ -188,7 +193,8 @@ KrylovInfo krylov_run(tdvp_ctx ctx, const MatVec& op, double2* theta, int64_t n,
         tridiag_eigen(alphas, betas, all, evals, z);
         y.assign(kk, double2{0.0, 0.0});
         for (int i = 0; i < kk; ++i) {
-            const double ph = -tau * evals[i], c0 = std::cos(ph), s0 = std::sin(ph);
+            const double2 e = phase(evals[i]);
+            const double c0 = e.x, s0 = e.y;
             const double w0 = z[i];  // row 0
             for (int j = 0; j < kk; ++j) {
                 const double f = z[(size_t)j * kk + i] * w0;
@@ -265,13 +271,14 @@ KrylovInfo krylov_run(tdvp_ctx ctx, const MatVec& op, double2* theta, int64_t n,
 
 }  // namespace
 
-KrylovInfo expm_krylov(tdvp_ctx ctx, const MatVec& op, double2* theta, int64_t n, double tau, int kmax, double tol) {
-    return krylov_run(ctx, op, theta, n, tau, kmax, tol, KrylovMode::Exp, nullptr);
+KrylovInfo expm_krylov(tdvp_ctx ctx, const MatVec& op, double2* theta, int64_t n, double tau, int kmax, double tol,
+                       bool imaginary) {
+    return krylov_run(ctx, op, theta, n, tau, kmax, tol, KrylovMode::Exp, nullptr, imaginary);
 }
 
 KrylovInfo ground_krylov(tdvp_ctx ctx, const MatVec& op, double2* theta, int64_t n, int kmax, double tol,
                          double* energy) {
-    return krylov_run(ctx, op, theta, n, 0.0, kmax, tol, KrylovMode::Ground, energy);
+    return krylov_run(ctx, op, theta, n, 0.0, kmax, tol, KrylovMode::Ground, energy, false);
 }
 
 }  // namespace tdvp

@@ -121,7 +121,7 @@ struct Stepper {
         const int64_t n = (int64_t)a.chil * D * a.chir;
         const double f = heff_flops(a.nsite, a.chil, a.chir, m->d, a.wl, a.wr);
         MatVec op = [&](const double2* x, double2* y) { heff_apply(ctx, a, x, Dt::C128, y, Dt::C128); };
-        KrylovInfo ki = expm_krylov(ctx, op, theta, n, tau, o.krylov_max, o.krylov_tol);
+        KrylovInfo ki = expm_krylov(ctx, op, theta, n, tau, o.krylov_max, o.krylov_tol, o.imaginary != 0);
         st.matvecs += ki.matvecs;
         st.flops += f * ki.matvecs;
         st.krylov_max_used = std::max(st.krylov_max_used, ki.k);
@@ -328,16 +328,20 @@ struct Stepper {
             split(j, th, true);
             update_right(j + 1);
         }
-        // the centre tensor carries the norm (1 - discarded weight of the last split)
+        normalize_centre();  // the centre carries the norm (1 - discarded weight of the last split)
+        return e;
+    }
+
+    // Scales the centre tensor (site 0; sites 1.. are right-orthonormal) to unit norm.
+    void normalize_centre() {
         const int64_t n0 = (int64_t)m->chi[0] * m->d * m->chi[1];
-        double2* nn = static_cast<double2*>(ctx->workspace("dmrg_nn", sizeof(double2)));
+        double2* nn = static_cast<double2*>(ctx->workspace("centre_nn", sizeof(double2)));
         vdot_multi(ctx, A(0), 0, 1, A(0), n0, nn);
         double2 h{0.0, 0.0};
         TDVP_CHECK_HIP(hipMemcpyAsync(&h, nn, sizeof(double2), hipMemcpyDeviceToHost, ctx->stream));
         TDVP_CHECK_HIP(hipStreamSynchronize(ctx->stream));
-        TDVP_REQUIRE(std::isfinite(h.x) && h.x > 0.0, TDVP_E_NUMERIC, "dmrg2_sweep: state vanished");
+        TDVP_REQUIRE(std::isfinite(h.x) && h.x > 0.0, TDVP_E_NUMERIC, "renormalisation: the state vanished");
         scale_copy(A(0), A(0), 1.0 / std::sqrt(h.x), n0, ctx->stream);
-        return e;
     }
 
     void finish(double t0) {
@@ -438,6 +442,7 @@ int tdvp1_step(tdvp_ctx ctx, tdvp_mps mps, tdvp_mpo mpo, double dt, const tdvp_o
         Stepper s(ctx, mps, mpo, *opts, st);
         try {
             s.step1(dt);
+            if (opts->imaginary) s.normalize_centre();
         } catch (...) {
             mps->env_valid = false;
             throw;
@@ -458,6 +463,7 @@ int tdvp2_step(tdvp_ctx ctx, tdvp_mps mps, tdvp_mpo mpo, double dt, const tdvp_o
         Stepper s(ctx, mps, mpo, *opts, st);
         try {
             s.step2(dt);
+            if (opts->imaginary) s.normalize_centre();
         } catch (...) {
             mps->env_valid = false;
             throw;

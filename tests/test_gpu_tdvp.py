@@ -221,6 +221,54 @@ def test_hybrid_step_matches_oracle(ctx, dt_):
     assert m.chi == [1] + [A.shape[2] for A in st_o.T]
 
 
+@pytest.mark.parametrize("two_site", [False, True])
+def test_imaginary_time_full_rank_matches_normalised_exp(ctx, two_site):
+    """Imaginary-time steps at full bond dimension equal exp(-tau H) psi_0 / ||.||."""
+    import scipy.linalg as sla
+    import paper_1912_06127_amd as pkg
+    N = 8
+    print(f"imaginary time N={N} two_site={two_site}", flush=True)
+    c, lam = xxx_fit(N, 3)
+    g = ompo.eval_exponentials(c, lam, N - 1)
+    H = spin.longrange_hamiltonian(N, g, spin.xxx_pairs(), spin.SZ, 0.1)
+    Hd = H.toarray() if hasattr(H, "toarray") else np.asarray(H)
+    T = omps.normalize_centre(omps.right_canonicalize(wl.random_site_tensors(61, wl.full_rank_bonds(N, 2), 2)))
+    W = pkg.MPO.longrange(ctx, N, spin.xxx_pairs(), c=c, lam=lam, onsite=spin.SZ, h=0.1)
+    m = pkg.MPS.from_tensors(ctx, T)
+    opts = pkg.TDVPOptions(compute="c128", imaginary=True)
+    step = pkg.tdvp2_step if two_site else pkg.tdvp1_step
+    for _ in range(5):
+        step(ctx, m, W, 0.1, opts)
+    ref = sla.expm(-0.5 * Hd) @ omps.to_dense(T)
+    ref /= np.linalg.norm(ref)
+    assert np.linalg.norm(omps.to_dense(m.tensors()) - ref) < 1e-9
+    assert abs(pkg.norm2(ctx, m) - 1.0) < 1e-12
+
+
+@pytest.mark.parametrize("dt_", ["c128", "c64"])
+def test_imaginary_time_truncated_matches_oracle(ctx, dt_):
+    import paper_1912_06127_amd as pkg
+    N = 10
+    print(f"imaginary time truncated N={N} {dt_}", flush=True)
+    c, lam = xxx_fit(N, 3)
+    Ws = ompo.mpo_exponentials(N, c, lam, spin.xxx_pairs())
+    bits = [i % 2 for i in range(N)]
+    st_o = otdvp.MPSState(omps.padded_product_state(bits, [1] * (N + 1)), Ws)
+    tr = otdvp.Truncation(chi_max=6, w_max=1e-10, eps=1e-12)
+    W = pkg.MPO.longrange(ctx, N, spin.xxx_pairs(), c=c, lam=lam)
+    m = pkg.MPS.init(ctx, N, 2, [1] * (N + 1), basis_state=bits)
+    opts = pkg.TDVPOptions(compute=dt_, chi_max=6, w_max=1e-10, eps_rel=1e-12, imaginary=True)
+    for s in range(8):
+        otdvp.imaginary_time_step(st_o, 0.1, tr)
+        pkg.tdvp2_step(ctx, m, W, 0.1, opts)
+        z = pkg.expect(ctx, m, list(range(N)), spin.SZ).real
+        zref = omps.expect_sites(st_o.T, spin.SZ).real
+        assert np.max(np.abs(z - zref)) <= OBS_TOL[dt_], (s, np.max(np.abs(z - zref)))
+    e = pkg.energy(ctx, m, W).real
+    e_ref = omps.mpo_expectation(st_o.T, Ws).real / omps.norm2(st_o.T)
+    assert abs(e - e_ref) <= OBS_TOL[dt_]
+
+
 def test_tdvp2_full_rank_matches_exact_evolution(ctx):
     import paper_1912_06127_amd as pkg
     N = 8

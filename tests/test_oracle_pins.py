@@ -441,3 +441,34 @@ def test_dmrg_truncated_is_variational_and_monotone():
     assert all(e >= E0 - 1e-12 for e in es)
     assert all(b <= a + 1e-10 for a, b in zip(es, es[1:]))
     assert es[-1] - E0 < 0.05 * abs(E0)
+
+
+@pytest.mark.parametrize("two_site", [False, True])
+def test_imaginary_time_full_rank_equals_normalised_exp(two_site):
+    """At full bond dimension the TDVP splitting is exact, so imaginary-time
+    steps give exp(-tau H) psi_0 / ||.|| of the Kronecker-built Hamiltonian,
+    and a long run approaches its ground energy."""
+    N = 8
+    c, lam, g = fitted_xxx(N, 3)
+    Ws = mpo.mpo_exponentials(N, c, lam, spin.xxx_pairs(), spin.SZ, 0.1)
+    H = spin.longrange_hamiltonian(N, g, spin.xxx_pairs(), spin.SZ, 0.1)
+    T = random_canonical(N, 6)
+    psi0 = mps.to_dense(T)
+    st = tdvp.MPSState(T, Ws)
+    tr = tdvp.Truncation() if two_site else None
+    for _ in range(5):
+        tdvp.imaginary_time_step(st, 0.1, tr)
+    Hd = H.toarray() if hasattr(H, "toarray") else np.asarray(H)
+    ref = sla.expm(-0.5 * Hd) @ psi0
+    ref /= np.linalg.norm(ref)
+    assert np.linalg.norm(mps.to_dense(st.T) - ref) < 1e-9
+    for _ in range(60):
+        tdvp.imaginary_time_step(st, 0.25, tr)
+    # tau = 15.5: the energy of the exact normalised exp(-tau H) psi_0, below
+    # the start and approaching the ground energy
+    far = sla.expm(-15.5 * Hd) @ psi0
+    far /= np.linalg.norm(far)
+    E = mps.mpo_expectation(st.T, Ws).real
+    assert abs(E - np.vdot(far, Hd @ far).real) < 1e-9
+    E0 = np.linalg.eigvalsh(Hd)[0]
+    assert E0 <= E < E0 + 1e-3 < np.vdot(psi0, Hd @ psi0).real
