@@ -857,10 +857,11 @@ void grouped_gemm_plan(tdvp_ctx ctx, const std::vector<GemmDesc>& g, bool fp64, 
             float best_ms = 1e30f;
             const bool prof = ctx->prof_on;
             ctx->prof_on = false;
-            // candidates: the tiles that win on large ragged groups
-            const int cand32[] = {10, 2, 12, 15}, cand64[] = {2, 12, 15};
+            // candidates: the tiles that win on large ragged groups (128x128 with
+            // 16 waves since the grouped tile order)
+            const int cand32[] = {10, 2, 12, 15, 13}, cand64[] = {2, 12, 15};
             const int* cand = fp64 ? cand64 : cand32;
-            const int ncand = fp64 ? 3 : 4;
+            const int ncand = fp64 ? 3 : 5;
             for (int ci = 0; ci < ncand; ++ci) {
                 const TileCfg& c = *find_tile(cand[ci], fp64);
                 upload(c.id);
