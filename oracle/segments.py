@@ -38,6 +38,11 @@ step (Sec. III A):
   Environments of a departing boundary are the ones left by the last update
   there, i.e. out of date (Sec. III D, item i).
 
+Repair (Sec. III D, Fig. reorth): the parallel updates break the gauge at
+the partition boundaries and the norm drifts; ``reorthonormalize`` brings the
+state back to the inverse canonical gauge of the normalised state and
+recomputes every environment, a serial step taken now and then.
+
 Within one phase the segments touch disjoint tensors and environments, so
 they may run in any order with identical results.  Per step every pair is
 evolved forward by dt and every site 1..N-2 backward by dt, as in Eq. proj2site.
@@ -216,7 +221,11 @@ class SegmentState:
         self.chi_static = chi_static
         self.kmax, self.tol = kmax, tol
         self.stats = SegStats()
-        # all environments from the initial (exactly canonical) state (Sec. III B)
+        self.build_environments()
+
+    def build_environments(self):
+        """Every beta/gamma from the current gauge (Fig. environments); at
+        the start they come from the exactly canonical state (Sec. III B)."""
         N = self.N
         self.beta = [None] * N
         self.gamma = [None] * N
@@ -274,6 +283,43 @@ class SegmentState:
             self.site_update(op.j, op.tau)
         else:
             self.pair_update(op.j, op.tau, op.refresh)
+
+
+def norm2(st: SegmentState) -> float:
+    """<psi|psi> of the state Psi_1 V_1 Psi_2 ... Psi_N as it stands.  The
+    parallel updates break the gauge conditions at the partition boundaries,
+    so this drifts from 1 (Sec. III D, item ii, Fig. reorth)."""
+    E = np.ones((1, 1), dtype=np.complex128)
+    for A in st.tensors():
+        E = np.einsum("ab,asc,bsd->cd", E, A.conj(), A)
+    return float(E[0, 0].real)
+
+
+def gauge_defect(st: SegmentState) -> float:
+    """Largest deviation from the inverse canonical conditions: Psi_j V_j
+    left orthonormal and V_{j-1} Psi_j right orthonormal (Sec. II A)."""
+    dev = 0.0
+    for j in range(st.N - 1):
+        A = st.Psi[j] * st.V[j][None, None, :]
+        chil, d, chir = A.shape
+        M = A.reshape(chil * d, chir)
+        dev = max(dev, np.max(np.abs(M.conj().T @ M - np.eye(chir))))
+        B = st.V[j][:, None, None] * st.Psi[j + 1]
+        chil, d, chir = B.shape
+        M = B.reshape(chil, d * chir)
+        if j + 1 < st.N - 1:  # the last tensor carries the norm
+            dev = max(dev, np.max(np.abs(M @ M.conj().T - np.eye(chil))))
+    return float(dev)
+
+
+def reorthonormalize(st: SegmentState) -> SegmentState:
+    """Serial repair of a segment run (Sec. III D, Fig. reorth): bring the
+    state as it stands back to the inverse canonical gauge of the normalised
+    state and recompute every environment.  The bond dimensions are kept;
+    nothing is truncated, so the state changes only by its normalisation."""
+    st.Psi, st.V = to_inverse_canonical(st.tensors())
+    st.build_environments()
+    return st
 
 
 def step(st: SegmentState, sizes, dt: float, order=None):
