@@ -210,7 +210,8 @@ def segments_timing(pkg, ctx, np, graph=True):
 
     One untimed step (tile tuning), one timed eager step, one step that
     captures every phase's batched exponentiation in a HIP graph and one step
-    that replays them.
+    that replays them; then the norm of the state and one serial
+    reorthonormalisation with environment recompute (Sec. III D), timed.
     """
     import workloads as wl
     p = wl.XY_N201
@@ -256,6 +257,16 @@ def segments_timing(pkg, ctx, np, graph=True):
     res["matvecs_per_step"] = st["matvecs"]
     res["chi_max"] = max(chi)
     res["w_total"] = sg.w_total
+    progress("segments: norm and reorthonormalisation (serial repair)")
+    t0 = time.perf_counter()
+    n2 = sg.norm2()
+    res["norm2_s"] = round(time.perf_counter() - t0, 3)
+    res["norm_drift"] = n2 - 1.0
+    t0 = time.perf_counter()
+    sg.reorthonormalize(mpo)
+    ctx.sync()
+    res["reorth_s"] = round(time.perf_counter() - t0, 2)
+    res["norm_drift_after_reorth"] = sg.norm2() - 1.0
     sg.close()
     mpo.close()
     res["workload"] = ("segment-parallel 2TDVP, N=201 XY alpha=1.5 (K=6, w=14), 32 segments 11|6x30|10, "

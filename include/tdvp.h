@@ -314,6 +314,21 @@ int seg_get_psi(tdvp_seg seg, int j, void* out);
  * memory (double [chi_{j+1}]). */
 int seg_get_bond(tdvp_seg seg, int j, double* out);
 int seg_destroy(tdvp_seg seg);
+/* <psi|psi> of the state Psi_0 V_0 Psi_1 ... Psi_{N-1} as it stands, in FP64
+ * (left transfer matrices on the device).  The parallel updates break the
+ * gauge conditions at the segment boundaries, so this drifts from 1 as a run
+ * goes on (Sec. III D, item ii; Fig. reorth).  *out receives the value. */
+int seg_norm2(tdvp_ctx ctx, tdvp_seg seg, double* out);
+/* Serial repair of a segment run (Sec. III D, Fig. reorth): the bond
+ * matrices are folded into the site tensors, the state is brought back to the
+ * inverse canonical gauge of the normalised state (the same right
+ * orthonormalisation and split sweep as seg_init) and every environment is
+ * recomputed from it.  Bond dimensions are kept and nothing is truncated, so
+ * the state changes only by its normalisation.  mpo must be the MPO of the
+ * run.  Errors: TDVP_E_SHAPE if the MPO does not match, TDVP_E_NUMERIC if a
+ * Schmidt coefficient vanished; after an error the state is unspecified and
+ * must only be destroyed. */
+int seg_reorthonormalize(tdvp_ctx ctx, tdvp_seg seg, tdvp_mpo mpo);
 /* The operations of one half step (host only, no device work): for op n,
  * phase[n] (ops of one phase run together), kind[n] (2: pair (site, site+1)
  * forward, 1: one-site backward), site[n] (0-based) and tau[n] (forward

@@ -109,6 +109,8 @@ SIGNATURES = {
     "seg_get_psi": (_I, [_P, _I, _PD]),
     "seg_get_bond": (_I, [_P, _I, _PD]),
     "seg_destroy": (_I, [_P]),
+    "seg_norm2": (_I, [_P, _P, _PD]),
+    "seg_reorthonormalize": (_I, [_P, _P, _P]),
     "seg_schedule": (_I, [_I, _PI, _D, _I, _I, _PI, _PI, _PI, _PD, _PI]),
     "tdvp_profile_enable": (_I, [_P, _I]),
     "tdvp_ctx_set_gemm_form": (_I, [_P, _I]),

@@ -588,6 +588,18 @@ class Segments:
         _check(self.ctx.handle, _lib.load().seg_get_bond(self.handle, j, _dptr(out)))
         return out
 
+    def norm2(self) -> float:
+        """<psi|psi> of the state as it stands (drifts from 1 under the
+        parallel updates)."""
+        out = C.c_double()
+        _check(self.ctx.handle, _lib.load().seg_norm2(self.ctx.handle, self.handle, C.byref(out)))
+        return out.value
+
+    def reorthonormalize(self, mpo: "MPO") -> None:
+        """Back to the inverse canonical gauge of the normalised state, with
+        every environment recomputed (a serial step)."""
+        _check(self.ctx.handle, _lib.load().seg_reorthonormalize(self.ctx.handle, self.handle, mpo.handle))
+
     def tensors(self):
         """Ordinary MPS tensors of the state: Psi_0, V_0 Psi_1, V_1 Psi_2, ..."""
         out = [self.psi(0)]

@@ -779,6 +779,56 @@ void build_environments(tdvp_ctx ctx, tdvp_seg sg, tdvp_mpo W) {
     TDVP_CHECK_HIP(hipStreamSynchronize(ctx->stream));
 }
 
+// ------------------------------------------------------------ repair
+// <psi|psi> of Psi_0 V_0 Psi_1 ... Psi_{N-1} by left transfers of the
+// tensors A_j = Psi_j V_j (the last tensor as it stands), FP64.
+double state_norm2(tdvp_ctx ctx, tdvp_seg sg) {
+    const int N = sg->N, d = sg->d;
+    hipStream_t s = ctx->stream;
+    std::vector<double2> id((size_t)d * d, double2{0.0, 0.0});
+    for (int k = 0; k < d; ++k) id[(size_t)k * d + k] = double2{1.0, 0.0};
+    DevMem idd(ctx, sizeof(double2) * d * d);
+    DevMem E(ctx, sizeof(double2)), E2;
+    const double2 one{1.0, 0.0};
+    TDVP_CHECK_HIP(hipMemcpyAsync(idd.ptr, id.data(), sizeof(double2) * d * d, hipMemcpyHostToDevice, s));
+    TDVP_CHECK_HIP(hipMemcpyAsync(E.ptr, &one, sizeof(one), hipMemcpyHostToDevice, s));
+    TDVP_CHECK_HIP(hipStreamSynchronize(s));
+    Mop mop;
+    mop_make(ctx, mop, 1, idd.ptr, nullptr, Dt::C128, 1, 1, 1, d, true, true);
+    for (int j = 0; j < N; ++j) {
+        const int cl = sg->chi[j], cr = sg->chi[j + 1];
+        const double2* A = sg->psi(j);
+        if (j + 1 < N) {
+            double2* T = static_cast<double2*>(ctx->workspace("nrm_A", sizeof(double2) * (size_t)cl * d * cr));
+            copy2d(T, cr, sg->psi(j), cr, cl * d, cr, 0, s);
+            scale_cols(T, cr, sg->Vd[j].as<double>(), cl * d, cr, s);
+            A = T;
+        }
+        E2 = DevMem(ctx, sizeof(double2) * (size_t)cr * cr);
+        EnvArgs a{cl, cr, cl, cr, d, 1, 1, A, A, Dt::C128, &mop, true, 4};
+        env_left(ctx, a, E.ptr, Dt::C128, E2.ptr, Dt::C128);
+        std::swap(E, E2);
+    }
+    double2 v{0.0, 0.0};
+    TDVP_CHECK_HIP(hipMemcpyAsync(&v, E.ptr, sizeof(v), hipMemcpyDeviceToHost, s));
+    TDVP_CHECK_HIP(hipStreamSynchronize(s));
+    return v.x;
+}
+
+// Serial repair of a segment run (Sec. III D, Fig. reorth): fold the bond
+// matrices into the site tensors (an ordinary MPS of the same state), bring
+// it back to the inverse canonical gauge of the normalised state and rebuild
+// every environment.  Bond dimensions are kept, nothing is truncated.
+void reorthonormalize(tdvp_ctx ctx, tdvp_seg sg, tdvp_mpo W) {
+    for (int j = 0; j + 1 < sg->N; ++j) {
+        const int rows = sg->chi[j] * sg->d, c = sg->chi[j + 1];
+        scale_cols(sg->psi(j), c, sg->Vd[j].as<double>(), rows, c, ctx->stream);
+    }
+    TDVP_CHECK_HIP(hipStreamSynchronize(ctx->stream));
+    to_inverse_canonical(ctx, sg, 0);
+    build_environments(ctx, sg, W);
+}
+
 }  // namespace
 }  // namespace tdvp
 
@@ -896,6 +946,25 @@ int seg_get_bond(tdvp_seg sg, int j, double* out) {
     return guarded(sg->ctx, [&] {
         TDVP_REQUIRE(j >= 0 && j + 1 < sg->N, TDVP_E_ARG, "seg_get_bond: bond out of range");
         std::copy(sg->Vh[j].begin(), sg->Vh[j].end(), out);
+    });
+}
+
+int seg_norm2(tdvp_ctx ctx, tdvp_seg sg, double* out) {
+    if (!ctx || !sg) return TDVP_E_ARG;
+    return guarded(ctx, [&] {
+        TDVP_REQUIRE(out, TDVP_E_ARG, "seg_norm2: null argument");
+        TDVP_REQUIRE(sg->ctx == ctx, TDVP_E_ARG, "seg_norm2: state belongs to another context");
+        *out = state_norm2(ctx, sg);
+    });
+}
+
+int seg_reorthonormalize(tdvp_ctx ctx, tdvp_seg sg, tdvp_mpo mpo) {
+    if (!ctx || !sg) return TDVP_E_ARG;
+    return guarded(ctx, [&] {
+        TDVP_REQUIRE(sg->ctx == ctx, TDVP_E_ARG, "seg_reorthonormalize: state belongs to another context");
+        TDVP_REQUIRE(mpo && mpo->N == sg->N && mpo->d == sg->d, TDVP_E_SHAPE,
+                     "seg_reorthonormalize: MPO does not match");
+        reorthonormalize(ctx, sg, mpo);
     });
 }
 

@@ -104,6 +104,52 @@ def test_segment_steps_match_oracle(ctx, cs, dt_, batched):
             assert np.allclose(np.sort(1.0 / sg.bond(j)), np.sort(1.0 / st_o.V[j]), rtol=1e-8, atol=1e-12)
 
 
+@pytest.mark.parametrize("dt_", ["c128", "c64"])
+def test_reorthonormalize_matches_oracle(ctx, dt_):
+    """Sec. III D, Fig. reorth: after truncated parallel steps the norm has
+    drifted; the repair normalises the state without changing its direction,
+    restores the gauge, and the recomputed environments drive the next step
+    exactly as the oracle's do."""
+    import paper_1912_06127_amd as pkg
+    N, sizes, lo, hi, seed = SEG_CASES[0]
+    print(f"reorthonormalise N={N} {dt_}", flush=True)
+    chi, T = case(N, sizes, lo, hi, seed)
+    *_, Ws = xy_mpo(N)
+    W = pkg.MPO.from_tensors(ctx, Ws)
+    sg = pkg.Segments.init(ctx, W, T, sizes, compute=dt_)
+    st_o = oseg.SegmentState(T, Ws, chi_static=chi[1:], kmax=8, tol=0.0)
+    opts = pkg.SegmentOptions(compute=dt_)
+    for _ in range(3):
+        oseg.step(st_o, sizes, 0.05)
+        sg.step(W, 0.05, opts)
+    Tb = sg.tensors()
+    n_gpu, n_o = sg.norm2(), oseg.norm2(st_o)
+    assert abs(n_gpu - omps.norm2(Tb)) <= 1e-12  # the device transfer sum of its own state
+    assert abs(n_o - 1.0) > 1e-6  # the drift is there to repair
+    assert abs(n_gpu - n_o) <= OBS_TOL[dt_]
+    sg.reorthonormalize(W)
+    oseg.reorthonormalize(st_o)
+    assert sg.chi == chi
+    Ta = sg.tensors()
+    assert abs(sg.norm2() - 1.0) <= 1e-12
+    assert abs(omps.norm2(Ta) - 1.0) <= 1e-12
+    ov = abs(omps.overlap(Tb, Ta)) / np.sqrt(omps.norm2(Tb))
+    assert abs(ov - 1.0) <= 1e-12
+    for j in range(N - 1):
+        A = sg.psi(j) * sg.bond(j)[None, None, :]
+        assert omps.is_left_orthonormal(A, 1e-9), j
+        if dt_ == "c128":
+            assert np.allclose(np.sort(1.0 / sg.bond(j)), np.sort(1.0 / st_o.V[j]), rtol=1e-8, atol=1e-12), j
+    # the next step runs on the recomputed environments
+    oseg.step(st_o, sizes, 0.05)
+    sg.step(W, 0.05, opts)
+    Tg, To = sg.tensors(), st_o.tensors()
+    assert np.max(np.abs(sz_profile(Tg) - sz_profile(To))) <= OBS_TOL[dt_]
+    if dt_ == "c128":
+        ov = abs(omps.overlap(Tg, To)) / np.sqrt(omps.norm2(Tg) * omps.norm2(To))
+        assert abs(ov - 1.0) <= 1e-10
+
+
 def test_batched_equals_instance_by_instance(ctx):
     import paper_1912_06127_amd as pkg
     N, sizes, lo, hi, seed = SEG_CASES[2]
