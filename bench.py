@@ -164,7 +164,8 @@ def sweep_timing(pkg, ctx, steps=40):
     evolution twice: an untimed pass that lets the GEMM autotuner see every
     shape, then the timed pass.  Observables are excluded from the step time.
     The spin profile C_i = <sigma^z_i>/4 at the end is compared between the
-    FP32-MFMA and the FP64 path.
+    FP32-MFMA and the FP64 path.  The FP64 evolution is then repeated with the
+    truncated-Taylor exponential in place of Lanczos (timed pass only).
     """
     import numpy as np
     N, cap = 64, 512
@@ -194,6 +195,20 @@ def sweep_timing(pkg, ctx, steps=40):
                              "heff_env_gflops": round(flops / sum(times) * 1e-9, 1),
                              "chi_peak": max(mps.chi), "w_total": wt}
             mps.close()
+    # the FP64 evolution again with the truncated-Taylor exponential (shapes already tuned)
+    opts = pkg.TDVPOptions(compute="c128", chi_max=cap, w_max=1e-8, eps_rel=1e-12, krylov_tol=1e-10,
+                           exp_method="taylor")
+    mps = pkg.MPS.init(ctx, N, 2, [1] * (N + 1), basis_state=bits)
+    times, mv = [], 0
+    for _ in range(steps):
+        st = pkg.tdvp2_step(ctx, mps, mpo, 0.05, opts)
+        times.append(st["seconds"])
+        mv += st["matvecs"]
+    pt = 0.25 * pkg.expect(ctx, mps, list(range(N)), sz).real
+    res["c128_taylor"] = {"s_per_step": round(float(np.mean(times)), 4), "matvecs_per_step": mv / steps,
+                          "chi_peak": max(mps.chi),
+                          "max_abs_obs_diff_vs_lanczos": float(np.max(np.abs(pt - prof["c128"])))}
+    mps.close()
     mpo.close()
     res["speedup_fp32_vs_fp64"] = round(res["c128"]["s_per_step"] / res["c64"]["s_per_step"], 2)
     res["max_abs_obs_diff_c64_vs_c128"] = float(np.max(np.abs(prof["c64"] - prof["c128"])))

@@ -187,6 +187,14 @@ typedef struct {
                             (backward steps exp(+tau H_eff)) and the state is
                             renormalised after the step; dt is then the
                             imaginary-time step.  0: real time. */
+    int exp_method;      /* local exponentials: 0 = Lanczos (Sec. III A), 1 = truncated
+                            Taylor series with scaling (Al-Mohy and Higham 2011, the
+                            alternative named with the Lanczos method in Sec. III A):
+                            degree m <= 55 and s steps from the backward-error bounds
+                            theta_m (unit roundoff 2^-53) and a 16-step Lanczos
+                            enclosure of the spectrum, shifted to its midpoint;
+                            terms stop at max(2^-53, krylov_tol) relative.
+                            krylov_max does not apply.  TDVP_E_ARG otherwise. */
 } tdvp_opts;
 
 typedef struct {
@@ -202,7 +210,7 @@ typedef struct {
 
 /* Fill opts with defaults: C128, krylov_max 40, tol 1e-13, chi_max
  * 1<<30, w_max 0, eps_rel 0, guard on, strict off, gemm_form 0, svd_mode 0,
- * real time. */
+ * real time, Lanczos exponentials. */
 int tdvp_opts_default(tdvp_opts* opts);
 
 /* One symmetric one-site TDVP step of size dt (Sec. II D, Eq. proj1site):

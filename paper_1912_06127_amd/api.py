@@ -425,6 +425,7 @@ class TDVPOptions:
     gemm_form: int = 0
     svd_mode: int = 0           # 1 SVD, 2 density-matrix eigen-decomposition, 0 automatic
     imaginary: bool = False     # imaginary time: exp(-dt H), state renormalised after each step
+    exp_method: str = "lanczos"  # local exponentials: "lanczos" or "taylor" (Al-Mohy-Higham)
 
     def to_c(self) -> Opts:
         o = Opts()
@@ -439,6 +440,9 @@ class TDVPOptions:
         o.gemm_form = self.gemm_form
         o.svd_mode = self.svd_mode
         o.imaginary = int(self.imaginary)
+        if self.exp_method not in ("lanczos", "taylor"):
+            raise ValueError(f"exp_method must be 'lanczos' or 'taylor', not {self.exp_method!r}")
+        o.exp_method = 1 if self.exp_method == "taylor" else 0
         return o
 
 

@@ -282,6 +282,10 @@ void lanczos_3term(double2* w, const double2* vk, const double2* vkm1, const dou
                    double beta, int64_t n, hipStream_t s);
 // out = scale * in
 void scale_copy(double2* out, const double2* in, double scale, int64_t n, hipStream_t s);
+// Truncated-Taylor exponential action: b <- alpha (y - c b) and F <- F + b;
+// taylor_rescale: F <- eta F and b <- F.
+void taylor_term(double2* b, const double2* y, double2* F, int64_t n, double2 alpha, double c, hipStream_t s);
+void taylor_rescale(double2* F, double2* b, int64_t n, double2 eta, hipStream_t s);
 // out = sum_j coef[j] V[j]
 void combine(double2* out, const double2* V, int64_t vstride, int nv, const double2* coef,
              int64_t n, hipStream_t s);

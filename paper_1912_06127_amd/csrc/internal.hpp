@@ -75,6 +75,14 @@ struct KrylovInfo {
 // imaginary = true: theta <- exp(-tau H) theta instead.
 KrylovInfo expm_krylov(tdvp_ctx ctx, const MatVec& op, double2* theta, int64_t n, double tau,
                        int kmax, double tol, bool imaginary = false);
+// theta <- exp(-i tau H) theta (imaginary: exp(-tau H) theta) by the
+// truncated Taylor series with scaling of Al-Mohy and Higham (2011): the
+// degree m <= 55 and the number of steps s from the table of theta_m and a
+// Lanczos enclosure of the spectrum seen from theta; each step stops early
+// once two consecutive terms fall below tol relative to the partial sum.
+// info.k = the largest number of terms summed in a step.
+KrylovInfo expm_taylor(tdvp_ctx ctx, const MatVec& op, double2* theta, int64_t n, double tau, double tol,
+                       bool imaginary);
 // theta <- normalised Ritz vector of the lowest Ritz value of H in the
 // Krylov space of theta (Lanczos with full reorthogonalisation); stops when
 // the residual norm of that Ritz pair is <= tol.  *energy (nullable) = the

@@ -685,6 +685,28 @@ __global__ void scale_copy_kernel(double2* out, const double2* in, double scale,
     out[i] = make_double2(scale * v.x, scale * v.y);
 }
 
+// One term of the Taylor series: b <- alpha (y - c b), F <- F + b.
+__global__ void taylor_term_kernel(double2* b, const double2* y, double2* F, int64_t n, double ar, double ai,
+                                   double c) {
+    const int64_t i = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
+    if (i >= n) return;
+    const double2 yi = y[i], bi = b[i], fi = F[i];
+    const double ur = yi.x - c * bi.x, ui = yi.y - c * bi.y;
+    const double2 nb = make_double2(ar * ur - ai * ui, ar * ui + ai * ur);
+    b[i] = nb;
+    F[i] = make_double2(fi.x + nb.x, fi.y + nb.y);
+}
+
+// End of one scaling step: F <- eta F, b <- F.
+__global__ void taylor_rescale_kernel(double2* F, double2* b, int64_t n, double er, double ei) {
+    const int64_t i = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
+    if (i >= n) return;
+    const double2 f = F[i];
+    const double2 g = make_double2(er * f.x - ei * f.y, er * f.y + ei * f.x);
+    F[i] = g;
+    b[i] = g;
+}
+
 __global__ void combine_kernel(double2* out, const double2* V, int64_t vstride, int nv,
                                const double2* coef, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
@@ -1140,6 +1162,18 @@ void lanczos_3term(double2* w, const double2* vk, const double2* vkm1, const dou
 void scale_copy(double2* out, const double2* in, double scale, int64_t n, hipStream_t s) {
     if (n == 0) return;
     hipLaunchKernelGGL(scale_copy_kernel, dim3(nblk(n)), dim3(kVecThreads), 0, s, out, in, scale, n);
+    TDVP_CHECK_HIP(hipGetLastError());
+}
+
+void taylor_term(double2* b, const double2* y, double2* F, int64_t n, double2 alpha, double c, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(taylor_term_kernel, dim3(nblk(n)), dim3(kVecThreads), 0, s, b, y, F, n, alpha.x, alpha.y, c);
+    TDVP_CHECK_HIP(hipGetLastError());
+}
+
+void taylor_rescale(double2* F, double2* b, int64_t n, double2 eta, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(taylor_rescale_kernel, dim3(nblk(n)), dim3(kVecThreads), 0, s, F, b, n, eta.x, eta.y);
     TDVP_CHECK_HIP(hipGetLastError());
 }
 

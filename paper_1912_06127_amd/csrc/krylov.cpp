@@ -87,10 +87,14 @@ void tridiag_eigen(const std::vector<double>& alpha, const std::vector<double>& 
 
 namespace {
 
-enum class KrylovMode { Exp, Ground };
+enum class KrylovMode { Exp, Ground, Interval };
 
 // Lanczos driver.  Exp: theta <- exp(-i tau H) theta.  Ground: theta <- the
 // normalised Ritz vector of the lowest Ritz value, *energy = that value.
+// Interval: kmax steps (fewer on breakdown), theta unchanged, energy[0..1] =
+// [min_i (r_i - res_i), max_i (r_i + res_i)] over the Ritz values r_i with
+// residual norms res_i = beta_k |e_k^T z_i| (an enclosure of the spectrum
+// seen from theta; [0, 0] for a zero theta).
 KrylovInfo krylov_run(tdvp_ctx ctx, const MatVec& op, double2* theta, int64_t n, double tau, int kmax, double tol,
                       KrylovMode mode, double* energy, bool imaginary) {
     // exp(-i tau lambda), or exp(-tau lambda) in imaginary time
@@ -99,6 +103,7 @@ KrylovInfo krylov_run(tdvp_ctx ctx, const MatVec& op, double2* theta, int64_t n,
     };
     KrylovInfo info;
     TDVP_REQUIRE(kmax >= 1, TDVP_E_ARG, "krylov_max must be >= 1");
+    if (mode == KrylovMode::Interval) energy[0] = energy[1] = 0.0;
     if (n == 0) return info;
     hipStream_t s = ctx->stream;
     double2* V = static_cast<double2*>(ctx->workspace("kry_V", sizeof(double2) * (size_t)(kmax + 1) * n));
@@ -165,6 +170,24 @@ KrylovInfo krylov_run(tdvp_ctx ctx, const MatVec& op, double2* theta, int64_t n,
         alphas.push_back(a);
         const int kk = (int)alphas.size();
         if (mode == KrylovMode::Ground) return consume_ground(k, b, kk);
+        if (mode == KrylovMode::Interval) {
+            double scale = 0.0;
+            for (double v : alphas) scale = std::max(scale, std::fabs(v));
+            for (double v : betas) scale = std::max(scale, v);
+            if (k + 1 < kmax && b > 1e-14 * scale && scale != 0.0) {
+                betas.push_back(b);
+                return false;
+            }
+            tridiag_eigen(alphas, betas, {kk - 1}, evals, z);
+            double lo = evals[0] - b * std::fabs(z[0]), hi = evals[0] + b * std::fabs(z[0]);
+            for (int i = 1; i < kk; ++i) {
+                lo = std::min(lo, evals[i] - b * std::fabs(z[i]));
+                hi = std::max(hi, evals[i] + b * std::fabs(z[i]));
+            }
+            energy[0] = lo;
+            energy[1] = hi;
+            return true;
+        }
         // e_{kk-1}^T exp(-i tau T) e_0 needs the first and last eigenvector rows only
         tridiag_eigen(alphas, betas, {0, kk - 1}, evals, z);
         double yr = 0.0, yi = 0.0;
@@ -214,7 +237,7 @@ KrylovInfo krylov_run(tdvp_ctx ctx, const MatVec& op, double2* theta, int64_t n,
         // consecutive exponentials of one vector length need similar
         // iteration counts: the first batch is the count of the last one
         int& hint = ctx->krylov_hint[mode == KrylovMode::Exp ? n : -n];
-        const int first = hint > 0 ? std::max(2, hint) : kFirstBatch;
+        const int first = mode == KrylovMode::Interval ? kmax : (hint > 0 ? std::max(2, hint) : kFirstBatch);
         int queued = 0;
         bool stop = false;
         while (!stop) {
@@ -234,7 +257,7 @@ KrylovInfo krylov_run(tdvp_ctx ctx, const MatVec& op, double2* theta, int64_t n,
             for (int k = queued; k < end && !stop; ++k) stop = consume(k, hs[1 + 2 * k], hs[2 + 2 * k]);
             queued = end;
         }
-        hint = k_used;
+        if (mode != KrylovMode::Interval) hint = k_used;
     } else {
         for (int k = 0; k < kmax; ++k) {
             double2* vk = V + (size_t)k * n;
@@ -253,6 +276,7 @@ KrylovInfo krylov_run(tdvp_ctx ctx, const MatVec& op, double2* theta, int64_t n,
             scale_copy(V + (size_t)(k + 1) * n, w, 1.0 / betas.back(), n, s);
         }
     }
+    if (mode == KrylovMode::Interval) return info;
     if (mode == KrylovMode::Exp) {  // the Ritz vector of Ground mode stays normalised
         for (auto& c : y) {
             c.x *= beta0;
@@ -279,6 +303,89 @@ KrylovInfo expm_krylov(tdvp_ctx ctx, const MatVec& op, double2* theta, int64_t n
 KrylovInfo ground_krylov(tdvp_ctx ctx, const MatVec& op, double2* theta, int64_t n, int kmax, double tol,
                          double* energy) {
     return krylov_run(ctx, op, theta, n, 0.0, kmax, tol, KrylovMode::Ground, energy, false);
+}
+
+namespace {
+#include "taylor_theta.inc"
+constexpr int kIntervalSteps = 16;
+}  // namespace
+
+// Truncated Taylor series with scaling (Al-Mohy and Higham 2011), applied
+// to the Hermitian H_eff through its matvec only.  The norm in the degree
+// selection is the spectral norm, exact for a Hermitian operator: the
+// spectrum seen from theta is enclosed by a short Lanczos run, the operator
+// is shifted to the midpoint c of that enclosure (exp(-i tau H) = e^{-i tau c}
+// exp(-i tau (H - c))) and ||tau (H - c)|| <= |tau| rho with rho the
+// half-width, widened by 5 %.  Then (m, s) minimise m s subject to
+// |tau| rho / s <= theta_m, and each of the s steps sums at most m terms,
+// stopping early once two consecutive terms are below tol relative to the
+// partial sum.
+KrylovInfo expm_taylor(tdvp_ctx ctx, const MatVec& op, double2* theta, int64_t n, double tau, double tol,
+                       bool imaginary) {
+    KrylovInfo info;
+    if (n == 0 || tau == 0.0) return info;
+    double iv[2];
+    info = krylov_run(ctx, op, theta, n, 0.0, (int)std::min<int64_t>(kIntervalSteps, n), 0.0, KrylovMode::Interval,
+                      iv, false);
+    if (iv[0] == 0.0 && iv[1] == 0.0 && info.matvecs == 0) return info;  // theta vanishes
+    const double c = 0.5 * (iv[0] + iv[1]);
+    const double rho = 0.5 * (iv[1] - iv[0]) * 1.05;
+    const double anorm = std::fabs(tau) * rho;
+    TDVP_REQUIRE(std::isfinite(anorm), TDVP_E_NUMERIC, "Taylor exponential: non-finite spectral bound");
+    int m = 0, s = 1;
+    if (anorm > 0.0) {
+        double best = 0.0;
+        for (int mm = 1; mm <= kTaylorMaxDegree; ++mm) {
+            const double ss = std::max(1.0, std::ceil(anorm / kTaylorTheta[mm]));
+            if (m == 0 || mm * ss < best) {
+                best = mm * ss;
+                m = mm;
+                s = (int)ss;
+            }
+        }
+    }
+    hipStream_t st = ctx->stream;
+    double2* F = static_cast<double2*>(ctx->workspace("tay_F", sizeof(double2) * (size_t)n));
+    double2* b = static_cast<double2*>(ctx->workspace("tay_b", sizeof(double2) * (size_t)n));
+    double2* y = static_cast<double2*>(ctx->workspace("tay_y", sizeof(double2) * (size_t)n));
+    double2* nrm = static_cast<double2*>(ctx->workspace("tay_nrm", sizeof(double2) * 2));
+    TDVP_CHECK_HIP(hipMemcpyAsync(F, theta, sizeof(double2) * (size_t)n, hipMemcpyDeviceToDevice, st));
+    TDVP_CHECK_HIP(hipMemcpyAsync(b, theta, sizeof(double2) * (size_t)n, hipMemcpyDeviceToDevice, st));
+    // A = -i tau (H - c), or -tau (H - c) in imaginary time; eta = e^{-i tau c / s} (e^{-tau c / s})
+    const double2 eta = imaginary ? double2{std::exp(-tau * c / s), 0.0}
+                                  : double2{std::cos(-tau * c / s), std::sin(-tau * c / s)};
+    double2 h[2];
+    auto norms = [&](double& nb, double& nf) {
+        vdot_multi(ctx, b, 0, 1, b, n, nrm);
+        vdot_multi(ctx, F, 0, 1, F, n, nrm + 1);
+        TDVP_CHECK_HIP(hipMemcpyAsync(h, nrm, sizeof(h), hipMemcpyDeviceToHost, st));
+        TDVP_CHECK_HIP(hipStreamSynchronize(st));
+        nb = std::sqrt(std::max(0.0, h[0].x));
+        nf = std::sqrt(std::max(0.0, h[1].x));
+        TDVP_REQUIRE(std::isfinite(nb) && std::isfinite(nf), TDVP_E_NUMERIC,
+                     "Taylor exponential: non-finite value in H_eff application");
+    };
+    int terms = 0;
+    for (int i = 0; i < s; ++i) {
+        double c1 = 0.0, c2 = 0.0, nf = 0.0;
+        norms(c1, nf);
+        for (int j = 1; j <= m; ++j) {
+            op(b, y);
+            ++info.matvecs;
+            const double f = tau / ((double)s * j);
+            const double2 alpha = imaginary ? double2{-f, 0.0} : double2{0.0, -f};
+            taylor_term(b, y, F, n, alpha, c, st);
+            terms = std::max(terms, j);
+            norms(c2, nf);
+            if (c1 + c2 <= tol * nf) break;
+            c1 = c2;
+        }
+        taylor_rescale(F, b, n, eta, st);
+    }
+    TDVP_CHECK_HIP(hipMemcpyAsync(theta, F, sizeof(double2) * (size_t)n, hipMemcpyDeviceToDevice, st));
+    info.k = terms;
+    info.converged = true;
+    return info;
 }
 
 }  // namespace tdvp

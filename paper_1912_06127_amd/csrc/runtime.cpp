@@ -149,6 +149,7 @@ int tdvp_opts_default(tdvp_opts* o) {
     o->multiplet_guard = 1;
     o->strict = 0;
     o->imaginary = 0;
+    o->exp_method = 0;
     o->gemm_form = 0;
     o->svd_mode = 0;
     return TDVP_OK;

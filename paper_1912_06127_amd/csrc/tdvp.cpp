@@ -60,6 +60,7 @@ struct Stepper {
         TDVP_REQUIRE(form == 3 || form == 4, TDVP_E_ARG, "gemm_form must be 0, 3 or 4");
         TDVP_REQUIRE(opts.krylov_max >= 1, TDVP_E_ARG, "krylov_max must be >= 1");
         TDVP_REQUIRE(opts.chi_max >= 1, TDVP_E_ARG, "chi_max must be >= 1");
+        TDVP_REQUIRE(opts.exp_method == 0 || opts.exp_method == 1, TDVP_E_ARG, "exp_method must be 0 or 1");
         TDVP_REQUIRE(m->N == W->N && m->d == W->d, TDVP_E_SHAPE, "MPS and MPO sizes differ");
         for (int j = 0; j < m->N; ++j)
             TDVP_REQUIRE(m->chi[j] <= (int64_t)m->d * m->chi[j + 1] &&
@@ -121,7 +122,9 @@ struct Stepper {
         const int64_t n = (int64_t)a.chil * D * a.chir;
         const double f = heff_flops(a.nsite, a.chil, a.chir, m->d, a.wl, a.wr);
         MatVec op = [&](const double2* x, double2* y) { heff_apply(ctx, a, x, Dt::C128, y, Dt::C128); };
-        KrylovInfo ki = expm_krylov(ctx, op, theta, n, tau, o.krylov_max, o.krylov_tol, o.imaginary != 0);
+        KrylovInfo ki = o.exp_method == 1
+                            ? expm_taylor(ctx, op, theta, n, tau, std::max(0x1p-53, o.krylov_tol), o.imaginary != 0)
+                            : expm_krylov(ctx, op, theta, n, tau, o.krylov_max, o.krylov_tol, o.imaginary != 0);
         st.matvecs += ki.matvecs;
         st.flops += f * ki.matvecs;
         st.krylov_max_used = std::max(st.krylov_max_used, ki.k);

@@ -35,7 +35,28 @@ def test_version_and_default_options():
     o = _lib.Opts()
     assert lib.tdvp_opts_default(C.byref(o)) == 0
     assert o.compute == _lib.TDVP_C128 and o.krylov_max == 40 and o.multiplet_guard == 1
+    assert o.imaginary == 0 and o.exp_method == 0
     assert lib.tdvp_opts_default(None) == 1
+    with pytest.raises(ValueError):
+        pkg.TDVPOptions(exp_method="pade").to_c()
+
+
+def test_taylor_degree_bounds_match_published_table():
+    """theta_m of the truncated-Taylor exponential, generated here from the
+    backward-error definition, against the table published with the method
+    (Al-Mohy and Higham 2011, three significant digits) as shipped by scipy's
+    implementation of it."""
+    em = pytest.importorskip("scipy.sparse.linalg._expm_multiply")
+    ref = getattr(em, "_theta", None)
+    if not ref:
+        pytest.skip("scipy does not expose the published table")
+    text = open(os.path.join(ROOT, "paper_1912_06127_amd", "csrc", "taylor_theta.inc")).read()
+    vals = {int(m): float(v) for v, m in re.findall(r"^\s+([0-9.eE+-]+),\s+// m = (\d+)$", text, flags=re.M)}
+    assert sorted(vals) == list(range(1, 56))
+    assert all(vals[m] < vals[m + 1] for m in range(1, 55))
+    for m, t in ref.items():
+        # m = 1: the published 2.29e-16 against 2u = 2.22e-16 from the leading term
+        assert abs(vals[m] / t - 1.0) < (0.04 if m == 1 else 0.01), (m, vals[m], t)
 
 
 def test_null_arguments_are_rejected():
