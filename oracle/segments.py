@@ -38,6 +38,10 @@ step (Sec. III A):
   Environments of a departing boundary are the ones left by the last update
   there, i.e. out of date (Sec. III D, item i).
 
+One-site variant (``schedule1``, ``step1``; proposed in the Discussion
+without a boundary rule): one-site sweeps inside the segments and the same
+two-site boundary pairs; see ``schedule1`` for the reading.
+
 Repair (Sec. III D, Fig. reorth): the parallel updates break the gauge at
 the partition boundaries and the norm drifts; ``reorthonormalize`` brings the
 state back to the inverse canonical gauge of the normalised state and
@@ -54,8 +58,9 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from .env import trivial_env, update_left, update_right
-from .heff import apply_heff1, apply_heff2
+from .heff import apply_heff0, apply_heff1, apply_heff2
 from .krylov import expm_krylov
+from .mps import lq
 from .tdvp import Truncation, truncation_rank
 
 
@@ -119,7 +124,7 @@ def directions(p: int, first_half: bool):
 
 @dataclass
 class Op:
-    kind: str        # "pair" or "site"
+    kind: str        # "pair", "site" or "bond" (zero-site, one-site schedule)
     j: int           # first site of the pair, or the site
     tau: float       # forward time (negative for backward steps)
     segment: int
@@ -203,6 +208,7 @@ class SegStats:
     matvecs: int = 0
     pair_updates: int = 0
     site_updates: int = 0
+    bond_updates: int = 0
 
 
 class SegmentState:
@@ -278,11 +284,135 @@ class SegmentState:
         if refresh in ("right", "both"):
             self.gamma[j] = update_right(self.gamma[j + 1], Vh.reshape(chi, d2, chir), self.W[j + 1])
 
+    def bond_update(self, j: int, tau: float, refresh: str):
+        """Zero-site step on the bond between sites j and j+1 (one-site
+        schedule, Eq. proj1site).  "left" (sweeping right): Psi_j = Q R,
+        the bond matrix is R (V_j Psi_{j+1} is right orthonormal) and
+        beta_{j+1} comes from Q; "right" (sweeping left): Psi_{j+1} = L Q',
+        the bond matrix is L (Psi_j V_j is left orthonormal) and gamma_j comes
+        from Q'.  C <- exp(-i tau H_0) C, then C = u s vh restores the inverse
+        canonical form across the bond: Psi_j = (Q or Psi_j V_j) u s, V_j =
+        1/s, Psi_{j+1} = s vh (V_j Psi_{j+1} or Q'), and the environment on
+        the sweep's side is rebuilt from the new isometry."""
+        chil, d, chim = self.Psi[j].shape
+        chir = self.Psi[j + 1].shape[2]
+        if refresh == "left":
+            Q, C = np.linalg.qr(self.Psi[j].reshape(chil * d, chim))
+            Q = Q.reshape(chil, d, chim)
+            Qr = self.V[j][:, None, None] * self.Psi[j + 1]
+            beta = update_left(self.beta[j], Q, self.W[j])
+            gamma = self.gamma[j]
+        else:
+            C, Qh = lq(self.Psi[j + 1].reshape(chim, d * chir))
+            Qr = Qh.reshape(chim, d, chir)
+            Q = self.Psi[j] * self.V[j][None, None, :]
+            beta = self.beta[j + 1]
+            gamma = update_right(self.gamma[j + 1], Qr, self.W[j + 1])
+        C = self._expm(lambda x: apply_heff0(beta, gamma, x), C, tau)
+        u, S, vh = np.linalg.svd(C)
+        self.Psi[j] = np.einsum("asb,bc->asc", Q, u * S[None, :])
+        self.V[j] = 1.0 / S
+        self.Psi[j + 1] = np.einsum("ab,bsc->asc", S[:, None] * vh, Qr)
+        if refresh == "left":
+            self.beta[j + 1] = update_left(self.beta[j], np.einsum("asb,bc->asc", Q, u), self.W[j])
+        else:
+            self.gamma[j] = update_right(self.gamma[j + 1], np.einsum("ab,bsc->asc", vh, Qr), self.W[j + 1])
+        self.stats.bond_updates += 1
+
     def run(self, op: Op):
         if op.kind == "site":
             self.site_update(op.j, op.tau)
+        elif op.kind == "bond":
+            self.bond_update(op.j, op.tau, op.refresh)
         else:
             self.pair_update(op.j, op.tau, op.refresh)
+
+
+def schedule1(sizes, dt: float, first_half: bool):
+    """Phases of one half step of the segment-parallel one-site scheme.
+
+    The Discussion proposes a parallel one-site TDVP without giving its
+    boundary rule; the reading here keeps the two-site boundary pairs of the
+    two-site schedule and runs one-site sweeps inside the segments.  It
+    integrates the tangent-space splitting of Eq. proj1site with, at every
+    boundary bond b, the terms of sites b, b+1 and bond b replaced by the one
+    two-site term of (b, b+1) (which contains them): the pair goes forward,
+    every other site forward, every other bond backward.
+
+    Directions and boundary timing are those of ``schedule``: a boundary
+    pair departing in the first half goes forward by dt/2 before the sweeps,
+    a meeting one by dt after them in the first half and by dt/2 in the
+    second.  A segment sweeping right over its own sites a..z (its sites
+    minus the ones in boundary pairs) does: the bond from its left boundary
+    site backward by dt/2, site a forward by dt/2, then bond j backward and
+    site j+1 forward for j = a..z-1, then the bond into its right boundary
+    pair backward (mirror image sweeping left); the chain ends have no
+    bonds.  At p = 1 this is the serial one-site step.  Inner segments need
+    at least three sites, the end segments two.  Bond dimensions are fixed:
+    the boundary splits truncate back to the current dimension.
+    """
+    p = len(sizes)
+    if any(n < 2 for n in sizes) or any(n < 3 for n in sizes[1:-1]):
+        raise ValueError("end segments need two sites and inner segments three")
+    N = sum(sizes)
+    if N < 4:
+        raise ValueError("need at least four sites")
+    bounds, lo = [], 0
+    for n in sizes:
+        bounds.append((lo, lo + n - 1))
+        lo += n
+    dirs = directions(p, first_half)
+    half = dt / 2.0
+    before, after = Phase("boundary pairs (departing)"), Phase("boundary pairs (meeting)")
+    for s in range(p - 1):
+        b = bounds[s][1]
+        if dirs[s] == 1 and dirs[s + 1] == -1:
+            after.ops.append(Op("pair", b, dt if first_half else half, s, "both"))
+        elif first_half:
+            before.ops.append(Op("pair", b, half, s, "both"))
+    sweeps = []
+    for s, (lo_s, hi_s) in enumerate(bounds):
+        a = lo_s + (1 if s > 0 else 0)
+        z = hi_s - (1 if s < p - 1 else 0)
+        ops = []
+        if dirs[s] == 1:
+            if s > 0:
+                ops.append(Op("bond", lo_s, -half, s, "left"))
+            ops.append(Op("site", a, half, s, ""))
+            for j in range(a, z):
+                ops.append(Op("bond", j, -half, s, "left"))
+                ops.append(Op("site", j + 1, half, s, ""))
+            if s < p - 1:
+                ops.append(Op("bond", z, -half, s, "left"))
+        else:
+            if s < p - 1:
+                ops.append(Op("bond", z, -half, s, "right"))
+            ops.append(Op("site", z, half, s, ""))
+            for j in range(z - 1, a - 1, -1):
+                ops.append(Op("bond", j, -half, s, "right"))
+                ops.append(Op("site", j, half, s, ""))
+            if s > 0:
+                ops.append(Op("bond", lo_s, -half, s, "right"))
+        sweeps.append(ops)
+    phases = [before] if before.ops else []
+    for i in range(max(len(o) for o in sweeps)):
+        ph = Phase(f"sweep micro-step {i}")
+        ph.ops = [o[i] for o in sweeps if i < len(o)]
+        phases.append(ph)
+    if after.ops:
+        phases.append(after)
+    return phases
+
+
+def step1(st: SegmentState, sizes, dt: float):
+    """One time step of the segment-parallel one-site scheme.  The state
+    should be built with ``chi_static`` equal to its bond profile so that the
+    boundary pairs keep the bond dimensions fixed."""
+    for first in (True, False):
+        for ph in schedule1(sizes, dt, first):
+            for op in ph.ops:
+                st.run(op)
+    return st
 
 
 def norm2(st: SegmentState) -> float:

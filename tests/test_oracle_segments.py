@@ -199,3 +199,90 @@ def test_reorthonormalize_is_identity_on_a_fresh_state():
     for a, b in zip(V0, st.V):
         assert np.allclose(np.sort(a), np.sort(b), rtol=1e-11)
     assert np.linalg.norm(omps.to_dense(st.tensors()) - psi) < 1e-12
+
+
+# ------------------------------------------------- one-site segment schedule
+
+@pytest.mark.parametrize("sizes", [[10], [5, 5], [2, 3, 3, 2], [3, 4, 4, 3, 3, 3], [11] + [6] * 30 + [10]])
+def test_one_site_schedule_time_bookkeeping(sizes):
+    """Per step: boundary pairs forward by dt, every other site forward by dt,
+    every other bond backward by dt (Eq. proj1site with the boundary terms
+    merged into two-site terms); ops inside a phase touch disjoint sites."""
+    N, dt = sum(sizes), 0.1
+    bounds = np.cumsum(sizes)[:-1] - 1  # boundary bonds b (pairs (b, b+1))
+    pair = np.zeros(N - 1)
+    site = np.zeros(N)
+    bond = np.zeros(N - 1)
+    for first in (True, False):
+        for ph in seg.schedule1(sizes, dt, first):
+            touched = []
+            for op in ph.ops:
+                if op.kind == "pair":
+                    pair[op.j] += op.tau
+                    touched += [op.j, op.j + 1]
+                elif op.kind == "site":
+                    site[op.j] += op.tau
+                    touched.append(op.j)
+                else:
+                    bond[op.j] += op.tau
+                    touched += [op.j, op.j + 1]
+            assert len(touched) == len(set(touched)), ph.name
+    in_pair = set(bounds) | set(bounds + 1)
+    for j in range(N):
+        assert abs(site[j] - (0.0 if j in in_pair else dt)) < 1e-15, j
+    for j in range(N - 1):
+        if j in set(bounds):
+            assert abs(pair[j] - dt) < 1e-15 and bond[j] == 0.0
+        else:
+            assert pair[j] == 0.0 and abs(bond[j] + dt) < 1e-15, j
+    with pytest.raises(ValueError):
+        seg.schedule1([3, 2, 2, 3], dt, True)  # inner segments need three sites
+
+
+def test_one_site_single_segment_is_the_serial_step():
+    N = 10
+    Ws, _ = xxx(N)
+    T0 = omps.normalize_centre(omps.right_canonicalize(wl.random_site_tensors(11, wl.full_rank_bonds(N, 2, 6), 2)))
+    st = seg.SegmentState(T0, Ws, chi_static=[A.shape[2] for A in T0])
+    so = otdvp.MPSState(T0, Ws)
+    for _ in range(3):
+        seg.step1(st, [N], 0.05)
+        otdvp.tdvp1_step(so, 0.05)
+    assert np.linalg.norm(omps.to_dense(st.tensors()) - omps.to_dense(so.T)) < 1e-12
+    assert st.stats.pair_updates == 0 and st.stats.bond_updates == 6 * (N - 1)
+
+
+@pytest.mark.parametrize("sizes", [[5, 5], [2, 3, 3, 2]])
+def test_one_site_full_rank_parallel_step_is_exact(sizes):
+    N = 10
+    Ws, g = xxx(N)
+    H = spin.longrange_hamiltonian(N, g, spin.xxx_pairs(), spin.SX, 0.4)
+    T0 = omps.normalize_centre(omps.right_canonicalize(wl.random_site_tensors(12, wl.full_rank_bonds(N, 2), 2)))
+    chi = [A.shape[2] for A in T0]
+    st = seg.SegmentState(T0, Ws, chi_static=chi)
+    for _ in range(4):
+        seg.step1(st, sizes, 0.05)
+    ref = spin.ExactEvolution(H).evolve(omps.to_dense(T0), 0.2)
+    assert np.linalg.norm(omps.to_dense(st.tensors()) - ref) < 1e-10
+    assert [P.shape[2] for P in st.Psi] == chi
+
+
+def test_one_site_parallel_error_is_first_order_and_norm_tracks_boundary_weight():
+    N, Tt = 12, 0.2
+    Ws, _ = xxx(N)
+    T0 = omps.normalize_centre(omps.right_canonicalize(wl.random_site_tensors(11, wl.full_rank_bonds(N, 2, 8), 2)))
+    chi = [A.shape[2] for A in T0]
+    diffs = []
+    for dt in (0.05, 0.025, 0.0125):
+        a = seg.SegmentState(T0, Ws, chi_static=chi)
+        b = seg.SegmentState(T0, Ws, chi_static=chi)
+        for _ in range(round(Tt / dt)):
+            seg.step1(a, [N], dt)
+            seg.step1(b, [3, 3, 3, 3], dt)
+        diffs.append(np.linalg.norm(omps.to_dense(a.tensors()) - omps.to_dense(b.tensors())))
+    assert diffs[0] > 1e-5
+    assert diffs[0] / diffs[1] > 1.8 and diffs[1] / diffs[2] > 1.8
+    # one-site steps conserve the norm; only the boundary splits truncate
+    assert b.stats.w_total > 1e-7
+    assert abs(seg.norm2(b) - (1.0 - b.stats.w_total)) < 1e-10
+    assert [P.shape[2] for P in b.Psi] == chi
