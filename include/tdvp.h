@@ -292,6 +292,15 @@ typedef struct {
     int svd_mode;        /* 0: density-matrix split, SVD when a kept singular
                             value is below 1e-6 of the largest; 1: SVD; 2:
                             density matrix always */
+    int one_site;        /* 1: the parallel one-site scheme proposed in the
+                            Discussion, with two-site boundary pairs (a reading):
+                            one-site sweeps inside the segments, zero-site bond
+                            steps (QR/LQ, exponential, SVD back to the inverse
+                            canonical form), the boundary pairs and their timing
+                            as in the two-site schedule; bond dimensions change only
+                            at boundary splits.  Inner segments need at least three
+                            sites (TDVP_E_SHAPE).  At one segment it is the serial
+                            one-site step.  0: the two-site schedule (Sec. III B). */
 } tdvp_seg_opts;
 
 /* Defaults: C64, krylov_k 8, chi_max 1<<30, w_max 0, eps_rel 0, guard on,

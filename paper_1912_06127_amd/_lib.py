@@ -41,7 +41,7 @@ class SegOpts(C.Structure):
     _fields_ = [
         ("compute", C.c_int), ("krylov_k", C.c_int), ("chi_max", C.c_int), ("w_max", C.c_double),
         ("eps_rel", C.c_double), ("multiplet_guard", C.c_int), ("static_shapes", C.c_int),
-        ("batched", C.c_int), ("use_graph", C.c_int), ("svd_mode", C.c_int),
+        ("batched", C.c_int), ("use_graph", C.c_int), ("svd_mode", C.c_int), ("one_site", C.c_int),
     ]
 
 

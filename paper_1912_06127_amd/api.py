@@ -500,6 +500,7 @@ class SegmentOptions:
     batched: bool = True
     use_graph: bool = False
     svd_mode: int = 0
+    one_site: bool = False       # one-site sweeps with two-site boundary pairs
 
     def to_c(self) -> SegOpts:
         o = SegOpts()
@@ -513,6 +514,7 @@ class SegmentOptions:
         o.batched = int(self.batched)
         o.use_graph = int(self.use_graph)
         o.svd_mode = self.svd_mode
+        o.one_site = int(self.one_site)
         return o
 
 

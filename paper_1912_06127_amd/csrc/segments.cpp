@@ -46,7 +46,8 @@ struct SOp {
     bool pair;
     int j;
     double tau;
-    int refresh;  // pairs: 1 left environment, 2 right, 3 both
+    int refresh;        // pairs: 1 left environment, 2 right, 3 both; bonds: 1 sweeping right, 2 left
+    bool bond = false;  // zero-site step on the bond (j, j+1) (one-site schedule)
 };
 using SPhase = std::vector<SOp>;
 
@@ -106,6 +107,68 @@ std::vector<SPhase> seg_schedule(const std::vector<int>& sizes, double dt, bool 
                 o.push_back({true, j, half, 2});
                 o.push_back({false, j, -half, 0});
             }
+        }
+        longest = std::max(longest, o.size());
+    }
+    std::vector<SPhase> out;
+    if (!before.empty()) out.push_back(before);
+    for (size_t i = 0; i < longest; ++i) {
+        SPhase ph;
+        for (int s = 0; s < p; ++s)
+            if (i < sweeps[s].size()) ph.push_back(sweeps[s][i]);
+        out.push_back(ph);
+    }
+    if (!after.empty()) out.push_back(after);
+    return out;
+}
+
+// One-site schedule (the parallel one-site TDVP proposed in the Discussion;
+// the boundary rule is a reading): the two-site boundary pairs and their
+// timing as above, one-site sweeps inside the segments.  A segment sweeping
+// right over its own sites a..z (its sites without those of boundary pairs)
+// does the bond from its left boundary site backward by dt/2, site a forward
+// by dt/2, then bond j backward and site j+1 forward for j = a..z-1, then the
+// bond into its right boundary pair backward (mirror image sweeping left).
+// Per step every boundary pair and every other site go forward by dt and
+// every other bond backward by dt; at p = 1 this is the serial one-site step.
+std::vector<SPhase> seg_schedule1(const std::vector<int>& sizes, double dt, bool first) {
+    const int p = (int)sizes.size();
+    int N = 0;
+    std::vector<int> lo(p), hi(p);
+    for (int s = 0; s < p; ++s) {
+        lo[s] = N;
+        N += sizes[s];
+        hi[s] = N - 1;
+    }
+    const std::vector<int> dir = seg_dirs(p, first);
+    const double half = dt / 2.0;
+    SPhase before, after;
+    for (int s = 0; s + 1 < p; ++s) {
+        const bool meet = dir[s] == 1 && dir[s + 1] == -1;
+        if (meet) after.push_back({true, hi[s], first ? dt : half, 3});
+        else if (first) before.push_back({true, hi[s], half, 3});
+    }
+    std::vector<SPhase> sweeps(p);
+    size_t longest = 0;
+    for (int s = 0; s < p; ++s) {
+        const int a = lo[s] + (s > 0 ? 1 : 0), z = hi[s] - (s + 1 < p ? 1 : 0);
+        SPhase& o = sweeps[s];
+        if (dir[s] == 1) {
+            if (s > 0) o.push_back({false, lo[s], -half, 1, true});
+            o.push_back({false, a, half, 0});
+            for (int j = a; j < z; ++j) {
+                o.push_back({false, j, -half, 1, true});
+                o.push_back({false, j + 1, half, 0});
+            }
+            if (s + 1 < p) o.push_back({false, z, -half, 1, true});
+        } else {
+            if (s + 1 < p) o.push_back({false, z, -half, 2, true});
+            o.push_back({false, z, half, 0});
+            for (int j = z - 1; j >= a; --j) {
+                o.push_back({false, j, -half, 2, true});
+                o.push_back({false, j, half, 0});
+            }
+            if (s > 0) o.push_back({false, lo[s], -half, 2, true});
         }
         longest = std::max(longest, o.size());
     }
@@ -210,6 +273,78 @@ struct SegRun {
     HeffArgs h2(int j) {
         return HeffArgs{2, sg->chi[j], sg->chi[j + 2], sg->d, W->w[j], W->w[j + 2], sg->beta[j].ptr,
                         sg->gamma[j + 1].ptr, sg->edt, &W->mop(2, j, fp64), fp64, form};
+    }
+
+    HeffArgs h0(int j) {  // bond between sites j and j+1
+        const int c = sg->chi[j + 1];
+        return HeffArgs{0, c, c, sg->d, W->w[j + 1], W->w[j + 1], sg->beta[j + 1].ptr, sg->gamma[j].ptr, sg->edt,
+                        &W->mop(0, j, fp64), fp64, form};
+    }
+
+    double2* ws(const char* name, size_t elems) {
+        return static_cast<double2*>(ctx->workspace(name, sizeof(double2) * std::max<size_t>(1, elems)));
+    }
+
+    // Zero-site step on bond j of the one-site schedule (Eq. proj1site).
+    // refresh 1 (sweeping right): Psi_j = Q R, the bond matrix is R (V_j
+    // Psi_{j+1} is right orthonormal), beta_{j+1} from Q; refresh 2 (sweeping
+    // left): Psi_{j+1} = L Q', the bond matrix is L (Psi_j V_j is left
+    // orthonormal), gamma_j from Q'.  C <- exp(-i tau H_0) C and C = u s vh
+    // give back the inverse canonical form: Psi_j = (Q or Psi_j V_j) u s,
+    // V_j = 1/s, Psi_{j+1} = s vh (V_j Psi_{j+1} or Q'), and the environment
+    // on the sweep's side is rebuilt from the new isometry.
+    void bond_step(int j, double tau, int refresh) {
+        ProfScope prof(ctx, "seg_bond", 0.0, 0.0);
+        const int d = sg->d, chil = sg->chi[j], c = sg->chi[j + 1], chir = sg->chi[j + 2];
+        const int rows = chil * d, cols = d * chir;
+        TDVP_REQUIRE(rows >= c && cols >= c, TDVP_E_SHAPE, "segment bond step: bond exceeds its rank bound");
+        hipStream_t s = ctx->stream;
+        double2* C = ws("seg_bC", (size_t)c * c);
+        double2* Q = ws("seg_bQ", (size_t)(refresh == 1 ? rows : cols) * c);
+        if (refresh == 1) {
+            qr_rowmajor(ctx, sg->psi(j), rows, c, Q, C);
+            refresh_left(j, Q, chil, c);
+        } else {
+            lq_rowmajor(ctx, sg->psi(j + 1), c, cols, C, Q);
+            refresh_right(j + 1, Q, c, chir);
+        }
+        const HeffArgs h = h0(j);
+        MatVec mv = [&](const double2* a, double2* b) { heff_apply(ctx, h, a, Dt::C128, b, Dt::C128); };
+        KrylovInfo ki = expm_krylov(ctx, mv, C, (int64_t)c * c, tau, o.krylov_k, 0.0);
+        st.matvecs += ki.matvecs;
+        st.flops += heff_flops(0, c, c, d, h.wl, h.wr) * ki.matvecs;
+        st.krylov_max_used = std::max(st.krylov_max_used, ki.k);
+        SvdResult r = svd_rowmajor(ctx, C, c, c);
+        TDVP_REQUIRE(r.k == c, TDVP_E_SHAPE, "segment bond step: rank-deficient SVD");
+        for (double v : r.S)
+            TDVP_REQUIRE(v > 0.0 && std::isfinite(v), TDVP_E_NUMERIC,
+                         "segment bond step: a singular value of the bond matrix is zero or not finite");
+        double2* T = ws("seg_bT", (size_t)rows * c);
+        double2* X = ws("seg_bX", (size_t)c * cols);
+        if (refresh == 1) {
+            zgemm_rowmajor(ctx, Q, r.U, T, rows, c, c);  // A_j = Q u
+            copy2d(X, cols, sg->psi(j + 1), cols, c, cols, 0, s);
+            scale_rows(X, cols, sg->Vd[j].as<double>(), c, cols, s);
+            zgemm_rowmajor(ctx, r.Vh, X, sg->psi(j + 1), c, c, cols);  // vh V_j Psi_{j+1}
+            scale_rows(sg->psi(j + 1), cols, r.S_dev, c, cols, s);
+            copy2d(sg->psi(j), c, T, c, rows, c, 0, s);
+            scale_cols(sg->psi(j), c, r.S_dev, rows, c, s);
+            refresh_left(j, T, chil, c);
+        } else {
+            zgemm_rowmajor(ctx, r.Vh, Q, X, c, c, cols);  // B_{j+1} = vh Q'
+            copy2d(T, c, sg->psi(j), c, rows, c, 0, s);
+            scale_cols(T, c, sg->Vd[j].as<double>(), rows, c, s);
+            zgemm_rowmajor(ctx, T, r.U, sg->psi(j), rows, c, c);  // Psi_j V_j u
+            scale_cols(sg->psi(j), c, r.S_dev, rows, c, s);
+            copy2d(sg->psi(j + 1), cols, X, cols, c, cols, 0, s);
+            scale_rows(sg->psi(j + 1), cols, r.S_dev, c, cols, s);
+            refresh_right(j + 1, X, c, chir);
+        }
+        std::vector<double> inv(c);
+        for (int k = 0; k < c; ++k) inv[k] = 1.0 / r.S[k];
+        sg->Vh[j] = inv;
+        TDVP_CHECK_HIP(hipMemcpyAsync(sg->Vd[j].ptr, inv.data(), sizeof(double) * c, hipMemcpyHostToDevice, s));
+        TDVP_CHECK_HIP(hipStreamSynchronize(s));  // inv goes out of scope
     }
 
     void refresh_left(int j, const double2* A, int chil, int chir) {  // beta[j+1] from beta[j], A_j
@@ -633,11 +768,34 @@ struct SegRun {
         }
     }
 
+    // A phase of the one-site schedule: its boundary pairs, its site
+    // exponentials (batched like the two-site schedule's) and its bond steps;
+    // the ops of a phase are independent, so running them kind by kind is
+    // the same as any other order.
+    void run_one_site_phase(const SPhase& ph, bool first, int idx) {
+        SPhase pairs, sites, bonds;
+        for (const auto& op : ph) (op.bond ? bonds : (op.pair ? pairs : sites)).push_back(op);
+        if (!pairs.empty()) {
+            if (o.batched) run_batched(pairs, true, first, 1000 + 2 * idx);
+            else run_serial(pairs, true);
+        }
+        if (!sites.empty()) {
+            if (o.batched) run_batched(sites, false, first, 1001 + 2 * idx);
+            else run_serial(sites, false);
+        }
+        for (const auto& op : bonds) bond_step(op.j, op.tau, op.refresh);
+    }
+
     void step(double dt) {
         reset_flag(ctx, sg->flag.as<int>());
         const auto t0 = std::chrono::steady_clock::now();
         for (int half = 0; half < 2; ++half) {
             const bool first = half == 0;
+            if (o.one_site) {
+                const std::vector<SPhase> phases = seg_schedule1(sg->sizes, dt, first);
+                for (size_t idx = 0; idx < phases.size(); ++idx) run_one_site_phase(phases[idx], first, (int)idx);
+                continue;
+            }
             const std::vector<SPhase> phases = seg_schedule(sg->sizes, dt, first);
             for (size_t idx = 0; idx < phases.size(); ++idx) {
                 const SPhase& ph = phases[idx];
@@ -846,6 +1004,7 @@ int tdvp_seg_opts_default(tdvp_seg_opts* o) {
     o->batched = 1;
     o->use_graph = 0;
     o->svd_mode = 0;
+    o->one_site = 0;
     return TDVP_OK;
 }
 
@@ -914,6 +1073,11 @@ int seg_step(tdvp_ctx ctx, tdvp_seg sg, tdvp_mpo mpo, double dt, const tdvp_seg_
         TDVP_REQUIRE(!o.use_graph || (o.batched && o.static_shapes), TDVP_E_ARG,
                      "seg_step: graphs need the batched path with static shapes");
         TDVP_REQUIRE(o.svd_mode >= 0 && o.svd_mode <= 2, TDVP_E_ARG, "seg_step: svd_mode must be 0, 1 or 2");
+        TDVP_REQUIRE(o.one_site == 0 || o.one_site == 1, TDVP_E_ARG, "seg_step: one_site must be 0 or 1");
+        if (o.one_site)
+            for (size_t s = 1; s + 1 < sg->sizes.size(); ++s)
+                TDVP_REQUIRE(sg->sizes[s] >= 3, TDVP_E_SHAPE,
+                             "seg_step: the one-site schedule needs at least three sites in every inner segment");
         tdvp_stats st{};
         const bool fp64 = sg->edt == Dt::C128;
         SegRun r{ctx, sg, mpo, o, st, fp64, fp64 ? 4 : 3};

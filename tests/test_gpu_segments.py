@@ -150,6 +150,63 @@ def test_reorthonormalize_matches_oracle(ctx, dt_):
         assert abs(ov - 1.0) <= 1e-10
 
 
+ONE_SITE_CASES = [
+    # N, sizes, chi_lo, chi_hi, seed
+    (20, [4, 3, 3, 3, 3, 4], 6, 24, 41),
+    (16, [16], 4, 20, 43),
+]
+
+
+@pytest.mark.parametrize("batched", [True, False])
+@pytest.mark.parametrize("dt_", ["c128", "c64"])
+@pytest.mark.parametrize("cs", ONE_SITE_CASES, ids=lambda c: f"N{c[0]}_p{len(c[1])}")
+def test_one_site_segment_steps_match_oracle(ctx, cs, dt_, batched):
+    """The one-site schedule (site steps forward, zero-site bond steps
+    backward, two-site boundary pairs) against the oracle's step1."""
+    import paper_1912_06127_amd as pkg
+    N, sizes, lo, hi, seed = cs
+    print(f"one-site segments N={N} sizes={sizes} {dt_} batched={batched}", flush=True)
+    chi, T = case(N, sizes, lo, hi, seed)
+    *_, Ws = xy_mpo(N)
+    W = pkg.MPO.from_tensors(ctx, Ws)
+    sg = pkg.Segments.init(ctx, W, T, sizes, compute=dt_)
+    st_o = oseg.SegmentState(T, Ws, chi_static=chi[1:], kmax=8, tol=0.0)
+    opts = pkg.SegmentOptions(compute=dt_, batched=batched, one_site=True)
+    for s in range(2):
+        oseg.step1(st_o, sizes, 0.02)
+        info = sg.step(W, 0.02, opts)
+        assert info["matvecs"] > 0
+        Tg, To = sg.tensors(), st_o.tensors()
+        err = np.max(np.abs(sz_profile(Tg) - sz_profile(To)))
+        assert err <= OBS_TOL[dt_], (s, err)
+    assert sg.chi == chi
+    if dt_ == "c128":
+        ov = abs(omps.overlap(Tg, To)) / np.sqrt(omps.norm2(Tg) * omps.norm2(To))
+        assert abs(ov - 1.0) <= 1e-10
+        assert abs(sg.w_total - st_o.stats.w_total) <= 1e-10 * max(1.0, st_o.stats.w_total)
+        assert abs(sg.norm2() - oseg.norm2(st_o)) <= 1e-10
+
+
+@pytest.mark.parametrize("sizes", [[5, 5], [3, 4]])
+def test_one_site_segments_full_rank_match_exact_evolution(ctx, sizes):
+    import paper_1912_06127_amd as pkg
+    N = sum(sizes)
+    print(f"one-site segments full rank {sizes}", flush=True)
+    c, lam, pairs, Ws = xy_mpo(N)
+    g = ompo.eval_exponentials(c, lam, N - 1)
+    H = spin.longrange_hamiltonian(N, g, pairs)
+    T = omps.normalize_centre(omps.right_canonicalize(wl.random_site_tensors(90, wl.full_rank_bonds(N, 2), 2)))
+    psi0 = omps.to_dense(T)
+    W = pkg.MPO.from_tensors(ctx, Ws)
+    sg = pkg.Segments.init(ctx, W, T, sizes, compute="c128")
+    for _ in range(4):
+        sg.step(W, 0.05, pkg.SegmentOptions(compute="c128", krylov_k=16, one_site=True))
+    ref = spin.ExactEvolution(H).evolve(psi0, 0.2)
+    got = omps.to_dense(sg.tensors())
+    assert abs(abs(np.vdot(ref, got)) - 1.0) < 1e-10
+    assert np.linalg.norm(got - ref) < 1e-9
+
+
 def test_batched_equals_instance_by_instance(ctx):
     import paper_1912_06127_amd as pkg
     N, sizes, lo, hi, seed = SEG_CASES[2]
@@ -206,3 +263,10 @@ def test_segment_arguments_are_checked(ctx):
         sg.step(W, 0.01, pkg.SegmentOptions(compute="c128"))
     with pytest.raises(pkg.TDVPError):  # graphs need static shapes
         sg.step(W, 0.01, pkg.SegmentOptions(compute="c64", static_shapes=False, use_graph=True))
+    N = 10
+    chi, T = case(N, [3, 2, 2, 3], 2, 8, 5)
+    *_, Ws = xy_mpo(N)
+    W = pkg.MPO.from_tensors(ctx, Ws)
+    sg = pkg.Segments.init(ctx, W, T, [3, 2, 2, 3], compute="c64")
+    with pytest.raises(pkg.TDVPError):  # one-site schedule: inner segments need three sites
+        sg.step(W, 0.01, pkg.SegmentOptions(compute="c64", one_site=True))
