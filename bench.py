@@ -226,7 +226,9 @@ def segments_timing(pkg, ctx, np, graph=True):
     One untimed step (tile tuning), one timed eager step, one step that
     captures every phase's batched exponentiation in a HIP graph and one step
     that replays them; then the norm of the state and one serial
-    reorthonormalisation with environment recompute (Sec. III D), timed.
+    reorthonormalisation with environment recompute (Sec. III D), timed; then
+    the one-site schedule (two-site boundary pairs) on the same state: one
+    untimed step (tile tuning for the one-site shapes) and one timed step.
     """
     import workloads as wl
     p = wl.XY_N201
@@ -282,6 +284,20 @@ def segments_timing(pkg, ctx, np, graph=True):
     ctx.sync()
     res["reorth_s"] = round(time.perf_counter() - t0, 2)
     res["norm_drift_after_reorth"] = sg.norm2() - 1.0
+    progress("segments: one-site schedule, warm-up step (tile tuning)")
+    o1 = pkg.SegmentOptions(one_site=True)
+    sg.step(mpo, p["dt"], o1)
+    progress("segments: one-site schedule, timed step")
+    ctx.profile(True)
+    st1 = sg.step(mpo, p["dt"], o1)
+    prof1 = ctx.profile_read()
+    ctx.profile(False)
+    res["one_site"] = {"s_per_step": round(st1["seconds"], 3), "flops_per_step": st1["flops"],
+                       "matvecs_per_step": st1["matvecs"],
+                       "batched_expm_s": round(prof1.get("seg_batched_expm", {}).get("ms", 0.0) * 1e-3, 3),
+                       "bond_steps_s": round(prof1.get("seg_bonds", {}).get("ms", 0.0) * 1e-3, 3),
+                       "boundary_splits_s": round(prof1.get("seg_splits", {}).get("ms", 0.0) * 1e-3, 3),
+                       "chi_unchanged": sg.chi == chi, "w_total": sg.w_total}
     sg.close()
     mpo.close()
     res["workload"] = ("segment-parallel 2TDVP, N=201 XY alpha=1.5 (K=6, w=14), 32 segments 11|6x30|10, "

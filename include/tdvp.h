@@ -295,12 +295,16 @@ typedef struct {
     int one_site;        /* 1: the parallel one-site scheme proposed in the
                             Discussion, with two-site boundary pairs (a reading):
                             one-site sweeps inside the segments, zero-site bond
-                            steps (QR/LQ, exponential, SVD back to the inverse
-                            canonical form), the boundary pairs and their timing
-                            as in the two-site schedule; bond dimensions change only
-                            at boundary splits.  Inner segments need at least three
-                            sites (TDVP_E_SHAPE).  At one segment it is the serial
-                            one-site step.  0: the two-site schedule (Sec. III B). */
+                            steps (QR/LQ, exponential, absorbed into the next site),
+                            the boundary pairs and their timing as in the two-site
+                            schedule; bond dimensions change only at boundary
+                            splits.  Inner bonds then hold V_j = 1 (the mixed
+                            canonical form inside segments) until
+                            seg_reorthonormalize; a two-site step before that
+                            returns TDVP_E_STATE.  Inner segments need at least
+                            three sites (TDVP_E_SHAPE).  At one segment it is the
+                            serial one-site step.  0: the two-site schedule
+                            (Sec. III B). */
 } tdvp_seg_opts;
 
 /* Defaults: C64, krylov_k 8, chi_max 1<<30, w_max 0, eps_rel 0, guard on,
@@ -328,7 +332,8 @@ int seg_get_info(tdvp_seg seg, int* N, int* d, int* chi, double* w_total);
 /* Psi_j to host memory (complex128 [chi_j][d][chi_{j+1}]). */
 int seg_get_psi(tdvp_seg seg, int j, void* out);
 /* V_j = 1/Lambda_j of bond j (between sites j and j+1, 0-based) to host
- * memory (double [chi_{j+1}]). */
+ * memory (double [chi_{j+1}]); after one-site steps inner bonds of segments
+ * hold 1 (see tdvp_seg_opts.one_site). */
 int seg_get_bond(tdvp_seg seg, int j, double* out);
 int seg_destroy(tdvp_seg seg);
 /* <psi|psi> of the state Psi_0 V_0 Psi_1 ... Psi_{N-1} as it stands, in FP64

@@ -37,6 +37,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <exception>
+#include <functional>
 #include <thread>
 
 namespace tdvp {
@@ -233,6 +234,7 @@ struct tdvp_seg_s {
     double w_total = 0.0;
     std::map<std::string, std::unique_ptr<PhasePlan>> plans;
     DevMem flag;                     // device int: non-finite value seen during a step
+    bool mixed_gauge = false;        // one-site steps left unit V on inner bonds
     hipStream_t cap_stream = nullptr; // graphs are captured here (the context stream may be the null stream)
     std::vector<std::unique_ptr<SegLane>> lanes;
     hipEvent_t ready = nullptr;
@@ -289,10 +291,11 @@ struct SegRun {
     // refresh 1 (sweeping right): Psi_j = Q R, the bond matrix is R (V_j
     // Psi_{j+1} is right orthonormal), beta_{j+1} from Q; refresh 2 (sweeping
     // left): Psi_{j+1} = L Q', the bond matrix is L (Psi_j V_j is left
-    // orthonormal), gamma_j from Q'.  C <- exp(-i tau H_0) C and C = u s vh
-    // give back the inverse canonical form: Psi_j = (Q or Psi_j V_j) u s,
-    // V_j = 1/s, Psi_{j+1} = s vh (V_j Psi_{j+1} or Q'), and the environment
-    // on the sweep's side is rebuilt from the new isometry.
+    // orthonormal), gamma_j from Q'.  C <- exp(-i tau H_0) C is absorbed into
+    // the next site, Psi_{j+1} = C V_j Psi_{j+1} (or Psi_j = Psi_j V_j C), the
+    // isometry stays (Psi_j = Q or Psi_{j+1} = Q') and V_j = 1: inside a
+    // segment the state keeps the mixed canonical form of the serial step, and
+    // only the boundary pairs restore Schmidt values.
     void bond_step(int j, double tau, int refresh) {
         ProfScope prof(ctx, "seg_bond", 0.0, 0.0);
         const int d = sg->d, chil = sg->chi[j], c = sg->chi[j + 1], chir = sg->chi[j + 2];
@@ -314,37 +317,23 @@ struct SegRun {
         st.matvecs += ki.matvecs;
         st.flops += heff_flops(0, c, c, d, h.wl, h.wr) * ki.matvecs;
         st.krylov_max_used = std::max(st.krylov_max_used, ki.k);
-        SvdResult r = svd_rowmajor(ctx, C, c, c);
-        TDVP_REQUIRE(r.k == c, TDVP_E_SHAPE, "segment bond step: rank-deficient SVD");
-        for (double v : r.S)
-            TDVP_REQUIRE(v > 0.0 && std::isfinite(v), TDVP_E_NUMERIC,
-                         "segment bond step: a singular value of the bond matrix is zero or not finite");
-        double2* T = ws("seg_bT", (size_t)rows * c);
-        double2* X = ws("seg_bX", (size_t)c * cols);
         if (refresh == 1) {
-            zgemm_rowmajor(ctx, Q, r.U, T, rows, c, c);  // A_j = Q u
+            double2* X = ws("seg_bX", (size_t)c * cols);
             copy2d(X, cols, sg->psi(j + 1), cols, c, cols, 0, s);
             scale_rows(X, cols, sg->Vd[j].as<double>(), c, cols, s);
-            zgemm_rowmajor(ctx, r.Vh, X, sg->psi(j + 1), c, c, cols);  // vh V_j Psi_{j+1}
-            scale_rows(sg->psi(j + 1), cols, r.S_dev, c, cols, s);
-            copy2d(sg->psi(j), c, T, c, rows, c, 0, s);
-            scale_cols(sg->psi(j), c, r.S_dev, rows, c, s);
-            refresh_left(j, T, chil, c);
+            zgemm_rowmajor(ctx, C, X, sg->psi(j + 1), c, c, cols);  // C V_j Psi_{j+1}
+            copy2d(sg->psi(j), c, Q, c, rows, c, 0, s);
         } else {
-            zgemm_rowmajor(ctx, r.Vh, Q, X, c, c, cols);  // B_{j+1} = vh Q'
+            double2* T = ws("seg_bT", (size_t)rows * c);
             copy2d(T, c, sg->psi(j), c, rows, c, 0, s);
             scale_cols(T, c, sg->Vd[j].as<double>(), rows, c, s);
-            zgemm_rowmajor(ctx, T, r.U, sg->psi(j), rows, c, c);  // Psi_j V_j u
-            scale_cols(sg->psi(j), c, r.S_dev, rows, c, s);
-            copy2d(sg->psi(j + 1), cols, X, cols, c, cols, 0, s);
-            scale_rows(sg->psi(j + 1), cols, r.S_dev, c, cols, s);
-            refresh_right(j + 1, X, c, chir);
+            zgemm_rowmajor(ctx, T, C, sg->psi(j), rows, c, c);  // Psi_j V_j C
+            copy2d(sg->psi(j + 1), cols, Q, cols, c, cols, 0, s);
         }
-        std::vector<double> inv(c);
-        for (int k = 0; k < c; ++k) inv[k] = 1.0 / r.S[k];
-        sg->Vh[j] = inv;
-        TDVP_CHECK_HIP(hipMemcpyAsync(sg->Vd[j].ptr, inv.data(), sizeof(double) * c, hipMemcpyHostToDevice, s));
-        TDVP_CHECK_HIP(hipStreamSynchronize(s));  // inv goes out of scope
+        std::vector<double> one(c, 1.0);
+        sg->Vh[j] = one;
+        TDVP_CHECK_HIP(hipMemcpyAsync(sg->Vd[j].ptr, one.data(), sizeof(double) * c, hipMemcpyHostToDevice, s));
+        TDVP_CHECK_HIP(hipStreamSynchronize(s));  // one goes out of scope
     }
 
     void refresh_left(int j, const double2* A, int chil, int chir) {  // beta[j+1] from beta[j], A_j
@@ -696,23 +685,14 @@ struct SegRun {
     // The splits of one phase (instance i reads theta + off[i]); instances are
     // taken largest first by a pool of lanes.  Each split only touches its own
     // pair of sites, bond and environments.
-    void split_concurrent(const SPhase& ph, const double2* theta, const std::vector<int64_t>& off) {
-        const int n = (int)ph.size();
-        const int nl = std::min(lane_count(), n);
-        if (nl <= 1) {
-            for (int i = 0; i < n; ++i) split(ph[i].j, theta + off[i], ph[i].refresh);
-            return;
-        }
+    // Runs body(r, i) for the listed op indices on nl split lanes (each a
+    // host thread with its own stream, rocBLAS handle and workspaces); the
+    // lanes start after the work queued so far on the context stream, and the
+    // context stream waits for all of them.
+    void on_lanes(int nl, const std::vector<int>& order, const std::function<void(SegRun&, int)>& body) {
         ensure_lanes(nl);
-        for (const auto& op : ph) {  // operators are cached lazily; build them here, single-threaded
-            W->mop(1, op.j, fp64);
-            W->mop(3, op.j + 1, fp64);
-        }
-        std::vector<int> order(n);
-        for (int i = 0; i < n; ++i) order[i] = i;
-        std::sort(order.begin(), order.end(),
-                  [&](int a, int b) { return off[a + 1] - off[a] > off[b + 1] - off[b]; });
         TDVP_CHECK_HIP(hipEventRecord(sg->ready, ctx->stream));
+        const int n = (int)order.size();
         std::atomic<int> next{0};
         std::vector<std::exception_ptr> errs(nl);
         std::vector<tdvp_stats> lst(nl);
@@ -725,10 +705,7 @@ struct SegRun {
                     TDVP_CHECK_HIP(hipStreamWaitEvent(L.c.stream, sg->ready, 0));
                     lst[l] = tdvp_stats{};
                     SegRun r{&L.c, sg, W, o, lst[l], fp64, form};
-                    for (int t = next++; t < n; t = next++) {
-                        const int i = order[t];
-                        r.split(ph[i].j, theta + off[i], ph[i].refresh);
-                    }
+                    for (int t = next++; t < n; t = next++) body(r, order[t]);
                     TDVP_CHECK_HIP(hipEventRecord(L.done, L.c.stream));
                 } catch (...) {
                     errs[l] = std::current_exception();
@@ -740,9 +717,50 @@ struct SegRun {
             if (!errs[l]) TDVP_CHECK_HIP(hipStreamWaitEvent(ctx->stream, sg->lanes[l]->done, 0));
             st.w_step += lst[l].w_step;
             st.flops += lst[l].flops;
+            st.matvecs += lst[l].matvecs;
+            st.krylov_max_used = std::max(st.krylov_max_used, lst[l].krylov_max_used);
         }
         for (auto& e : errs)
             if (e) std::rethrow_exception(e);
+    }
+
+    void split_concurrent(const SPhase& ph, const double2* theta, const std::vector<int64_t>& off) {
+        const int n = (int)ph.size();
+        const int nl = std::min(lane_count(), n);
+        if (nl <= 1) {
+            for (int i = 0; i < n; ++i) split(ph[i].j, theta + off[i], ph[i].refresh);
+            return;
+        }
+        for (const auto& op : ph) {  // operators are cached lazily; build them here, single-threaded
+            W->mop(1, op.j, fp64);
+            W->mop(3, op.j + 1, fp64);
+        }
+        std::vector<int> order(n);
+        for (int i = 0; i < n; ++i) order[i] = i;
+        std::sort(order.begin(), order.end(),
+                  [&](int a, int b) { return off[a + 1] - off[a] > off[b + 1] - off[b]; });
+        on_lanes(nl, order, [&](SegRun& r, int i) { r.split(ph[i].j, theta + off[i], ph[i].refresh); });
+    }
+
+    // The bond steps of a phase (one per segment at most, on disjoint
+    // tensors and environments), concurrently on the split lanes.
+    void bonds_concurrent(const SPhase& ph) {
+        const int n = (int)ph.size();
+        const int nl = std::min(lane_count(), n);
+        if (nl <= 1) {
+            for (const auto& op : ph) bond_step(op.j, op.tau, op.refresh);
+            return;
+        }
+        for (const auto& op : ph) {
+            W->mop(0, op.j, fp64);
+            W->mop(1, op.j, fp64);
+            W->mop(3, op.j + 1, fp64);
+        }
+        std::vector<int> order(n);
+        for (int i = 0; i < n; ++i) order[i] = i;
+        std::sort(order.begin(), order.end(), [&](int a, int b) { return sg->chi[ph[a].j + 1] > sg->chi[ph[b].j + 1]; });
+        ProfScope ps(ctx, "seg_bonds", 0.0, 0.0);
+        on_lanes(nl, order, [&](SegRun& r, int i) { r.bond_step(ph[i].j, ph[i].tau, ph[i].refresh); });
     }
 
     // Instance by instance (reference for the batched path).
@@ -783,7 +801,9 @@ struct SegRun {
             if (o.batched) run_batched(sites, false, first, 1001 + 2 * idx);
             else run_serial(sites, false);
         }
-        for (const auto& op : bonds) bond_step(op.j, op.tau, op.refresh);
+        if (o.batched) bonds_concurrent(bonds);
+        else
+            for (const auto& op : bonds) bond_step(op.j, op.tau, op.refresh);
     }
 
     void step(double dt) {
@@ -792,6 +812,7 @@ struct SegRun {
         for (int half = 0; half < 2; ++half) {
             const bool first = half == 0;
             if (o.one_site) {
+                sg->mixed_gauge = true;
                 const std::vector<SPhase> phases = seg_schedule1(sg->sizes, dt, first);
                 for (size_t idx = 0; idx < phases.size(); ++idx) run_one_site_phase(phases[idx], first, (int)idx);
                 continue;
@@ -985,6 +1006,7 @@ void reorthonormalize(tdvp_ctx ctx, tdvp_seg sg, tdvp_mpo W) {
     TDVP_CHECK_HIP(hipStreamSynchronize(ctx->stream));
     to_inverse_canonical(ctx, sg, 0);
     build_environments(ctx, sg, W);
+    sg->mixed_gauge = false;
 }
 
 }  // namespace
@@ -1074,6 +1096,8 @@ int seg_step(tdvp_ctx ctx, tdvp_seg sg, tdvp_mpo mpo, double dt, const tdvp_seg_
                      "seg_step: graphs need the batched path with static shapes");
         TDVP_REQUIRE(o.svd_mode >= 0 && o.svd_mode <= 2, TDVP_E_ARG, "seg_step: svd_mode must be 0, 1 or 2");
         TDVP_REQUIRE(o.one_site == 0 || o.one_site == 1, TDVP_E_ARG, "seg_step: one_site must be 0 or 1");
+        TDVP_REQUIRE(o.one_site || !sg->mixed_gauge, TDVP_E_STATE,
+                     "seg_step: after one-site steps call seg_reorthonormalize before a two-site step");
         if (o.one_site)
             for (size_t s = 1; s + 1 < sg->sizes.size(); ++s)
                 TDVP_REQUIRE(sg->sizes[s] >= 3, TDVP_E_SHAPE,

@@ -187,6 +187,33 @@ def test_one_site_segment_steps_match_oracle(ctx, cs, dt_, batched):
         assert abs(sg.norm2() - oseg.norm2(st_o)) <= 1e-10
 
 
+def test_one_site_then_two_site_goes_through_the_repair(ctx):
+    """One-site steps leave unit V on inner bonds; a two-site step is refused
+    until seg_reorthonormalize restores the Schmidt form, and the sequence
+    one-site step, repair, two-site step equals the oracle's."""
+    import paper_1912_06127_amd as pkg
+    N, sizes, lo, hi, seed = ONE_SITE_CASES[0]
+    chi, T = case(N, sizes, lo, hi, seed)
+    *_, Ws = xy_mpo(N)
+    W = pkg.MPO.from_tensors(ctx, Ws)
+    sg = pkg.Segments.init(ctx, W, T, sizes, compute="c128")
+    st_o = oseg.SegmentState(T, Ws, chi_static=chi[1:], kmax=8, tol=0.0)
+    sg.step(W, 0.02, pkg.SegmentOptions(compute="c128", one_site=True))
+    oseg.step1(st_o, sizes, 0.02)
+    with pytest.raises(pkg.TDVPError):
+        sg.step(W, 0.02, pkg.SegmentOptions(compute="c128"))
+    sg.reorthonormalize(W)
+    oseg.reorthonormalize(st_o)
+    sg.step(W, 0.02, pkg.SegmentOptions(compute="c128"))
+    oseg.step(st_o, sizes, 0.02)
+    Tg, To = sg.tensors(), st_o.tensors()
+    assert np.max(np.abs(sz_profile(Tg) - sz_profile(To))) <= 1e-10
+    ov = abs(omps.overlap(Tg, To)) / np.sqrt(omps.norm2(Tg) * omps.norm2(To))
+    assert abs(ov - 1.0) <= 1e-10
+    for j in range(N - 1):
+        assert np.allclose(np.sort(1.0 / sg.bond(j)), np.sort(1.0 / st_o.V[j]), rtol=1e-8, atol=1e-12), j
+
+
 @pytest.mark.parametrize("sizes", [[5, 5], [3, 4]])
 def test_one_site_segments_full_rank_match_exact_evolution(ctx, sizes):
     import paper_1912_06127_amd as pkg
