@@ -156,7 +156,7 @@ def ising_timing(pkg, ctx, wl):
     return res
 
 
-def sweep_timing(pkg, ctx, steps=40):
+def sweep_timing(pkg, ctx, steps=40, taylor=True):
     """2TDVP quench of the N=64 1/r^2 XXX chain (K = 6 exponentials, w = 20).
 
     Neel state (odd sites up, 1-based) with site 32 flipped; dt = 0.05,
@@ -196,19 +196,20 @@ def sweep_timing(pkg, ctx, steps=40):
                              "chi_peak": max(mps.chi), "w_total": wt}
             mps.close()
     # the FP64 evolution again with the truncated-Taylor exponential (shapes already tuned)
-    opts = pkg.TDVPOptions(compute="c128", chi_max=cap, w_max=1e-8, eps_rel=1e-12, krylov_tol=1e-10,
-                           exp_method="taylor")
-    mps = pkg.MPS.init(ctx, N, 2, [1] * (N + 1), basis_state=bits)
-    times, mv = [], 0
-    for _ in range(steps):
-        st = pkg.tdvp2_step(ctx, mps, mpo, 0.05, opts)
-        times.append(st["seconds"])
-        mv += st["matvecs"]
-    pt = 0.25 * pkg.expect(ctx, mps, list(range(N)), sz).real
-    res["c128_taylor"] = {"s_per_step": round(float(np.mean(times)), 4), "matvecs_per_step": mv / steps,
-                          "chi_peak": max(mps.chi),
-                          "max_abs_obs_diff_vs_lanczos": float(np.max(np.abs(pt - prof["c128"])))}
-    mps.close()
+    if taylor:
+        opts = pkg.TDVPOptions(compute="c128", chi_max=cap, w_max=1e-8, eps_rel=1e-12, krylov_tol=1e-10,
+                               exp_method="taylor")
+        mps = pkg.MPS.init(ctx, N, 2, [1] * (N + 1), basis_state=bits)
+        times, mv = [], 0
+        for _ in range(steps):
+            st = pkg.tdvp2_step(ctx, mps, mpo, 0.05, opts)
+            times.append(st["seconds"])
+            mv += st["matvecs"]
+        pt = 0.25 * pkg.expect(ctx, mps, list(range(N)), sz).real
+        res["c128_taylor"] = {"s_per_step": round(float(np.mean(times)), 4), "matvecs_per_step": mv / steps,
+                              "chi_peak": max(mps.chi),
+                              "max_abs_obs_diff_vs_lanczos": float(np.max(np.abs(pt - prof["c128"])))}
+        mps.close()
     mpo.close()
     res["speedup_fp32_vs_fp64"] = round(res["c128"]["s_per_step"] / res["c64"]["s_per_step"], 2)
     res["max_abs_obs_diff_c64_vs_c128"] = float(np.max(np.abs(prof["c64"] - prof["c128"])))
@@ -217,7 +218,7 @@ def sweep_timing(pkg, ctx, steps=40):
     return res
 
 
-def segments_timing(pkg, ctx, np, graph=True):
+def segments_timing(pkg, ctx, np, graph=True, extras=True):
     """Segment-parallel 2TDVP, N=201 long-range XY (alpha 1.5, K = 6, w = 14),
     32 segments (11 | 6 x 30 | 10), uneven bond profile (one seeded draw in
     [64, 1024] per segment), seeded random state, dt = 0.01, static shapes,
@@ -274,6 +275,18 @@ def segments_timing(pkg, ctx, np, graph=True):
     res["matvecs_per_step"] = st["matvecs"]
     res["chi_max"] = max(chi)
     res["w_total"] = sg.w_total
+    if extras:
+        one_site_and_repair(pkg, ctx, sg, mpo, p, chi, res)
+    sg.close()
+    mpo.close()
+    res["workload"] = ("segment-parallel 2TDVP, N=201 XY alpha=1.5 (K=6, w=14), 32 segments 11|6x30|10, "
+                       "chi per segment U{64..1024} (seeded), dt=0.01, static shapes, k=8")
+    return res
+
+
+def one_site_and_repair(pkg, ctx, sg, mpo, p, chi, res):
+    """Norm drift, the serial repair and the one-site schedule on the state
+    the two-site steps left."""
     progress("segments: norm and reorthonormalisation (serial repair)")
     t0 = time.perf_counter()
     n2 = sg.norm2()
@@ -298,11 +311,6 @@ def segments_timing(pkg, ctx, np, graph=True):
                        "bond_steps_s": round(prof1.get("seg_bonds", {}).get("ms", 0.0) * 1e-3, 3),
                        "boundary_splits_s": round(prof1.get("seg_splits", {}).get("ms", 0.0) * 1e-3, 3),
                        "chi_unchanged": sg.chi == chi, "w_total": sg.w_total}
-    sg.close()
-    mpo.close()
-    res["workload"] = ("segment-parallel 2TDVP, N=201 XY alpha=1.5 (K=6, w=14), 32 segments 11|6x30|10, "
-                       "chi per segment U{64..1024} (seeded), dt=0.01, static shapes, k=8")
-    return res
 
 
 def gradient_timing(pkg, ctx, torch, np, steps=2):
@@ -378,6 +386,9 @@ def main():
     ap.add_argument("--only-segments", action="store_true",
                     help="run only the segment-parallel N=201 workload and print its timings (for profiling)")
     ap.add_argument("--segments-no-graph", action="store_true", help="segment workload: eager steps only")
+    ap.add_argument("--segments-no-extras", action="store_true",
+                    help="segment workload: skip the repair and the one-site schedule")
+    ap.add_argument("--sweep-no-taylor", action="store_true", help="sweep workload: skip the Taylor-exponential pass")
     ap.add_argument("--only-sweep", action="store_true",
                     help="run only the N=64 2TDVP quench sweep and print its timings (for profiling)")
     ap.add_argument("--grad-steps", type=int, default=2)
@@ -398,13 +409,14 @@ def main():
 
     if args.only_sweep:
         ctx = pkg.Context(0)
-        print(json.dumps({"sweep": sweep_timing(pkg, ctx, args.sweep_steps)}))
+        print(json.dumps({"sweep": sweep_timing(pkg, ctx, args.sweep_steps, taylor=not args.sweep_no_taylor)}))
         ctx.close()
         return
 
     if args.only_segments:
         ctx = pkg.Context(0)
-        print(json.dumps({"segments": segments_timing(pkg, ctx, np, graph=not args.segments_no_graph)}))
+        print(json.dumps({"segments": segments_timing(pkg, ctx, np, graph=not args.segments_no_graph,
+                                                      extras=not args.segments_no_extras)}))
         ctx.close()
         return
 

@@ -275,6 +275,25 @@ def test_graph_replay_equals_eager(ctx, dt_):
             assert np.array_equal(a.psi(j), b.psi(j)), (s, j)
 
 
+def test_one_site_graph_replay_equals_eager(ctx):
+    """One-site schedule: the site exponentials of every phase replayed from
+    captured graphs, the bond steps and boundary splits eager in between;
+    bitwise equal to eager execution."""
+    import paper_1912_06127_amd as pkg
+    N, sizes, lo, hi, seed = ONE_SITE_CASES[0]
+    chi, T = case(N, sizes, lo, hi, seed)
+    *_, Ws = xy_mpo(N)
+    W = pkg.MPO.from_tensors(ctx, Ws)
+    a = pkg.Segments.init(ctx, W, T, sizes, compute="c64")
+    b = pkg.Segments.init(ctx, W, T, sizes, compute="c64")
+    for s in range(3):
+        print(f"one-site graph step {s}", flush=True)
+        a.step(W, 0.02, pkg.SegmentOptions(compute="c64", one_site=True))
+        b.step(W, 0.02, pkg.SegmentOptions(compute="c64", one_site=True, use_graph=True))
+        for j in range(N):
+            assert np.array_equal(a.psi(j), b.psi(j)), (s, j)
+
+
 def test_segment_arguments_are_checked(ctx):
     import paper_1912_06127_amd as pkg
     N = 8
