@@ -205,7 +205,8 @@ typedef struct {
     int chi_peak;        /* largest bond dimension after the step */
     int matvecs;         /* number of H_eff applications */
     int krylov_max_used; /* largest Krylov dimension used */
-    int flags;           /* bit 0: a Krylov run hit krylov_max unconverged */
+    int flags;           /* bit 0: a Krylov run hit krylov_max unconverged;
+                            bit 1 (seg_step): the one-site schedule ran */
 } tdvp_stats;
 
 /* Fill opts with defaults: C128, krylov_max 40, tol 1e-13, chi_max
@@ -304,7 +305,11 @@ typedef struct {
                             returns TDVP_E_STATE.  Inner segments need at least
                             three sites (TDVP_E_SHAPE).  At one segment it is the
                             serial one-site step.  0: the two-site schedule
-                            (Sec. III B). */
+                            (Sec. III B).  2: the hybrid scheme of the Discussion
+                            on segments: two-site steps until every bond holds
+                            min(chi_max, d^min(j, N-j)) (and, with static shapes, its
+                            initial dimension), one-site steps from then on
+                            (stats flags bit 1 tells which ran). */
 } tdvp_seg_opts;
 
 /* Defaults: C64, krylov_k 8, chi_max 1<<30, w_max 0, eps_rel 0, guard on,

@@ -415,6 +415,30 @@ def step1(st: SegmentState, sizes, dt: float):
     return st
 
 
+def saturated(st: SegmentState) -> bool:
+    """Every bond holds min(chi_max, d^min(j, N-j)) and, with per-bond caps,
+    its cap: the bond dimensions can grow no further."""
+    N, d = st.N, st.Psi[0].shape[1]
+    for j in range(1, N):
+        cap = st.tr.chi_max if st.chi_static is None else min(st.tr.chi_max, st.chi_static[j - 1])
+        if len(st.V[j - 1]) < min(cap, d ** min(j, N - j)):
+            return False
+    return True
+
+
+def hybrid_step(st: SegmentState, sizes, dt: float) -> bool:
+    """The hybrid scheme of the Discussion on segments: two-site steps until
+    the bond dimensions are saturated, one-site steps from then on.  Returns
+    True when the one-site schedule ran."""
+    one = getattr(st, "one_site_started", False) or saturated(st)
+    if one:
+        st.one_site_started = True
+        step1(st, sizes, dt)
+    else:
+        step(st, sizes, dt)
+    return one
+
+
 def norm2(st: SegmentState) -> float:
     """<psi|psi> of the state Psi_1 V_1 Psi_2 ... Psi_N as it stands.  The
     parallel updates break the gauge conditions at the partition boundaries,

@@ -500,7 +500,7 @@ class SegmentOptions:
     batched: bool = True
     use_graph: bool = False
     svd_mode: int = 0
-    one_site: bool = False       # one-site sweeps with two-site boundary pairs
+    one_site: bool | str = False  # one-site sweeps with two-site boundary pairs; "auto": hybrid switch
 
     def to_c(self) -> SegOpts:
         o = SegOpts()
@@ -514,7 +514,12 @@ class SegmentOptions:
         o.batched = int(self.batched)
         o.use_graph = int(self.use_graph)
         o.svd_mode = self.svd_mode
-        o.one_site = int(self.one_site)
+        if self.one_site == "auto":
+            o.one_site = 2
+        elif isinstance(self.one_site, (bool, int)) and int(self.one_site) in (0, 1):
+            o.one_site = int(self.one_site)
+        else:
+            raise ValueError(f"one_site must be a bool or 'auto', not {self.one_site!r}")
         return o
 
 

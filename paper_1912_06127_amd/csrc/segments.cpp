@@ -958,6 +958,20 @@ void build_environments(tdvp_ctx ctx, tdvp_seg sg, tdvp_mpo W) {
     TDVP_CHECK_HIP(hipStreamSynchronize(ctx->stream));
 }
 
+// The hybrid switch for segment runs: every bond holds its largest possible
+// dimension, min(chi_max, d^min(j, N-j)) and, with static shapes, its initial
+// dimension (the serial rule with the static caps added).
+bool seg_saturated(const tdvp_seg_s& sg, const tdvp_seg_opts& o) {
+    const int N = sg.N;
+    for (int j = 1; j < N; ++j) {
+        const int64_t cmax = o.static_shapes ? std::min(o.chi_max, sg.cap[j]) : o.chi_max;
+        int64_t lim = 1;
+        for (int e = 0; e < std::min(j, N - j) && lim < cmax; ++e) lim *= sg.d;
+        if (sg.chi[j] < std::min(lim, cmax)) return false;
+    }
+    return true;
+}
+
 // ------------------------------------------------------------ repair
 // <psi|psi> of Psi_0 V_0 Psi_1 ... Psi_{N-1} by left transfers of the
 // tensors A_j = Psi_j V_j (the last tensor as it stands), FP64.
@@ -1095,17 +1109,22 @@ int seg_step(tdvp_ctx ctx, tdvp_seg sg, tdvp_mpo mpo, double dt, const tdvp_seg_
         TDVP_REQUIRE(!o.use_graph || (o.batched && o.static_shapes), TDVP_E_ARG,
                      "seg_step: graphs need the batched path with static shapes");
         TDVP_REQUIRE(o.svd_mode >= 0 && o.svd_mode <= 2, TDVP_E_ARG, "seg_step: svd_mode must be 0, 1 or 2");
-        TDVP_REQUIRE(o.one_site == 0 || o.one_site == 1, TDVP_E_ARG, "seg_step: one_site must be 0 or 1");
-        TDVP_REQUIRE(o.one_site || !sg->mixed_gauge, TDVP_E_STATE,
-                     "seg_step: after one-site steps call seg_reorthonormalize before a two-site step");
+        TDVP_REQUIRE(o.one_site >= 0 && o.one_site <= 2, TDVP_E_ARG, "seg_step: one_site must be 0, 1 or 2");
         if (o.one_site)
             for (size_t s = 1; s + 1 < sg->sizes.size(); ++s)
                 TDVP_REQUIRE(sg->sizes[s] >= 3, TDVP_E_SHAPE,
                              "seg_step: the one-site schedule needs at least three sites in every inner segment");
+        // 2: the hybrid scheme (two-site steps until the bond dimensions are saturated)
+        const bool one = o.one_site == 1 || (o.one_site == 2 && (sg->mixed_gauge || seg_saturated(*sg, o)));
+        TDVP_REQUIRE(one || !sg->mixed_gauge, TDVP_E_STATE,
+                     "seg_step: after one-site steps call seg_reorthonormalize before a two-site step");
+        tdvp_seg_opts oo = o;
+        oo.one_site = one ? 1 : 0;
         tdvp_stats st{};
         const bool fp64 = sg->edt == Dt::C128;
-        SegRun r{ctx, sg, mpo, o, st, fp64, fp64 ? 4 : 3};
+        SegRun r{ctx, sg, mpo, oo, st, fp64, fp64 ? 4 : 3};
         r.step(dt);
+        if (one) st.flags |= 2;
         if (stats) *stats = st;
     });
 }

@@ -286,3 +286,23 @@ def test_one_site_parallel_error_is_first_order_and_norm_tracks_boundary_weight(
     assert b.stats.w_total > 1e-7
     assert abs(seg.norm2(b) - (1.0 - b.stats.w_total)) < 1e-10
     assert [P.shape[2] for P in b.Psi] == chi
+
+
+def test_segment_hybrid_switches_once_saturated():
+    """Discussion: two-site steps while the bond dimensions can grow, the
+    one-site schedule once every bond holds min(chi_max, d^min(j, N-j));
+    from then on the bond dimensions stay fixed."""
+    N, sizes = 12, [3, 3, 3, 3]
+    Ws, _ = xxx(N)
+    T0 = omps.normalize_centre(omps.right_canonicalize(wl.random_site_tensors(21, wl.full_rank_bonds(N, 2, 3), 2)))
+    st = seg.SegmentState(T0, Ws, otdvp.Truncation(chi_max=8))
+    assert not seg.saturated(st)
+    ran = []
+    for _ in range(4):
+        ran.append(seg.hybrid_step(st, sizes, 0.05))
+        if ran[-1]:
+            chi = [len(v) for v in st.V]
+    assert ran[0] is False and ran[-1] is True
+    assert ran.index(True) >= 1 and all(ran[ran.index(True):])
+    assert seg.saturated(st) and [len(v) for v in st.V] == chi
+    assert max(len(v) for v in st.V) == 8
