@@ -194,7 +194,9 @@ typedef struct {
                             theta_m (unit roundoff 2^-53) and a 16-step Lanczos
                             enclosure of the spectrum, shifted to its midpoint;
                             terms stop at max(2^-53, krylov_tol) relative.
-                            krylov_max does not apply.  TDVP_E_ARG otherwise. */
+                            krylov_max does not apply; TDVP_E_ARG if |dt| ||H_eff||
+                            would need more than 1e5 scaling steps.  TDVP_E_ARG for
+                            other values. */
 } tdvp_opts;
 
 typedef struct {

@@ -308,6 +308,7 @@ KrylovInfo ground_krylov(tdvp_ctx ctx, const MatVec& op, double2* theta, int64_t
 namespace {
 #include "taylor_theta.inc"
 constexpr int kIntervalSteps = 16;
+constexpr double kTaylorMaxSteps = 1e5;
 }  // namespace
 
 // Truncated Taylor series with scaling (Al-Mohy and Higham 2011), applied
@@ -332,6 +333,8 @@ KrylovInfo expm_taylor(tdvp_ctx ctx, const MatVec& op, double2* theta, int64_t n
     const double rho = 0.5 * (iv[1] - iv[0]) * 1.05;
     const double anorm = std::fabs(tau) * rho;
     TDVP_REQUIRE(std::isfinite(anorm), TDVP_E_NUMERIC, "Taylor exponential: non-finite spectral bound");
+    TDVP_REQUIRE(anorm <= kTaylorTheta[kTaylorMaxDegree] * kTaylorMaxSteps, TDVP_E_ARG,
+                 "Taylor exponential: |tau| ||H_eff|| needs more than 1e5 scaling steps");
     int m = 0, s = 1;
     if (anorm > 0.0) {
         double best = 0.0;
