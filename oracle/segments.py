@@ -404,13 +404,17 @@ def schedule1(sizes, dt: float, first_half: bool):
     return phases
 
 
-def step1(st: SegmentState, sizes, dt: float):
+def step1(st: SegmentState, sizes, dt: float, order=None):
     """One time step of the segment-parallel one-site scheme.  The state
     should be built with ``chi_static`` equal to its bond profile so that the
-    boundary pairs keep the bond dimensions fixed."""
+    boundary pairs keep the bond dimensions fixed.  ``order`` as in ``step``."""
     for first in (True, False):
         for ph in schedule1(sizes, dt, first):
-            for op in ph.ops:
+            ops = ph.ops
+            if order is not None:
+                rank = {s: i for i, s in enumerate(order)}
+                ops = sorted(ops, key=lambda o: rank[o.segment])
+            for op in ops:
                 st.run(op)
     return st
 

@@ -306,3 +306,18 @@ def test_segment_hybrid_switches_once_saturated():
     assert ran.index(True) >= 1 and all(ran[ran.index(True):])
     assert seg.saturated(st) and [len(v) for v in st.V] == chi
     assert max(len(v) for v in st.V) == 8
+
+
+def test_one_site_segment_order_does_not_change_the_result():
+    N = 13
+    Ws, _ = xxx(N)
+    T0 = omps.normalize_centre(omps.right_canonicalize(wl.random_site_tensors(17, wl.full_rank_bonds(N, 2, 8), 2)))
+    chi = [A.shape[2] for A in T0]
+    sizes = [3, 4, 3, 3]
+    a = seg.SegmentState(T0, Ws, chi_static=chi)
+    b = seg.SegmentState(T0, Ws, chi_static=chi)
+    for _ in range(2):
+        seg.step1(a, sizes, 0.05)
+        seg.step1(b, sizes, 0.05, order=[3, 1, 0, 2])
+    for x, y in zip(a.Psi, b.Psi):
+        assert np.array_equal(x, y)
