@@ -116,3 +116,21 @@ def test_refined_fit_lowers_the_maximum_error():
     f = 0.7 * 0.9 ** r + 0.3 * (-0.5) ** r
     c, lam, err = fit.fit_exponentials(f, 2, refine=True)
     assert err < 1e-13
+
+
+def test_taylor_degree_bounds_are_reproduced_by_their_generator():
+    """The shipped table is what its generator computes from the definition
+    (a few degrees, recomputed here in 80-digit arithmetic)."""
+    import importlib.util
+    pytest.importorskip("mpmath")
+    path = os.path.join(ROOT, "paper_1912_06127_amd", "csrc", "taylor_theta.py")
+    spec = importlib.util.spec_from_file_location("taylor_theta_gen", path)
+    gen = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(gen)
+    text = open(os.path.join(ROOT, "paper_1912_06127_amd", "csrc", "taylor_theta.inc")).read()
+    vals = {int(m): float(v) for v, m in re.findall(r"^\s+([0-9.eE+-]+),\s+// m = (\d+)$", text, flags=re.M)}
+    fact = [gen.mp.mpf(1)]
+    for n in range(1, gen.K + 1):
+        fact.append(fact[-1] * n)
+    for m in (2, 12, 55):
+        assert abs(float(gen.theta(m, fact)) / vals[m] - 1.0) < 1e-14, m
