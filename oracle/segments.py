@@ -40,7 +40,9 @@ step (Sec. III A):
 
 One-site variant (``schedule1``, ``step1``; proposed in the Discussion
 without a boundary rule): one-site sweeps inside the segments and the same
-two-site boundary pairs; see ``schedule1`` for the reading.
+two-site boundary pairs; see ``schedule1`` for the reading.  ``hybrid_step``
+runs two-site steps until the bond dimensions are saturated (``saturated``)
+and the one-site schedule from then on.
 
 Repair (Sec. III D, Fig. reorth): the parallel updates break the gauge at
 the partition boundaries and the norm drifts; ``reorthonormalize`` brings the
