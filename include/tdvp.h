@@ -365,6 +365,13 @@ int seg_reorthonormalize(tdvp_ctx ctx, tdvp_seg seg, tdvp_mpo mpo);
  * TDVP_E_SHAPE if it exceeds max_ops (outputs may then be NULL). */
 int seg_schedule(int nseg, const int* seg_sizes, double dt, int first_half, int max_ops, int* phase,
                  int* kind, int* site, double* tau, int* n_out);
+/* The operations of one half step of the one-site schedule
+ * (tdvp_seg_opts.one_site), host only, in the layout of seg_schedule: kind 2
+ * boundary pair forward, 1 site forward, 3 bond (site, site+1) backward while
+ * sweeping right, 4 the same while sweeping left.  TDVP_E_SHAPE also when an
+ * inner segment has fewer than three sites. */
+int seg_schedule1(int nseg, const int* seg_sizes, double dt, int first_half, int max_ops, int* phase,
+                  int* kind, int* site, double* tau, int* n_out);
 
 /* ------------------------------------------------------ raw-pointer kernels */
 

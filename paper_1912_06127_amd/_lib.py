@@ -112,6 +112,7 @@ SIGNATURES = {
     "seg_norm2": (_I, [_P, _P, _PD]),
     "seg_reorthonormalize": (_I, [_P, _P, _P]),
     "seg_schedule": (_I, [_I, _PI, _D, _I, _I, _PI, _PI, _PI, _PD, _PI]),
+    "seg_schedule1": (_I, [_I, _PI, _D, _I, _I, _PI, _PI, _PI, _PD, _PI]),
     "tdvp_profile_enable": (_I, [_P, _I]),
     "tdvp_ctx_set_gemm_form": (_I, [_P, _I]),
     "tdvp_profile_read": (_I, [_P, _I, C.c_char_p, _PD, _PD, _PD, C.POINTER(C.c_long), _PI]),

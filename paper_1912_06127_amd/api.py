@@ -523,19 +523,21 @@ class SegmentOptions:
         return o
 
 
-def segment_schedule(sizes, dt: float, first_half: bool):
-    """[(phase, kind, site, tau)] of one half step as the library runs it (kind 2 pair, 1 site)."""
+def segment_schedule(sizes, dt: float, first_half: bool, one_site: bool = False):
+    """[(phase, kind, site, tau)] of one half step as the library runs it (kind 2 pair, 1 site;
+    one-site schedule: 3 / 4 bond sweeping right / left)."""
     sz = np.ascontiguousarray(sizes, dtype=np.int32)
     n = C.c_int()
     lib = _lib.load()
-    rc = lib.seg_schedule(len(sz), _iptr(sz), float(dt), int(first_half), 0, None, None, None, None, C.byref(n))
+    fn = lib.seg_schedule1 if one_site else lib.seg_schedule
+    rc = fn(len(sz), _iptr(sz), float(dt), int(first_half), 0, None, None, None, None, C.byref(n))
     if rc != 0 and not (rc == 2 and n.value > 0):  # 2: the count exceeds max_ops = 0
         raise TDVPError(rc, "seg_schedule rejected the segment sizes")
     m = n.value
     ph, kd, st = (np.zeros(m, dtype=np.int32) for _ in range(3))
     tau = np.zeros(m)
-    rc = lib.seg_schedule(len(sz), _iptr(sz), float(dt), int(first_half), m, _iptr(ph), _iptr(kd), _iptr(st),
-                          _dptr(tau), C.byref(n))
+    rc = fn(len(sz), _iptr(sz), float(dt), int(first_half), m, _iptr(ph), _iptr(kd), _iptr(st), _dptr(tau),
+            C.byref(n))
     if rc != 0:
         raise TDVPError(rc, "seg_schedule failed")
     return [(int(a), int(b), int(c), float(t)) for a, b, c, t in zip(ph, kd, st, tau)]

@@ -1200,6 +1200,31 @@ int seg_schedule(int nseg, const int* seg_sizes, double dt, int first_half, int 
     return n <= max_ops ? TDVP_OK : TDVP_E_SHAPE;
 }
 
+int seg_schedule1(int nseg, const int* seg_sizes, double dt, int first_half, int max_ops, int* phase, int* kind,
+                  int* site, double* tau, int* n_out) {
+    if (!seg_sizes || !n_out || nseg < 1 || (nseg > 1 && nseg % 2)) return TDVP_E_ARG;
+    int N = 0;
+    for (int s = 0; s < nseg; ++s) {
+        if (seg_sizes[s] < 2 || (s > 0 && s + 1 < nseg && seg_sizes[s] < 3)) return TDVP_E_SHAPE;
+        N += seg_sizes[s];
+    }
+    if (N < 4) return TDVP_E_SHAPE;
+    const auto phases = seg_schedule1(std::vector<int>(seg_sizes, seg_sizes + nseg), dt, first_half != 0);
+    int n = 0;
+    for (size_t p = 0; p < phases.size(); ++p)
+        for (const auto& op : phases[p]) {
+            if (n < max_ops && phase && kind && site && tau) {
+                phase[n] = (int)p;
+                kind[n] = op.bond ? (op.refresh == 1 ? 3 : 4) : (op.pair ? 2 : 1);
+                site[n] = op.j;
+                tau[n] = op.tau;
+            }
+            ++n;
+        }
+    *n_out = n;
+    return n <= max_ops ? TDVP_OK : TDVP_E_SHAPE;
+}
+
 int seg_destroy(tdvp_seg sg) {
     if (!sg) return TDVP_E_ARG;
     (void)hipStreamSynchronize(sg->ctx->stream);

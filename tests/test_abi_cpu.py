@@ -100,6 +100,24 @@ def test_library_segment_schedule_equals_oracle(sizes):
         pkg.segment_schedule([3, 3, 3], 0.1, True)
 
 
+@pytest.mark.parametrize("sizes", [[10], [5, 5], [2, 3, 3, 2], [3, 4, 4, 3, 3, 3], [11] + [6] * 30 + [10]])
+def test_library_one_site_schedule_equals_oracle(sizes):
+    """The one-site schedule (host logic) lists the oracle's operations phase by phase."""
+    import paper_1912_06127_amd as pkg
+    from oracle import segments as oseg
+    code = {"pair": 2, "site": 1}
+    for first in (True, False):
+        got = pkg.segment_schedule(sizes, 0.1, first, one_site=True)
+        ref = []
+        for p, ph in enumerate(oseg.schedule1(sizes, 0.1, first)):
+            for op in ph.ops:
+                k = code.get(op.kind) or (3 if op.refresh == "left" else 4)
+                ref.append((p, k, op.j, op.tau))
+        assert sorted(got) == sorted(ref)
+    with pytest.raises(pkg.TDVPError):
+        pkg.segment_schedule([3, 2, 2, 3], 0.1, True, one_site=True)
+
+
 def test_refined_fit_lowers_the_maximum_error():
     """Levenberg-Marquardt with Lawson reweighting after the matrix pencil:
     never worse, clearly better on power laws, every channel still decaying,
