@@ -575,7 +575,9 @@ class Segments:
         st = Stats()
         _check(self.ctx.handle, _lib.load().seg_step(self.ctx.handle, self.handle, mpo.handle, float(dt),
                                                      C.byref(o), C.byref(st)))
-        return st.as_dict()
+        out = st.as_dict()
+        out["one_site"] = bool(st.flags & 2)  # which schedule ran (the "auto" mode decides per step)
+        return out
 
     @property
     def chi(self):
