@@ -102,12 +102,47 @@ def test_observables_match_dense():
     zz = mps.expect_two_point(T, 2, 6, spin.SZ, spin.SX)
     ref = spin.expval(psi, spin.site_op(spin.SZ, 2, N) @ spin.site_op(spin.SX, 6, N))
     assert abs(zz - ref) < 1e-13
+    # same site: Oi(i) Oj(i) is the operator product Oi Oj on site i (non-commuting
+    # pair, so a swapped order fails), and both argument orders of i > j
+    for i, j in ((4, 4), (7, 3)):
+        got = mps.expect_two_point(T, i, j, spin.SX, spin.SY)
+        ref = spin.expval(psi, spin.site_op(spin.SX, i, N) @ spin.site_op(spin.SY, j, N))
+        assert abs(got - ref) < 1e-13, (i, j, got, ref)
+    assert abs(mps.expect_two_point(T, 4, 4, spin.SX, spin.SY) - 1j * z[3]) < 1e-13  # sx sy = i sz
     T2 = random_canonical(N, 12)
     assert abs(mps.overlap(T, T2) - np.vdot(psi, mps.to_dense(T2))) < 1e-13
     c, lam, g = fitted_xxx(N, 3)
     Ws = mpo.mpo_exponentials(N, c, lam, spin.xxx_pairs())
     H = spin.longrange_hamiltonian(N, g, spin.xxx_pairs())
     assert abs(mps.mpo_expectation(T, Ws) - spin.expval(psi, H)) < 1e-12
+
+
+def test_infidelity_matches_dense_and_closed_form():
+    """Infidelity of Sec. IV: 1 - |<psi1|psi2>| / (||psi1|| ||psi2||) (modulus, not squared)."""
+    N = 7
+    T1 = random_canonical(N, 21)
+    T2 = random_canonical(N, 22)
+    # unnormalised inputs: scale one site of each state
+    T1[3] = 1.7 * T1[3]
+    T2[5] = (0.4 - 0.3j) * T2[5]
+    a, b = mps.to_dense(T1), mps.to_dense(T2)
+    ref = 1.0 - abs(np.vdot(a, b)) / (np.linalg.norm(a) * np.linalg.norm(b))
+    assert abs(mps.infidelity(T1, T2) - ref) < 1e-13
+    # a global phase and a scale leave it at zero
+    T3 = [A.copy() for A in T1]
+    T3[0] = np.exp(0.9j) * 2.5 * T3[0]
+    assert abs(mps.infidelity(T1, T3)) < 1e-13
+    # product states cos t|up> + sin t|down> on every site: 1 - |cos(t1 - t2)|^N
+    def product(t):
+        A = np.zeros((1, 2, 1), dtype=np.complex128)
+        A[0, 0, 0], A[0, 1, 0] = np.cos(t), np.sin(t)
+        return [A.copy() for _ in range(N)]
+    t1, t2 = 0.3, 1.1
+    assert abs(mps.infidelity(product(t1), product(t2)) - (1.0 - abs(np.cos(t1 - t2)) ** N)) < 1e-14
+    # orthogonal product states (up vs down at one site): infidelity 1
+    P, Q = product(0.0), product(0.0)
+    Q[2] = product(np.pi / 2)[2]
+    assert abs(mps.infidelity(P, Q) - 1.0) < 1e-15
 
 
 # ------------------------------------------------ environments (Sec. III A)
