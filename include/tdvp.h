@@ -315,7 +315,7 @@ typedef struct {
 } tdvp_seg_opts;
 
 /* Defaults: C64, krylov_k 8, chi_max 1<<30, w_max 0, eps_rel 0, guard on,
- * static_shapes 1, batched 1, use_graph 0, svd_mode 0. */
+ * static_shapes 1, batched 1, use_graph 0, svd_mode 0, one_site 0. */
 int tdvp_seg_opts_default(tdvp_seg_opts* opts);
 
 /* Build the segmented state from host site tensors (complex128
@@ -330,7 +330,12 @@ int tdvp_seg_opts_default(tdvp_seg_opts* opts);
 int seg_init(tdvp_ctx ctx, tdvp_mpo mpo, int N, int d, const int* chi, const void* const* tensors,
              int nseg, const int* seg_sizes, tdvp_dtype compute, tdvp_seg* out);
 /* One time step of size dt.  TDVP_E_NUMERIC if a Krylov recursion produced a
- * non-finite value or a kept singular value is zero. */
+ * non-finite value or a kept singular value is zero.  The per-segment splits
+ * and bond steps of a phase run on up to TDVP_SEG_LANES (default 8) library
+ * worker threads, each with its own stream and rocBLAS handle; their
+ * workspaces come from hipMalloc (the context's allocator callback is called
+ * only from the calling thread, which also sizes every state buffer and every
+ * solver workspace of the phase before the workers start). */
 int seg_step(tdvp_ctx ctx, tdvp_seg seg, tdvp_mpo mpo, double dt, const tdvp_seg_opts* opts,
              tdvp_stats* stats);
 /* N, d, the bond dimensions chi[N+1] and the cumulative discarded weight

@@ -134,6 +134,19 @@ struct GramResult {
     int n;
 };
 GramResult gram_eigen(tdvp_ctx ctx, const double2* M, int rows, int cols, bool left);
+// Largest dense problems a context's solver calls will see: reserves the
+// device memory rocSOLVER needs for them (rocBLAS's device-memory size query)
+// and the named workspaces of the calls above, and installs that memory as
+// the handle's workspace, so that the calls themselves allocate nothing.
+// Sizes <= 0 are skipped.  Grow-only: a later reservation for smaller
+// problems keeps the current memory.
+struct SolverSizes {
+    int eig_n = 0;                 // gram_eigen order above the one-workgroup Jacobi limit
+    int svd_rows = 0, svd_cols = 0;
+    int qr_rows = 0, qr_cols = 0;  // qr_rowmajor
+    int lq_rows = 0, lq_cols = 0;  // lq_rowmajor
+};
+void reserve_solver_workspace(tdvp_ctx ctx, const SolverSizes& s);
 // Row-major complex128 product C [m][n] = A [m][k] B [k][n] (FP64 MFMA).
 void zgemm_rowmajor(tdvp_ctx ctx, const double2* A, const double2* B, double2* C, int m, int k, int n);
 

@@ -263,10 +263,18 @@ struct SegRun {
 
     size_t esz() const { return elem_bytes(sg->edt); }
 
-    // state buffers always belong to the state's own context (lanes come and go)
-    void env_buf(DevMem& b, size_t elems) {
-        if (b.bytes < elems * esz()) b = DevMem(sg->ctx, elems * esz());
+    // State buffers always belong to the state's own context (lanes come and
+    // go) and are grow-only.  The context's allocator is called from the
+    // context's own thread only: before a phase runs on the split lanes every
+    // buffer its ops may write is sized there (presize_split / presize_bond),
+    // so a lane thread that would have to grow one reports an error instead.
+    void need(DevMem& b, size_t bytes) {
+        if (b.bytes >= bytes) return;
+        TDVP_REQUIRE(ctx == sg->ctx, TDVP_E_STATE,
+                     "segment step: a state buffer would grow on a split lane (not sized beforehand)");
+        b = DevMem(sg->ctx, bytes);
     }
+    void env_buf(DevMem& b, size_t elems) { need(b, elems * esz()); }
 
     HeffArgs h1(int j) {
         return HeffArgs{1, sg->chi[j], sg->chi[j + 1], sg->d, W->w[j], W->w[j + 1], sg->beta[j].ptr,
@@ -460,13 +468,37 @@ struct SegRun {
     }
     const double* scal_dev() { return static_cast<const double*>(ctx->workspace("seg_scal", 8)); }
 
-    // Bond j takes dimension chi: reallocate the two site tensors and V_j.
+    // Bond j takes dimension chi: the two site tensors and V_j keep their
+    // buffers when those are large enough (their contents are rewritten by the
+    // caller).
     void set_bond(int j, int chi) {
         if (sg->chi[j + 1] == chi) return;
         sg->chi[j + 1] = chi;
-        sg->Psi[j] = DevMem(sg->ctx, sizeof(double2) * sg->psi_elems(j));
-        sg->Psi[j + 1] = DevMem(sg->ctx, sizeof(double2) * sg->psi_elems(j + 1));
-        sg->Vd[j] = DevMem(sg->ctx, sizeof(double) * chi);
+        need(sg->Psi[j], sizeof(double2) * sg->psi_elems(j));
+        need(sg->Psi[j + 1], sizeof(double2) * sg->psi_elems(j + 1));
+        need(sg->Vd[j], sizeof(double) * chi);
+    }
+
+    // Largest bond a split of pair (j, j+1) can produce.
+    int split_cap(int j) const {
+        int cap = o.chi_max;
+        if (o.static_shapes) cap = std::min(cap, sg->cap[j + 1]);
+        return std::max(1, std::min({cap, sg->chi[j] * sg->d, sg->d * sg->chi[j + 2]}));
+    }
+    // On the calling thread, before a phase runs on the lanes: every state
+    // buffer the op may write, at its largest size.
+    void presize_split(const SOp& op) {
+        const int j = op.j, c = split_cap(j), d = sg->d;
+        need(sg->Psi[j], sizeof(double2) * (size_t)sg->chi[j] * d * c);
+        need(sg->Psi[j + 1], sizeof(double2) * (size_t)c * d * sg->chi[j + 2]);
+        need(sg->Vd[j], sizeof(double) * (size_t)c);
+        if (op.refresh & 1) env_buf(sg->beta[j + 1], (size_t)W->w[j + 1] * c * c);
+        if (op.refresh & 2) env_buf(sg->gamma[j], (size_t)W->w[j + 1] * c * c);
+    }
+    void presize_bond(const SOp& op) {
+        const int j = op.j, c = sg->chi[j + 1];
+        if (op.refresh == 1) env_buf(sg->beta[j + 1], (size_t)W->w[j + 1] * c * c);
+        else env_buf(sg->gamma[j], (size_t)W->w[j + 1] * c * c);
     }
 
     // ---------------------------------------------------------- phases
@@ -668,10 +700,14 @@ struct SegRun {
         if (!sg->ready) TDVP_CHECK_HIP(hipEventCreateWithFlags(&sg->ready, hipEventDisableTiming));
         while ((int)sg->lanes.size() < n) {
             auto L = std::make_unique<SegLane>();
+            // Lane workspaces come from hipMalloc, not from the context's
+            // allocator callback: the lanes are library worker threads, and the
+            // callback (which may re-enter an interpreter) is only called from
+            // the thread that owns the context.
             L->c.device = ctx->device;
-            L->c.alloc_fn = ctx->alloc_fn;
-            L->c.free_fn = ctx->free_fn;
-            L->c.user = ctx->user;
+            L->c.alloc_fn = nullptr;
+            L->c.free_fn = nullptr;
+            L->c.user = nullptr;
             L->c.autotune = ctx->autotune;
             TDVP_CHECK_HIP(hipStreamCreateWithFlags(&L->c.stream, hipStreamNonBlocking));
             TDVP_REQUIRE(rocblas_create_handle(&L->c.blas) == rocblas_status_success, TDVP_E_HIP,
@@ -731,10 +767,20 @@ struct SegRun {
             for (int i = 0; i < n; ++i) split(ph[i].j, theta + off[i], ph[i].refresh);
             return;
         }
+        SolverSizes ss;
         for (const auto& op : ph) {  // operators are cached lazily; build them here, single-threaded
             W->mop(1, op.j, fp64);
             W->mop(3, op.j + 1, fp64);
+            presize_split(op);
+            const int rows = sg->chi[op.j] * sg->d, cols = sg->d * sg->chi[op.j + 2];
+            if (o.svd_mode != 1) ss.eig_n = std::max(ss.eig_n, std::min(rows, cols));
+            if (o.svd_mode != 2) {
+                ss.svd_rows = std::max(ss.svd_rows, rows);
+                ss.svd_cols = std::max(ss.svd_cols, cols);
+            }
         }
+        ensure_lanes(nl);
+        for (int l = 0; l < nl; ++l) reserve_solver_workspace(&sg->lanes[l]->c, ss);
         std::vector<int> order(n);
         for (int i = 0; i < n; ++i) order[i] = i;
         std::sort(order.begin(), order.end(),
@@ -751,11 +797,23 @@ struct SegRun {
             for (const auto& op : ph) bond_step(op.j, op.tau, op.refresh);
             return;
         }
+        SolverSizes ss;
         for (const auto& op : ph) {
             W->mop(0, op.j, fp64);
             W->mop(1, op.j, fp64);
             W->mop(3, op.j + 1, fp64);
+            presize_bond(op);
+            const int rows = sg->chi[op.j] * sg->d, c = sg->chi[op.j + 1], cols = sg->d * sg->chi[op.j + 2];
+            if (op.refresh == 1) {
+                ss.qr_rows = std::max(ss.qr_rows, rows);
+                ss.qr_cols = std::max(ss.qr_cols, c);
+            } else {
+                ss.lq_rows = std::max(ss.lq_rows, c);
+                ss.lq_cols = std::max(ss.lq_cols, cols);
+            }
         }
+        ensure_lanes(nl);
+        for (int l = 0; l < nl; ++l) reserve_solver_workspace(&sg->lanes[l]->c, ss);
         std::vector<int> order(n);
         for (int i = 0; i < n; ++i) order[i] = i;
         std::sort(order.begin(), order.end(), [&](int a, int b) { return sg->chi[ph[a].j + 1] > sg->chi[ph[b].j + 1]; });

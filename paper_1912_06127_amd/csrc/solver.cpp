@@ -179,3 +179,80 @@ GramResult gram_eigen(tdvp_ctx ctx, const double2* M, int rows, int cols, bool l
 }
 
 }  // namespace tdvp
+
+namespace tdvp {
+
+namespace {
+
+// Device bytes rocSOLVER asks for when `call` runs in size-query mode (no
+// computation, only the workspace request is recorded on the handle).
+template <class F>
+size_t query_size(rocblas_handle h, F call) {
+    size_t sz = 0;
+    check_rs(rocblas_start_device_memory_size_query(h), "rocblas_start_device_memory_size_query");
+    const rocblas_status st = call();
+    check_rs(rocblas_stop_device_memory_size_query(h, &sz), "rocblas_stop_device_memory_size_query");
+    if (st != rocblas_status_success && st != rocblas_status_size_increased && st != rocblas_status_size_unchanged)
+        check_rs(st, "device memory size query");
+    return sz;
+}
+
+}  // namespace
+
+void reserve_solver_workspace(tdvp_ctx ctx, const SolverSizes& s) {
+    rocblas_handle h = ctx->blas;
+    size_t need = 0;
+    auto ws = [&](const char* name, size_t bytes) { return ctx->workspace(name, std::max<size_t>(bytes, 16)); };
+    // the query runs on the same (real, correctly sized) buffers the calls use
+    if (s.eig_n > kJacobiMaxOrder) {
+        const int n = s.eig_n;
+        auto* G = static_cast<double2*>(ws("gram_G", sizeof(double2) * (size_t)n * n));
+        auto* ev = static_cast<double*>(ws("gram_ev", sizeof(double) * (size_t)n));
+        auto* E = static_cast<double*>(ws("gram_E", sizeof(double) * (size_t)n));
+        auto* info = static_cast<int*>(ws("gram_info", sizeof(int)));
+        ws("gram_vecs", sizeof(double2) * (size_t)n * n);
+        need = std::max(need, query_size(h, [&] {
+            return rocsolver_zheevd(h, rocblas_evect_original, rocblas_fill_upper, n, rz(G), n, ev, E, info);
+        }));
+    }
+    if (s.svd_rows > 0 && s.svd_cols > 0) {
+        const int rows = s.svd_rows, cols = s.svd_cols, k = std::min(rows, cols);
+        auto* work = static_cast<double2*>(ws("svd_work", sizeof(double2) * (size_t)rows * cols));
+        auto* U = static_cast<double2*>(ws("svd_U", sizeof(double2) * (size_t)cols * k));
+        auto* V = static_cast<double2*>(ws("svd_V", sizeof(double2) * (size_t)k * rows));
+        auto* S = static_cast<double*>(ws("svd_S", sizeof(double) * (size_t)k));
+        ws("svd_E", sizeof(double) * (size_t)std::max(k, 1));
+        auto* info = static_cast<int*>(ws("svd_info", sizeof(int)));
+        auto* resid = static_cast<double*>(ws("svd_resid", sizeof(double)));
+        auto* sweeps = static_cast<int*>(ws("svd_sweeps", sizeof(int)));
+        need = std::max(need, query_size(h, [&] {
+            return rocsolver_zgesvdj(h, rocblas_svect_singular, rocblas_svect_singular, cols, rows, rz(work), cols,
+                                     0.0, resid, 100, sweeps, S, rz(U), cols, rz(V), k, info);
+        }));
+    }
+    auto qr_like = [&](int rows, int cols, bool lq) {
+        if (rows <= 0 || cols <= 0) return;
+        const int k = std::min(rows, cols);
+        auto* work = static_cast<double2*>(ws("qr_work", sizeof(double2) * (size_t)rows * cols));
+        auto* tau = static_cast<double2*>(ws("qr_tau", sizeof(double2) * (size_t)k));
+        if (!lq) {
+            need = std::max(need, query_size(h, [&] { return rocsolver_zgelqf(h, cols, rows, rz(work), cols, rz(tau)); }));
+            need = std::max(need, query_size(h, [&] { return rocsolver_zunglq(h, k, rows, k, rz(work), cols, rz(tau)); }));
+        } else {
+            need = std::max(need, query_size(h, [&] { return rocsolver_zgeqrf(h, cols, rows, rz(work), cols, rz(tau)); }));
+            need = std::max(need, query_size(h, [&] { return rocsolver_zungqr(h, cols, k, k, rz(work), cols, rz(tau)); }));
+        }
+    };
+    qr_like(s.qr_rows, s.qr_cols, false);
+    qr_like(s.lq_rows, s.lq_cols, true);
+    if (need == 0) return;
+    tdvp::Buffer& cur = ctx->work["rocblas_ws"];
+    if (cur.bytes >= need) return;
+    // the handle must let go of the old block before the workspace map frees it
+    TDVP_CHECK_HIP(hipStreamSynchronize(ctx->stream));
+    check_rs(rocblas_set_workspace(h, nullptr, 0), "rocblas_set_workspace");
+    void* p = ctx->workspace("rocblas_ws", need);
+    check_rs(rocblas_set_workspace(h, p, ctx->work["rocblas_ws"].bytes), "rocblas_set_workspace");
+}
+
+}  // namespace tdvp
