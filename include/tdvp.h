@@ -426,6 +426,24 @@ typedef struct {
 } tdvp_heff_desc;
 int apply_heff_batched(tdvp_ctx ctx, tdvp_dtype dtype, int n, const tdvp_heff_desc* descs);
 
+/* apply_heff without any device allocation, for callers that cannot allocate:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, layouts, ownership and result as apply_heff
+ * (the caller still passes every input and the output); the MPO-stage
+ * operator and the two intermediate stages live in one fixed scratch array of
+ * apply_heff_noalloc_max_bytes() bytes (64 MiB) that the library holds on each
+ * device it runs on until the process ends.  Problems needing more scratch
+ * return TDVP_E_NOMEM before any work is queued (two-site, w = 10, d = 2:
+ * chi_l * chi_r up to about 1e5 in complex64, 5e4 in complex128).  No GEMM
+ * tile timing and no split-K.  Every call on one device shares that device's
+ * array: calls that overlap in time on one device (from any context, stream
+ * or thread) race and give wrong results; calls queued on one stream are
+ * ordered and safe.  Nothing in the array needs to start at zero. */
+int apply_heff_noalloc(tdvp_ctx ctx, int nsite, tdvp_dtype dtype, int chil, int chir, int d, int wl,
+                       int wm, int wr, const void* L, const void* W1, const void* W2, const void* R,
+                       const void* theta, void* out);
+size_t apply_heff_noalloc_max_bytes(void);
+
 /* Environment update (Sec. III A, left-environment figure):
  *   dir = +1: out[l][b'][b] = sum conj(A[a'][s'][b']) env[k][a'][a] W[k][l][s'][s] A[a][s][b]
  *             (env = L_j [wl][chil][chil], out = L_{j+1} [wr][chir][chir])

@@ -93,6 +93,8 @@ SIGNATURES = {
     "dmrg2_sweep": (_I, [_P, _P, _P, C.POINTER(Opts), C.POINTER(Stats), C.POINTER(_D)]),
     "apply_heff": (_I, [_P, _I, _I, _I, _I, _I, _I, _I, _I, _P, _P, _P, _P, _P, _P]),
     "apply_heff_batched": (_I, [_P, _I, _I, C.POINTER(HeffDesc)]),
+    "apply_heff_noalloc": (_I, [_P, _I, _I, _I, _I, _I, _I, _I, _I, _P, _P, _P, _P, _P, _P]),
+    "apply_heff_noalloc_max_bytes": (C.c_size_t, []),
     "env_update": (_I, [_P, _I, _I, _I, _I, _I, _I, _I, _P, _P, _P, _P]),
     "apply_heff_adjoint": (_I, [_P, _I, _I, _I, _I, _I, _I, _I, _I] + [_P] * 11),
     "expect": (_I, [_P, _P, _I, _PI, _PD, _PD]),

@@ -162,12 +162,15 @@ def _dev(t: torch.Tensor, dtype) -> C.c_void_p:
     return C.c_void_p(t.data_ptr())
 
 
-def apply_heff(ctx: Context, L, R, theta, W1=None, W2=None, out=None) -> torch.Tensor:
+def apply_heff(ctx: Context, L, R, theta, W1=None, W2=None, out=None, noalloc: bool = False) -> torch.Tensor:
     """H_eff theta for a zero-, one- or two-site local state.
 
     L [wl][chil][chil], R [wr][chir][chir]; theta [chil][chir] (zero-site),
     [chil][d][chir] (one-site, W1 [wl][wr][d][d]) or [chil][d][d][chir]
-    (two-site, W1 [wl][wm][d][d], W2 [wm][wr][d][d]).
+    (two-site, W1 [wl][wm][d][d], W2 [wm][wr][d][d]).  ``noalloc`` calls the
+    library's allocation-free entry point (intermediates in its fixed
+    per-device scratch array; pass ``out`` to keep the call itself free of
+    allocations).
     """
     nsite = theta.dim() - 2
     dt = theta.dtype
@@ -178,10 +181,17 @@ def apply_heff(ctx: Context, L, R, theta, W1=None, W2=None, out=None) -> torch.T
     if out is None:
         out = torch.empty_like(theta)
     ptr = lambda t: _dev(t, dt) if t is not None else C.c_void_p()
-    rc = _lib.load().apply_heff(ctx.handle, nsite, _dtype_code(theta), chil, chir, d, wl, wm, wr,
-                                ptr(L), ptr(W1), ptr(W2), ptr(R), ptr(theta), ptr(out))
+    lib = _lib.load()
+    fn = lib.apply_heff_noalloc if noalloc else lib.apply_heff
+    rc = fn(ctx.handle, nsite, _dtype_code(theta), chil, chir, d, wl, wm, wr,
+            ptr(L), ptr(W1), ptr(W2), ptr(R), ptr(theta), ptr(out))
     _check(ctx.handle, rc)
     return out
+
+
+def apply_heff_noalloc_max_bytes() -> int:
+    """Size of the fixed per-device scratch array of the allocation-free H_eff call."""
+    return int(_lib.load().apply_heff_noalloc_max_bytes())
 
 
 def apply_heff_batched(ctx: Context, problems):

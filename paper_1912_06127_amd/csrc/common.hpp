@@ -69,8 +69,21 @@ struct tdvp_prof_total {
     long count = 0;
 };
 
+namespace tdvp {
+// Fixed device region handed out by workspace() while a call runs without
+// allocating (apply_heff_noalloc): requests are carved from it in order, a
+// name asked for twice gets the same block, and a request that does not fit
+// is an error instead of an allocation.
+struct Arena {
+    char* base = nullptr;
+    size_t cap = 0, used = 0;
+    std::map<std::string, std::pair<size_t, size_t>> named;  // name -> (offset, bytes)
+};
+}  // namespace tdvp
+
 struct tdvp_ctx_s {
     int device = 0;
+    tdvp::Arena* arena = nullptr;               // set only inside an allocation-free call
     hipStream_t stream = nullptr;
     tdvp_alloc_fn alloc_fn = nullptr;
     tdvp_free_fn free_fn = nullptr;

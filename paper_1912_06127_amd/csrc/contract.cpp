@@ -288,31 +288,40 @@ void env_right(tdvp_ctx ctx, const EnvArgs& a, const void* R, Dt r_dt, void* out
 
 using namespace tdvp;
 
+namespace tdvp {
+
+// Argument checks, MPO-stage operator and pipeline of the raw-pointer
+// H_eff call (shared by apply_heff and apply_heff_noalloc).
+void heff_raw_call(tdvp_ctx ctx, int nsite, tdvp_dtype dtype, int chil, int chir, int d, int wl, int wm, int wr,
+                   const void* L, const void* W1, const void* W2, const void* R, const void* theta, void* out) {
+    const Dt dt = to_dt(dtype);
+    TDVP_REQUIRE(nsite >= 0 && nsite <= 2, TDVP_E_ARG, "apply_heff: nsite must be 0, 1 or 2");
+    TDVP_REQUIRE(chil >= 1 && chir >= 1 && wl >= 1 && wr >= 1, TDVP_E_SHAPE,
+                 "apply_heff: dimensions must be positive");
+    TDVP_REQUIRE(nsite == 0 || d >= 1, TDVP_E_SHAPE, "apply_heff: d must be positive");
+    TDVP_REQUIRE(nsite != 2 || wm >= 1, TDVP_E_SHAPE, "apply_heff: wm must be positive");
+    TDVP_REQUIRE(nsite != 0 || wl == wr, TDVP_E_SHAPE, "apply_heff: zero-site needs wl == wr");
+    TDVP_REQUIRE(L && R && theta && out, TDVP_E_ARG, "apply_heff: null pointer");
+    TDVP_REQUIRE(nsite < 1 || W1, TDVP_E_ARG, "apply_heff: W1 is null");
+    TDVP_REQUIRE(nsite < 2 || W2, TDVP_E_ARG, "apply_heff: W2 is null");
+    TDVP_REQUIRE(out != theta && out != L && out != R, TDVP_E_ARG, "apply_heff: out aliases an input");
+    const bool fp64 = dt == Dt::C128;
+    Mop m;
+    const int kind = nsite == 0 ? 0 : (nsite == 1 ? 1 : 2);
+    mop_make(ctx, m, kind, W1, W2, dt, wl, nsite == 2 ? wm : wl, wr, d, fp64, false);
+    HeffArgs a{nsite, chil, chir, d, wl, wr, L, R, dt, &m, fp64, raw_gemm_form(ctx, fp64)};
+    heff_apply(ctx, a, theta, dt, out, dt);
+}
+
+}  // namespace tdvp
+
 extern "C" {
 
 int apply_heff(tdvp_ctx ctx, int nsite, tdvp_dtype dtype, int chil, int chir, int d, int wl, int wm,
                int wr, const void* L, const void* W1, const void* W2, const void* R,
                const void* theta, void* out) {
     if (!ctx) return TDVP_E_ARG;
-    return guarded(ctx, [&] {
-        const Dt dt = to_dt(dtype);
-        TDVP_REQUIRE(nsite >= 0 && nsite <= 2, TDVP_E_ARG, "apply_heff: nsite must be 0, 1 or 2");
-        TDVP_REQUIRE(chil >= 1 && chir >= 1 && wl >= 1 && wr >= 1, TDVP_E_SHAPE,
-                     "apply_heff: dimensions must be positive");
-        TDVP_REQUIRE(nsite == 0 || d >= 1, TDVP_E_SHAPE, "apply_heff: d must be positive");
-        TDVP_REQUIRE(nsite != 2 || wm >= 1, TDVP_E_SHAPE, "apply_heff: wm must be positive");
-        TDVP_REQUIRE(nsite != 0 || wl == wr, TDVP_E_SHAPE, "apply_heff: zero-site needs wl == wr");
-        TDVP_REQUIRE(L && R && theta && out, TDVP_E_ARG, "apply_heff: null pointer");
-        TDVP_REQUIRE(nsite < 1 || W1, TDVP_E_ARG, "apply_heff: W1 is null");
-        TDVP_REQUIRE(nsite < 2 || W2, TDVP_E_ARG, "apply_heff: W2 is null");
-        TDVP_REQUIRE(out != theta && out != L && out != R, TDVP_E_ARG, "apply_heff: out aliases an input");
-        const bool fp64 = dt == Dt::C128;
-        Mop m;
-        const int kind = nsite == 0 ? 0 : (nsite == 1 ? 1 : 2);
-        mop_make(ctx, m, kind, W1, W2, dt, wl, nsite == 2 ? wm : wl, wr, d, fp64, false);
-        HeffArgs a{nsite, chil, chir, d, wl, wr, L, R, dt, &m, fp64, raw_gemm_form(ctx, fp64)};
-        heff_apply(ctx, a, theta, dt, out, dt);
-    });
+    return guarded(ctx, [&] { heff_raw_call(ctx, nsite, dtype, chil, chir, d, wl, wm, wr, L, W1, W2, R, theta, out); });
 }
 
 int apply_heff_batched(tdvp_ctx ctx, tdvp_dtype dtype, int n, const tdvp_heff_desc* descs) {

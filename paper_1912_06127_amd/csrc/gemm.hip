@@ -751,6 +751,10 @@ void cgemm(tdvp_ctx ctx, const GemmDesc& g, bool fp64, int form) {
     kp.ldc = g.ldc;
     kp.strideC = g.strideC;
     const bool m3 = fp64 ? false : form == 3;
+    if (ctx->arena) {  // allocation-free call: no tile timing, no split-K partials
+        launch_cfg(ctx, kp, g.batch, fp64, m3, heuristic_cfg(g, fp64).cfg, 1);
+        return;
+    }
     const Choice ch = choose_cfg(ctx, g, kp, fp64, m3);
     if (!launch_cfg(ctx, kp, g.batch, fp64, m3, ch.cfg, ch.ks)) {
         const Choice h = heuristic_cfg(g, fp64);

@@ -147,6 +147,13 @@ struct SolverSizes {
     int lq_rows = 0, lq_cols = 0;  // lq_rowmajor
 };
 void reserve_solver_workspace(tdvp_ctx ctx, const SolverSizes& s);
+// Resolves (once per device, with that device current) the device address of
+// the fixed scratch array used by apply_heff_noalloc; failures are recorded
+// and reported by that call.
+void scratch_setup(int device);
+// apply_heff body: checks, MPO-stage operator, pipeline (workspaces by name).
+void heff_raw_call(tdvp_ctx ctx, int nsite, tdvp_dtype dtype, int chil, int chir, int d, int wl, int wm, int wr,
+                   const void* L, const void* W1, const void* W2, const void* R, const void* theta, void* out);
 // Row-major complex128 product C [m][n] = A [m][k] B [k][n] (FP64 MFMA).
 void zgemm_rowmajor(tdvp_ctx ctx, const double2* A, const double2* B, double2* C, int m, int k, int n);
 

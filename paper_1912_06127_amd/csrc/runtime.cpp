@@ -26,6 +26,21 @@ void tdvp_ctx_s::dev_free(void* p, size_t bytes) {
 }
 
 void* tdvp_ctx_s::workspace(const std::string& name, size_t bytes) {
+    if (arena) {
+        auto it = arena->named.find(name);
+        if (it != arena->named.end()) {
+            TDVP_REQUIRE(it->second.second >= bytes, TDVP_E_NOMEM,
+                         "allocation-free call: scratch block '" + name + "' asked for twice with a larger size");
+            return arena->base + it->second.first;
+        }
+        const size_t off = (arena->used + 255) / 256 * 256;
+        TDVP_REQUIRE(off + bytes <= arena->cap, TDVP_E_NOMEM,
+                     "allocation-free call: scratch exhausted (" + std::to_string(off + bytes) + " of " +
+                         std::to_string(arena->cap) + " bytes)");
+        arena->named[name] = {off, bytes};
+        arena->used = off + bytes;
+        return arena->base + off;
+    }
     tdvp::Buffer& b = work[name];
     if (b.bytes < bytes) {
         if (b.ptr) {
@@ -118,6 +133,7 @@ int tdvp_ctx_create(int device, void* hip_stream, tdvp_alloc_fn alloc_fn, tdvp_f
         return TDVP_E_HIP;
     }
     rocblas_set_stream(c->blas, c->stream);
+    tdvp::scratch_setup(device);  // this device's scratch address for apply_heff_noalloc
     *out = c;
     return TDVP_OK;
 }
