@@ -102,7 +102,11 @@ int tdvp_profile_read(tdvp_ctx ctx, int max_entries, char* names, double* ms, do
 /* Long-range spin-chain Hamiltonian (Sec. II C, Sec. IV):
  *   H = sum_{i<j} f(j-i) sum_a g_a A_a(i) B_a(j) + h sum_i X(i).
  * With K > 0, f(r) = Re sum_k c_k lambda_k^r (sum of exponentials,
- * Sec. II C): bond dimension m = n_terms K + 2.  With K = 0 every distance
+ * Sec. II C): bond dimension m = n_terms K + 2.  The weights and decay
+ * factors are either given (c and lambda) or, with c = lambda = NULL,
+ * fitted by the library to the power law f(r) = r^-alpha on
+ * r = 1..fit_rmax (fit_rmax <= 0: N-1) with tdvp_fit_exponentials (the
+ * couplings' strength goes into g).  With K = 0 every distance
  * r = 1..N-1 has its own chain of bond states and coupling[r-1] = f(r)
  * (exact MPO, bond dimension n_terms (N-1) + 2).
  * Operators are d x d complex128 matrices, host memory, [s'][s]. */
@@ -114,14 +118,41 @@ typedef struct {
     const double* A_ops;    /* [n_terms][d][d] complex128 */
     const double* B_ops;    /* [n_terms][d][d] complex128 */
     int K;                  /* exponentials per term; 0 = exact MPO */
-    const double* c;        /* [K] complex128 weights c_k (K > 0) */
-    const double* lambda;   /* [K] complex128 decay factors lambda_k (K > 0) */
+    const double* c;        /* [K] complex128 weights c_k, or NULL (fit) */
+    const double* lambda;   /* [K] complex128 decay factors lambda_k, or NULL (fit) */
     const double* coupling; /* [N-1] real f(1..N-1) (K = 0) */
     const double* onsite;   /* [d][d] complex128 X, or NULL */
     double h;               /* field strength multiplying X */
+    double alpha;           /* fitted power r^-alpha (K > 0, c = lambda = NULL) */
+    int fit_rmax;           /* fit range r = 1..fit_rmax; <= 0: N-1 */
+    int fit_refine;         /* 1: Levenberg-Marquardt refinement of the fit */
 } tdvp_mpo_spec;
 
-int mpo_longrange(tdvp_ctx ctx, const tdvp_mpo_spec* spec, tdvp_mpo* out);
+/* Build the MPO on the device.  fit_max_abs_err (nullable) receives the
+ * maximum of |f(r) - r^-alpha| over the fit range when the library fitted
+ * the exponentials, else 0.  Errors: TDVP_E_SHAPE for bad sizes,
+ * TDVP_E_ARG for missing operators or only one of c / lambda, the fit's
+ * errors as for tdvp_fit_exponentials. */
+int mpo_longrange(tdvp_ctx ctx, const tdvp_mpo_spec* spec, tdvp_mpo* out, double* fit_max_abs_err);
+
+/* Sum-of-exponentials fit (Sec. II C; the method of Pirvu et al. that the
+ * paper cites, read as a matrix pencil): f(r) ~ Re sum_k c_k lambda_k^r for
+ * the samples f[0..R-1] = f(1..R).  The Hankel matrix of the samples is cut
+ * to its K dominant right singular vectors (one-sided Jacobi SVD), the
+ * lambda_k are the eigenvalues of the shift operator on them and the c_k
+ * follow by least squares on all samples.  refine = 1 adds
+ * Levenberg-Marquardt iterations with Lawson reweighting towards the
+ * minimax fit (kept only when the maximum error drops).  Host only (no
+ * context, no device work).  c_out, lam_out: [K] complex128 (interleaved);
+ * max_abs_err (nullable): max_r |Re sum - f(r)|.  Errors: TDVP_E_ARG for
+ * K < 1, R < 2K or null pointers, TDVP_E_NUMERIC for non-finite samples or
+ * a rank-deficient problem, TDVP_E_NOCONV if the eigenvalue iteration
+ * fails. */
+int tdvp_fit_exponentials(const double* f, int R, int K, int refine, double* c_out, double* lam_out,
+                          double* max_abs_err);
+/* tdvp_fit_exponentials of f(r) = r^-alpha on r = 1..rmax. */
+int tdvp_fit_power_law(double alpha, int K, int rmax, int refine, double* c_out, double* lam_out,
+                       double* max_abs_err);
 /* MPO from explicit tensors: w[0..N] bond dimensions (w[0] = w[N] = 1),
  * W_host the concatenation of the N site tensors [w_j][w_{j+1}][d][d]
  * complex128 (host). */

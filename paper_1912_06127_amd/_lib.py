@@ -25,6 +25,7 @@ class MpoSpec(C.Structure):
         ("g", C.POINTER(C.c_double)), ("A_ops", C.POINTER(C.c_double)), ("B_ops", C.POINTER(C.c_double)),
         ("K", C.c_int), ("c", C.POINTER(C.c_double)), ("lam", C.POINTER(C.c_double)),
         ("coupling", C.POINTER(C.c_double)), ("onsite", C.POINTER(C.c_double)), ("h", C.c_double),
+        ("alpha", C.c_double), ("fit_rmax", C.c_int), ("fit_refine", C.c_int),
     ]
 
 
@@ -75,7 +76,9 @@ SIGNATURES = {
     "tdvp_ctx_destroy": (_I, [_P]),
     "tdvp_last_error": (C.c_char_p, [_P]),
     "tdvp_ctx_sync": (_I, [_P]),
-    "mpo_longrange": (_I, [_P, C.POINTER(MpoSpec), C.POINTER(_P)]),
+    "mpo_longrange": (_I, [_P, C.POINTER(MpoSpec), C.POINTER(_P), _PD]),
+    "tdvp_fit_exponentials": (_I, [_PD, _I, _I, _I, _PD, _PD, _PD]),
+    "tdvp_fit_power_law": (_I, [_D, _I, _I, _I, _PD, _PD, _PD]),
     "mpo_from_tensors": (_I, [_P, _I, _I, _PI, _PD, C.POINTER(_P)]),
     "mpo_get_info": (_I, [_P, _PI, _PI, _PI]),
     "mpo_get_tensor": (_I, [_P, _I, _PD]),

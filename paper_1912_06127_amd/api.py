@@ -284,11 +284,15 @@ class MPO:
 
     @classmethod
     def longrange(cls, ctx: Context, N: int, pairs, *, c=None, lam=None, coupling=None,
-                  onsite=None, h: float = 0.0):
+                  onsite=None, h: float = 0.0, alpha=None, K: int = 0, fit_rmax: int = 0,
+                  fit_refine: bool = False):
         """sum_{i<j} f(j-i) sum_a g_a A_a(i) B_a(j) + h sum X(i).
 
         pairs: list of (g_a, A_a, B_a).  Either (c, lam) for f(r) = Re sum
-        c_k lam_k^r, or coupling = [f(1), ..., f(N-1)] for the exact MPO.
+        c_k lam_k^r, or (alpha, K) for f(r) = r^-alpha fitted by the library
+        with K exponentials on r = 1..fit_rmax (0: N-1; the maximum fit error
+        is kept as ``fit_max_abs_err``), or coupling = [f(1), ..., f(N-1)] for
+        the exact MPO.
         """
         d = np.asarray(pairs[0][1]).shape[0] if pairs else np.asarray(onsite).shape[0]
         g = np.array([p[0] for p in pairs], dtype=np.float64)
@@ -302,6 +306,8 @@ class MPO:
             cc, ll = _c128(c), _c128(lam)
             keep += [cc, ll]
             spec.K, spec.c, spec.lam = len(np.atleast_1d(c)), _dptr(cc), _dptr(ll)
+        elif alpha is not None:
+            spec.K, spec.alpha, spec.fit_rmax, spec.fit_refine = int(K), float(alpha), int(fit_rmax), int(fit_refine)
         else:
             cp = np.ascontiguousarray(coupling, dtype=np.float64)
             keep.append(cp)
@@ -311,8 +317,11 @@ class MPO:
             keep.append(on)
             spec.onsite, spec.h = _dptr(on), float(h)
         h_ = C.c_void_p()
-        _check(ctx.handle, _lib.load().mpo_longrange(ctx.handle, C.byref(spec), C.byref(h_)))
-        return cls(ctx, h_)
+        err = C.c_double(0.0)
+        _check(ctx.handle, _lib.load().mpo_longrange(ctx.handle, C.byref(spec), C.byref(h_), C.byref(err)))
+        mpo = cls(ctx, h_)
+        mpo.fit_max_abs_err = err.value
+        return mpo
 
     @classmethod
     def from_tensors(cls, ctx: Context, Ws):

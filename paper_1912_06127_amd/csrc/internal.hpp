@@ -3,6 +3,8 @@
 
 #include "common.hpp"
 
+#include <complex>
+
 #include <functional>
 
 namespace tdvp {
@@ -154,6 +156,10 @@ void scratch_setup(int device);
 // apply_heff body: checks, MPO-stage operator, pipeline (workspaces by name).
 void heff_raw_call(tdvp_ctx ctx, int nsite, tdvp_dtype dtype, int chil, int chir, int d, int wl, int wm, int wr,
                    const void* L, const void* W1, const void* W2, const void* R, const void* theta, void* out);
+// Matrix-pencil fit f(r) ~ Re sum_k c_k lambda_k^r of samples f(1..R)
+// (optionally refined); returns the maximum absolute error on r = 1..R.
+double fit_exponentials(const std::vector<double>& f, int K, bool refine, std::vector<std::complex<double>>& c,
+                        std::vector<std::complex<double>>& lam);
 // Row-major complex128 product C [m][n] = A [m][k] B [k][n] (FP64 MFMA).
 void zgemm_rowmajor(tdvp_ctx ctx, const double2* A, const double2* B, double2* C, int m, int k, int n);
 

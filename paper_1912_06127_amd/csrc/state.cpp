@@ -135,16 +135,39 @@ void right_canonicalize(tdvp_ctx ctx, tdvp_mps m) {
 
 extern "C" {
 
-int mpo_longrange(tdvp_ctx ctx, const tdvp_mpo_spec* sp, tdvp_mpo* out) {
+int mpo_longrange(tdvp_ctx ctx, const tdvp_mpo_spec* sp, tdvp_mpo* out, double* fit_max_abs_err) {
     if (!ctx) return TDVP_E_ARG;
     return guarded(ctx, [&] {
         TDVP_REQUIRE(sp && out, TDVP_E_ARG, "mpo_longrange: null argument");
         *out = nullptr;
+        if (fit_max_abs_err) *fit_max_abs_err = 0.0;
         const int N = sp->N, d = sp->d, nH = sp->n_terms, K = sp->K;
         TDVP_REQUIRE(N >= 2 && d >= 1 && nH >= 0 && K >= 0, TDVP_E_SHAPE, "mpo_longrange: bad sizes");
         TDVP_REQUIRE(nH == 0 || (sp->g && sp->A_ops && sp->B_ops), TDVP_E_ARG, "mpo_longrange: null operators");
-        TDVP_REQUIRE(K == 0 || (sp->c && sp->lambda), TDVP_E_ARG, "mpo_longrange: null exponentials");
+        TDVP_REQUIRE(!sp->c == !sp->lambda, TDVP_E_ARG, "mpo_longrange: give both c and lambda, or neither");
         TDVP_REQUIRE(K > 0 || nH == 0 || sp->coupling, TDVP_E_ARG, "mpo_longrange: null couplings");
+        // K > 0 without c, lambda: fit f(r) = r^-alpha on r = 1..fit_rmax (Sec. II C)
+        std::vector<double> fitted;
+        const double* cw = sp->c;
+        const double* lw = sp->lambda;
+        if (K > 0 && !cw) {
+            TDVP_REQUIRE(std::isfinite(sp->alpha), TDVP_E_ARG, "mpo_longrange: alpha is not finite");
+            const int rmax = sp->fit_rmax > 0 ? sp->fit_rmax : N - 1;
+            std::vector<double> f(rmax);
+            for (int r = 1; r <= rmax; ++r) f[r - 1] = std::pow((double)r, -sp->alpha);
+            std::vector<std::complex<double>> c, lam;
+            const double err = fit_exponentials(f, K, sp->fit_refine != 0, c, lam);
+            if (fit_max_abs_err) *fit_max_abs_err = err;
+            fitted.resize(4 * K);
+            for (int k = 0; k < K; ++k) {
+                fitted[2 * k] = c[k].real();
+                fitted[2 * k + 1] = c[k].imag();
+                fitted[2 * K + 2 * k] = lam[k].real();
+                fitted[2 * K + 2 * k + 1] = lam[k].imag();
+            }
+            cw = fitted.data();
+            lw = fitted.data() + 2 * K;
+        }
         const int R = N - 1;
         const int chans = K > 0 ? K : R;  // bond states per term
         const int m = nH * chans + 2;
@@ -172,8 +195,8 @@ int mpo_longrange(tdvp_ctx ctx, const tdvp_mpo_spec* sp, tdvp_mpo* out) {
                 // channel (a, k): A opens, lambda_k per site, g c_k lambda_k B closes
                 for (int k = 0; k < K; ++k) {
                     const int st = 1 + a * K + k;
-                    const double lr = sp->lambda[2 * k], li = sp->lambda[2 * k + 1];
-                    const double cr = sp->c[2 * k], ci = sp->c[2 * k + 1];
+                    const double lr = lw[2 * k], li = lw[2 * k + 1];
+                    const double cr = cw[2 * k], ci = cw[2 * k + 1];
                     put(0, st, A, 1.0, 0.0);
                     put(st, st, id.data(), lr, li);
                     put(st, m - 1, B, g * (cr * lr - ci * li), g * (cr * li + ci * lr));

@@ -99,6 +99,29 @@ def test_mpo_longrange_matches_oracle_builders(ctx):
         assert np.max(np.abs(W2.tensor(j) - Ws[j])) < 1e-15
 
 
+def test_mpo_longrange_fits_the_power_law_itself(ctx):
+    """mpo_longrange with alpha and K (no c, lambda): the library fits r^-alpha
+    (Sec. II C) and builds the MPO; its dense operator equals the oracle's MPO
+    from the oracle's independent fit, and the reported fit error matches."""
+    import paper_1912_06127_amd as pkg
+    for N, alpha, K, pairs in ((8, 2.0, 3, spin.xxx_pairs()), (7, 1.5, 2, spin.xy_pairs())):
+        W = pkg.MPO.longrange(ctx, N, pairs, alpha=alpha, K=K, onsite=spin.SX, h=0.3)
+        c, lam, err = ompo.fit_exponentials(1.0 / np.arange(1, N) ** alpha, K)
+        ref = ompo.mpo_exponentials(N, c, lam, pairs, spin.SX, 0.3)
+        assert W.w == [1] + [len(pairs) * K + 2] * (N - 1) + [1]
+        dense = ompo.mpo_to_dense([W.tensor(j) for j in range(N)])
+        assert np.max(np.abs(dense - ompo.mpo_to_dense(ref))) < 1e-9
+        assert np.max(np.abs(dense - dense.conj().T)) < 1e-12
+        assert abs(W.fit_max_abs_err - err) < 1e-10
+    # the N = 201 XY workload's fit (alpha = 1.5, K = 6 on r <= 200) and the refined variant
+    p = wl.XY_N201
+    W = pkg.MPO.longrange(ctx, 201, spin.xy_pairs(), alpha=p["alpha"], K=p["K"])
+    _, _, err = ompo.fit_exponentials(1.0 / np.arange(1, 201) ** p["alpha"], p["K"])
+    assert abs(W.fit_max_abs_err - err) < 1e-3 * err
+    Wr = pkg.MPO.longrange(ctx, 201, spin.xy_pairs(), alpha=p["alpha"], K=p["K"], fit_refine=True)
+    assert Wr.fit_max_abs_err < W.fit_max_abs_err
+
+
 @pytest.mark.parametrize("dt_", ["c128", "c64"])
 def test_tdvp1_ising_n10_matches_exact_evolution(ctx, dt_):
     """Long-range Ising quench, N = 10, exact MPO, 1TDVP at D <= 32 vs ED (2^10 states)."""
