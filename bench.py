@@ -120,8 +120,102 @@ def cpu_baseline(wl, W, D=1024, budget_s=15.0, max_reps=10):
         "cores": int(threads),
         "kind": "oracle",
         "sample": f"{reps} two-site H_eff applications at D={D}, w=10 (numpy einsum, complex128), "
-                  f"{dt:.2f} s each; host has {os.cpu_count()} logical CPUs",
+                  f"{dt:.2f} s each; host {cpu_model()}, {os.cpu_count()} logical CPUs",
     }
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_timings(wl, W, budget_s=20.0):
+    """The FP64 oracle (numpy/scipy, complex128) timed on the host cores beside
+    each GPU workload, on bounded samples of the same inputs.  Test
+    infrastructure: only this leg of the benchmark calls the oracle."""
+    import numpy as np
+    from threadpoolctl import threadpool_info, threadpool_limits
+    from oracle import env as oenv
+    from oracle import heff as oheff
+    from oracle import mpo as ompo
+    from oracle import mps as omps
+    from oracle import segments as oseg
+    from oracle import spin
+    from oracle import tdvp as otdvp
+    out = {"cpu_model": cpu_model(), "logical_cpus": os.cpu_count(),
+           "blas_threads": int(max([q.get("num_threads", 1) for q in threadpool_info()] or [1]))}
+    # two-site H_eff at D = 1024, one BLAS thread
+    Lk, Rk, theta = wl.heff_micro_inputs(1024, 10)
+    beta, gamma = np.transpose(Lk, (1, 0, 2)), np.transpose(Rk, (2, 0, 1))
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        oheff.apply_heff2(beta, W, W, gamma, theta)
+        t1 = time.perf_counter() - t0
+    out["heff_D1024_1thread"] = {"s": round(t1, 2), "gflops": round(heff2_flops(1024, 10) / t1 * 1e-9, 2)}
+    del Lk, Rk, theta, beta, gamma
+    # N = 10 Ising quench, one-site TDVP (exact MPO), 10 steps
+    p = wl.ISING_N10
+    N = p["N"]
+    Ws = ompo.mpo_exact(N, lambda r: p["J"] / r ** p["alpha"], spin.ising_pairs(), spin.SX, p["h"])
+    st = otdvp.MPSState(omps.padded_product_state([0] * N, wl.full_rank_bonds(N, 2, p["chi_cap"])), Ws)
+    t0 = time.perf_counter()
+    for _ in range(10):
+        otdvp.tdvp1_step(st, p["dt"])
+    out["ising_n10_1tdvp"] = {"s_per_step": round((time.perf_counter() - t0) / 10, 4), "steps_timed": 10}
+    # N = 64 XXX quench, two-site TDVP: the first steps within the budget
+    N = 64
+    c, lam, _ = ompo.fit_exponentials(np.arange(1, N, dtype=float) ** -2.0, 6)
+    Ws = ompo.mpo_exponentials(N, c, lam, spin.xxx_pairs())
+    bits = [j % 2 for j in range(N)]
+    bits[31] ^= 1
+    st = otdvp.MPSState(omps.padded_product_state(bits, [1] * (N + 1)), Ws)
+    tr = otdvp.Truncation(chi_max=512, w_max=1e-8, eps=1e-12)
+    t0, n = time.perf_counter(), 0
+    while n < 10 and (n == 0 or time.perf_counter() - t0 < budget_s):
+        otdvp.tdvp2_step(st, 0.05, tr, tol=1e-10)
+        n += 1
+    out["xxx_n64_2tdvp"] = {"s_per_step": round((time.perf_counter() - t0) / n, 3), "steps_timed": n,
+                            "note": "the first steps of the 40-step quench (chi grows with time)"}
+    # N = 201 segments: one two-site update of the first phase at a real shape
+    # (bonds 384 | 192 | 192, w = 14, 8 Lanczos vectors and the split) and one
+    # two-site matvec at the largest shape of that phase (601 | 601 | 1009)
+    q = wl.XY_N201
+    c, lam, _ = ompo.fit_exponentials(1.0 / np.arange(1, q["N"]) ** q["alpha"], q["K"])
+    Wb = ompo.mpo_exponentials(6, c, lam, spin.xy_pairs())[2]
+    w = Wb.shape[0]
+    rng = np.random.default_rng(5)
+    res = {}
+    for tag, (cl, cm, cr), full in (("update_384x192x192", (384, 192, 192), True),
+                                    ("matvec_601x601x1009", (601, 601, 1009), False)):
+        b = wl.cgauss(rng, (cl, w, cl)) / np.sqrt(cl)
+        g = wl.cgauss(rng, (cr, w, cr)) / np.sqrt(cr)
+        Pl, Pr = wl.cgauss(rng, (cl, 2, cm)), wl.cgauss(rng, (cm, 2, cr))
+        V = np.ones(cm)
+        hop = lambda x: oheff.apply_heff2(b, Wb, Wb, g, x)
+        t0 = time.perf_counter()
+        if full:
+            oseg.local_pair_update(Pl, V, Pr, hop, 0.005, otdvp.Truncation(chi_max=cm), kmax=8, tol=0.0)
+        else:
+            hop(np.einsum("asb,btc->astc", Pl, Pr))
+        res[tag] = round(time.perf_counter() - t0, 3)
+    out["xy_n201_segments"] = {**res, "note": "synthetic environments at the real shapes of the first phase"}
+    # N = 32 Ising (the differentiation workload), one one-site TDVP step forward
+    p = wl.ISING_N32_GRAD
+    N = p["N"]
+    c, lam, _ = ompo.fit_exponentials(1.0 / np.arange(1, N) ** p["alpha"], p["K"])
+    Ws = ompo.mpo_exponentials(N, c, lam, spin.ising_pairs(), spin.SX, p["h"])
+    T0 = omps.normalize_centre(omps.right_canonicalize(
+        wl.random_site_tensors(p["seed_state"], wl.full_rank_bonds(N, 2, p["chi_cap"]), 2)))
+    st = otdvp.MPSState(T0, Ws)
+    t0 = time.perf_counter()
+    otdvp.tdvp1_step(st, p["dt"])
+    out["ising_n32_1tdvp"] = {"s_per_step": round(time.perf_counter() - t0, 2), "steps_timed": 1}
+    return out
 
 
 def ising_timing(pkg, ctx, wl):
@@ -190,6 +284,7 @@ def sweep_timing(pkg, ctx, steps=40, taylor=True):
             if timed:
                 prof[comp] = 0.25 * pkg.expect(ctx, mps, list(range(N)), sz).real
                 res[comp] = {"s_per_step": round(float(np.mean(times)), 4),
+                             "s_per_step_first10": round(float(np.mean(times[:10])), 4),
                              "s_per_step_last10": round(float(np.mean(times[-10:])), 4),
                              "matvecs_per_step": mv / steps,
                              "heff_env_gflops": round(flops / sum(times) * 1e-9, 1),
@@ -317,7 +412,8 @@ def gradient_timing(pkg, ctx, torch, np, steps=2):
     """Differentiable 1TDVP: N=32 long-range Ising (alpha 2, J = h = 1, K = 8,
     w = 10), random right-canonical state chi_j = min(2^j, 2^(32-j), 128),
     dt = 0.05, loss <sigma^z_16>, checkpoint every 5 steps; gradients with
-    respect to J and h through the hand-written apply_heff adjoint."""
+    respect to J and h through the hand-written apply_heff and environment
+    adjoints.  One untimed forward step per precision first."""
     import workloads as wl
     import paper_1912_06127_amd.autodiff as ad
     p = wl.ISING_N32_GRAD
@@ -336,6 +432,8 @@ def gradient_timing(pkg, ctx, torch, np, steps=2):
         h = torch.tensor(p["h"], dtype=torch.float64, device="cuda", requires_grad=True)
         Ws, _ = ad.mpo_sum_of_exponentials(N, c, lam, [(1.0, np.diag([1.0, -1.0]).astype(np.complex128),
                                                          np.diag([1.0, -1.0]).astype(np.complex128))], sx, J, h)
+        with torch.no_grad():  # untimed step: the GEMM autotuner sees this precision's shapes
+            ad.evolve(ctx, T0, [W.detach() for W in Ws], p["dt"], 1, compute=cdt, checkpoint_every=0)
         torch.cuda.synchronize()
         torch.cuda.reset_peak_memory_stats()
         base = torch.cuda.memory_allocated()  # buffers of earlier workloads still held
@@ -346,7 +444,7 @@ def gradient_timing(pkg, ctx, torch, np, steps=2):
         fwd = (time.perf_counter() - t0) / steps
         t0 = time.perf_counter()
         T = ad.evolve(ctx, T0, Ws, p["dt"], steps, compute=cdt, checkpoint_every=p["checkpoint_every"])
-        loss = ad.expect_site(T, p["site"] - 1, sz)
+        loss = ad.expect_site(ctx, T, p["site"] - 1, sz)
         loss.backward()
         torch.cuda.synchronize()
         both = (time.perf_counter() - t0) / steps
@@ -392,6 +490,8 @@ def main():
     ap.add_argument("--only-sweep", action="store_true",
                     help="run only the N=64 2TDVP quench sweep and print its timings (for profiling)")
     ap.add_argument("--grad-steps", type=int, default=2)
+    ap.add_argument("--only-grad", action="store_true",
+                    help="run only the differentiable 1TDVP workload (--grad-steps steps) and print its timings")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
@@ -410,6 +510,12 @@ def main():
     if args.only_sweep:
         ctx = pkg.Context(0)
         print(json.dumps({"sweep": sweep_timing(pkg, ctx, args.sweep_steps, taylor=not args.sweep_no_taylor)}))
+        ctx.close()
+        return
+
+    if args.only_grad:
+        ctx = pkg.Context(0)
+        print(json.dumps({"gradient": gradient_timing(pkg, ctx, torch, np, args.grad_steps)}))
         ctx.close()
         return
 
@@ -514,6 +620,9 @@ def main():
     if not args.no_cpu_baseline:
         progress("CPU oracle baseline")
         line["cpu_baseline"] = cpu_baseline(wl, W)
+        if not args.no_extras:
+            progress("CPU oracle beside the other workloads")
+            line["oracle_timings"] = oracle_timings(wl, W)
 
     ctx.close()
     print(json.dumps(line))

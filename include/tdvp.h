@@ -343,10 +343,14 @@ typedef struct {
                             min(chi_max, d^min(j, N-j)) (and, with static shapes, its
                             initial dimension), one-site steps from then on
                             (stats flags bit 1 tells which ran). */
+    int max_phases;      /* > 0: stop the step after this many phases of its
+                            schedule (inspection and testing of single phases;
+                            the state is then left mid-step and the next call
+                            starts a new step); 0: the whole step */
 } tdvp_seg_opts;
 
 /* Defaults: C64, krylov_k 8, chi_max 1<<30, w_max 0, eps_rel 0, guard on,
- * static_shapes 1, batched 1, use_graph 0, svd_mode 0, one_site 0. */
+ * static_shapes 1, batched 1, use_graph 0, svd_mode 0, one_site 0, max_phases 0. */
 int tdvp_seg_opts_default(tdvp_seg_opts* opts);
 
 /* Build the segmented state from host site tensors (complex128
@@ -484,6 +488,18 @@ size_t apply_heff_noalloc_max_bytes(void);
 int env_update(tdvp_ctx ctx, int dir, tdvp_dtype dtype, int chil, int chir, int d,
                int wl, int wr, const void* env_in, const void* A, const void* W,
                void* env_out);
+
+/* Adjoint of env_update (reverse mode; Sec. III A, Fig. environments): for a
+ * real loss and gradients in the convention g = dl/dRe z + i dl/dIm z,
+ * given out_bar = the gradient of env_out, writes the gradients of the
+ * inputs: env_bar (same shape as env_in), A_bar [chil][d][chir] (A enters
+ * as ket and, conjugated, as bra; both contributions are summed) and W_bar
+ * [wl][wr][d][d].  Any output may be NULL.  Same dimensions, layouts and
+ * dtype as env_update; device pointers owned by the caller; outputs must
+ * not alias inputs (TDVP_E_ARG). */
+int env_update_adjoint(tdvp_ctx ctx, int dir, tdvp_dtype dtype, int chil, int chir, int d, int wl, int wr,
+                       const void* env_in, const void* A, const void* W, const void* out_bar, void* env_bar,
+                       void* A_bar, void* W_bar);
 
 /* ------------------------------------------------------------ observables */
 

@@ -213,6 +213,21 @@ class SegStats:
     bond_updates: int = 0
 
 
+def local_pair_update(Psi_l, V, Psi_r, heff2, tau: float, tr: Truncation, kmax: int, tol: float):
+    """One two-site update of the segment schedule on its local data (Sec. III A
+    in the inverse canonical gauge, Fig. postupdate): Theta = Psi_l V Psi_r,
+    Theta <- exp(-i tau H_eff) Theta by Lanczos (heff2 applies H_eff), then the
+    truncated SVD Theta = U S Vh.  Returns (U [chil, d, chi], S, Vh [chi, d, chir],
+    discarded weight); the new tensors are Psi_l = U S, V = 1/S, Psi_r = S Vh."""
+    theta = np.einsum("asb,b,btc->astc", Psi_l, V, Psi_r)
+    theta = expm_krylov(heff2, theta, tau, kmax=kmax, tol=tol)
+    chil, d1, d2, chir = theta.shape
+    U, S, Vh = np.linalg.svd(theta.reshape(chil * d1, d2 * chir), full_matrices=False)
+    chi, w = truncation_rank(S, tr)
+    U, S, Vh = U[:, :chi], S[:chi], Vh[:chi, :]
+    return U.reshape(chil, d1, chi), S, Vh.reshape(chi, d2, chir), w
+
+
 class SegmentState:
     """Inverse canonical MPS, MPO and one stored beta/gamma per site.
 
@@ -266,16 +281,20 @@ class SegmentState:
         self.stats.site_updates += 1
 
     def pair_update(self, j: int, tau: float, refresh: str):
-        theta = np.einsum("asb,b,btc->astc", self.Psi[j], self.V[j], self.Psi[j + 1])
-        b, W1, W2, g = self.beta[j], self.W[j], self.W[j + 1], self.gamma[j + 1]
-        theta = self._expm(lambda x: apply_heff2(b, W1, W2, g, x), theta, tau)
-        chil, d1, d2, chir = theta.shape
-        U, S, Vh = np.linalg.svd(theta.reshape(chil * d1, d2 * chir), full_matrices=False)
         tr = self.tr
         if self.chi_static is not None:
             tr = Truncation(min(tr.chi_max, self.chi_static[j]), tr.w_max, tr.eps, tr.multiplet_guard)
-        chi, w = truncation_rank(S, tr)
-        U, S, Vh = U[:, :chi], S[:chi], Vh[:chi, :]
+        count = [0]
+
+        def op(x):
+            count[0] += 1
+            return apply_heff2(self.beta[j], self.W[j], self.W[j + 1], self.gamma[j + 1], x)
+
+        U, S, Vh, w = local_pair_update(self.Psi[j], self.V[j], self.Psi[j + 1], op, tau, tr, self.kmax, self.tol)
+        self.stats.matvecs += count[0]
+        chil, d1, chi = U.shape
+        d2, chir = Vh.shape[1], Vh.shape[2]
+        U, Vh = U.reshape(chil * d1, chi), Vh.reshape(chi, d2 * chir)
         self.stats.w_total += w
         self.stats.pair_updates += 1
         self.Psi[j] = (U * S[None, :]).reshape(chil, d1, chi)

@@ -43,6 +43,7 @@ class SegOpts(C.Structure):
         ("compute", C.c_int), ("krylov_k", C.c_int), ("chi_max", C.c_int), ("w_max", C.c_double),
         ("eps_rel", C.c_double), ("multiplet_guard", C.c_int), ("static_shapes", C.c_int),
         ("batched", C.c_int), ("use_graph", C.c_int), ("svd_mode", C.c_int), ("one_site", C.c_int),
+        ("max_phases", C.c_int),
     ]
 
 
@@ -99,6 +100,7 @@ SIGNATURES = {
     "apply_heff_noalloc": (_I, [_P, _I, _I, _I, _I, _I, _I, _I, _I, _P, _P, _P, _P, _P, _P]),
     "apply_heff_noalloc_max_bytes": (C.c_size_t, []),
     "env_update": (_I, [_P, _I, _I, _I, _I, _I, _I, _I, _P, _P, _P, _P]),
+    "env_update_adjoint": (_I, [_P, _I, _I, _I, _I, _I, _I, _I] + [_P] * 7),
     "apply_heff_adjoint": (_I, [_P, _I, _I, _I, _I, _I, _I, _I, _I] + [_P] * 11),
     "expect": (_I, [_P, _P, _I, _PI, _PD, _PD]),
     "transition_expect": (_I, [_P, _P, _P, _I, _PI, _PD, _PD]),

@@ -159,6 +159,9 @@ def _dtype_code(t: torch.Tensor) -> int:
 def _dev(t: torch.Tensor, dtype) -> C.c_void_p:
     if not t.is_cuda or not t.is_contiguous() or t.dtype != dtype:
         raise ValueError("tensor must be a contiguous device tensor of the common dtype")
+    if t.is_conj() or t.is_neg():
+        # a lazily conjugated (or negated) view: its memory does not hold its values
+        raise ValueError("tensor has a pending conjugation or negation; call resolve_conj()/resolve_neg() first")
     return C.c_void_p(t.data_ptr())
 
 
@@ -263,6 +266,27 @@ def env_update(ctx: Context, direction: int, env, A, W, out=None) -> torch.Tenso
         out = torch.empty(shape, dtype=dt, device=A.device)
     rc = _lib.load().env_update(ctx.handle, direction, _dtype_code(A), chil, chir, d, wl, wr,
                                 _dev(env, dt), _dev(A, dt), _dev(W, dt), _dev(out, dt))
+    _check(ctx.handle, rc)
+    return out
+
+
+def env_update_adjoint(ctx: Context, direction: int, env, A, W, out_bar, need=("env", "A", "W")) -> dict:
+    """Gradients of Re<out_bar, env_update(direction, env, A, W)> with respect to
+    env, A and W (the requested entries of "env", "A", "W")."""
+    dt = A.dtype
+    out = {}
+    if "env" in need:
+        out["env"] = torch.empty_like(env)
+    if "A" in need:
+        out["A"] = torch.empty_like(A)
+    if "W" in need:
+        out["W"] = torch.empty_like(W)
+    chil, d, chir = A.shape
+    wl, wr = W.shape[0], W.shape[1]
+    ptr = lambda t: _dev(t, dt) if t is not None else C.c_void_p()
+    rc = _lib.load().env_update_adjoint(ctx.handle, direction, _dtype_code(A), chil, chir, d, wl, wr, ptr(env),
+                                        ptr(A), ptr(W), ptr(out_bar), ptr(out.get("env")), ptr(out.get("A")),
+                                        ptr(out.get("W")))
     _check(ctx.handle, rc)
     return out
 
@@ -520,6 +544,7 @@ class SegmentOptions:
     use_graph: bool = False
     svd_mode: int = 0
     one_site: bool | str = False  # one-site sweeps with two-site boundary pairs; "auto": hybrid switch
+    max_phases: int = 0          # > 0: stop after this many phases (inspection; leaves the state mid-step)
 
     def to_c(self) -> SegOpts:
         o = SegOpts()
@@ -539,6 +564,7 @@ class SegmentOptions:
             o.one_site = int(self.one_site)
         else:
             raise ValueError(f"one_site must be a bool or 'auto', not {self.one_site!r}")
+        o.max_phases = int(self.max_phases)
         return o
 
 

@@ -1,14 +1,19 @@
 """Reverse-mode differentiation of one-site TDVP (Sec. II D, Eq. proj1site).
 
-Every effective-Hamiltonian application runs through ``ApplyHeff``, a
-``torch.autograd.Function`` whose forward is the library's ``apply_heff``
-kernel and whose backward is the hand-written ``apply_heff_adjoint`` kernel
-(gradients with respect to the state, both environments and the MPO tensor).
-The rest of the differentiable step (Lanczos recursion, the small Krylov
-exponential, QR/LQ gauge moves, environment updates) is composed of torch
-operations on device tensors, so autograd chains them.  Environments are not
-stored across time steps: ``checkpoint_every`` steps form one
-``torch.utils.checkpoint`` block that is recomputed during the backward pass.
+Every effective-Hamiltonian application runs through ``ApplyHeff`` and every
+environment update through ``EnvUpdate``: ``torch.autograd.Function``s whose
+forwards are the library's ``apply_heff`` / ``env_update`` kernels and whose
+backwards are the hand-written ``apply_heff_adjoint`` / ``env_update_adjoint``
+kernels (gradients with respect to the state, both environments and the MPO
+tensor).  The expectation value of the loss is a chain of environment updates
+with a one-channel MPO.  What remains torch operations, chained by autograd,
+is the Lanczos recursion on vectors, the small Krylov exponential, the QR/LQ
+gauge moves and the product of a bond matrix with the next site tensor.
+Environments are held in the compute precision (complex64 runs the
+contractions on FP32 MFMA), site tensors and Lanczos vectors in complex128.
+Environments are not stored across time steps: ``checkpoint_every`` steps form
+one ``torch.utils.checkpoint`` block that is recomputed during the backward
+pass.
 
 Layouts follow the library: site tensors A[a][s][b], MPO W[k][l][s'][s],
 environments L[k][a'][a] and R[l][b][b'].
@@ -21,23 +26,28 @@ from torch.utils.checkpoint import checkpoint
 from . import api
 
 
+def _dense(t, dtype):
+    """t in `dtype`, contiguous, with any lazy conjugation or negation applied
+    to its memory (the library reads raw device memory)."""
+    return t.to(dtype).resolve_conj().resolve_neg().contiguous()
+
+
 class ApplyHeff(torch.autograd.Function):
     """y = H_eff x for a zero-site (W None) or one-site local state.
 
-    ``compute`` is the dtype the kernel runs in (complex64: FP32 MFMA; the
-    state may be complex128 and is cast on the way in and out).
+    ``compute`` is the dtype the kernel runs in (complex64: FP32 MFMA).  The
+    environments are expected in that dtype already (``EnvUpdate`` produces
+    them so); the state may be complex128 and is cast on the way in and out.
     """
 
     @staticmethod
     def forward(ctx_, lib_ctx, compute, x, L, W, R):
-        cx = x.to(compute).contiguous()
-        cL = L.to(compute).contiguous()
-        cR = R.to(compute).contiguous()
-        cW = None if W is None else W.to(compute).contiguous()
+        cx = _dense(x, compute)
+        cL = _dense(L, compute)
+        cR = _dense(R, compute)
+        cW = None if W is None else _dense(W, compute)
         y = api.apply_heff(lib_ctx, cL, cR, cx, cW)
-        # the originals are saved (shared by every matvec of a Krylov run),
-        # not the converted copies
-        ctx_.save_for_backward(x, L, W if W is not None else torch.empty(0, device=x.device), R)
+        ctx_.save_for_backward(x, cL, cW if cW is not None else torch.empty(0, device=x.device), cR)
         ctx_.lib_ctx = lib_ctx
         ctx_.compute = compute
         ctx_.has_w = W is not None
@@ -46,10 +56,10 @@ class ApplyHeff(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx_, ybar):
-        x, L, W0, R = ctx_.saved_tensors
+        x, cL, cW, cR = ctx_.saved_tensors
         cdt = ctx_.compute
-        cx, cL, cR = (t.to(cdt).contiguous() for t in (x, L, R))
-        W = W0.to(cdt).contiguous() if ctx_.has_w else None
+        cx = _dense(x, cdt)
+        W = cW if ctx_.has_w else None
         need = []
         if ctx_.needs_input_grad[2]:
             need.append("theta")
@@ -59,21 +69,49 @@ class ApplyHeff(torch.autograd.Function):
             need.append("W")
         if ctx_.needs_input_grad[5]:
             need.append("R")
-        g = api.apply_heff_adjoint(ctx_.lib_ctx, cL, cR, cx, ybar.to(cx.dtype).contiguous(), W, need=need)
+        g = api.apply_heff_adjoint(ctx_.lib_ctx, cL, cR, cx, _dense(ybar, cdt), W, need=need)
         xd, Ld, Wd, Rd = ctx_.dtypes
         conv = lambda k, dt: g[k].to(dt) if k in g else None
         return (None, None, conv("theta", xd), conv("L", Ld), conv("W", Wd) if Wd is not None else None,
                 conv("R", Rd))
 
 
-def env_left(L, A, W):
-    """L'[l][b'][b] = sum conj(A[a' s' b']) L[k][a'][a] W[k][l][s'][s] A[a s b]."""
-    return torch.einsum("kpa,ptb,klts,asc->lbc", L, A.conj(), W, A)
+class EnvUpdate(torch.autograd.Function):
+    """Environment update (direction +1: left, -1: right) in the compute dtype;
+    backward by the library's env_update_adjoint."""
+
+    @staticmethod
+    def forward(ctx_, lib_ctx, compute, direction, env, A, W):
+        cenv = _dense(env, compute)
+        cA = _dense(A, compute)
+        cW = _dense(W, compute)
+        out = api.env_update(lib_ctx, direction, cenv, cA, cW)
+        ctx_.save_for_backward(cenv, cA, cW)
+        ctx_.lib_ctx = lib_ctx
+        ctx_.direction = direction
+        ctx_.dtypes = (env.dtype, A.dtype, W.dtype)
+        return out
+
+    @staticmethod
+    def backward(ctx_, gout):
+        cenv, cA, cW = ctx_.saved_tensors
+        need = [k for k, i in (("env", 3), ("A", 4), ("W", 5)) if ctx_.needs_input_grad[i]]
+        if not need:
+            return None, None, None, None, None, None
+        g = api.env_update_adjoint(ctx_.lib_ctx, ctx_.direction, cenv, cA, cW, _dense(gout, cA.dtype), need=need)
+        ed, ad, wd = ctx_.dtypes
+        conv = lambda k, dt: g[k].to(dt) if k in g else None
+        return None, None, None, conv("env", ed), conv("A", ad), conv("W", wd)
 
 
-def env_right(R, A, W):
-    """R'[k][a][a'] = sum A[a s b] W[k][l][s'][s] R[l][b][b'] conj(A[a' s' b'])."""
-    return torch.einsum("asb,klts,lbc,ptc->kap", A, W, R, A.conj())
+def env_left(lib_ctx, compute, L, A, W):
+    """L'[l][b'][b] = sum conj(A[a' s' b']) L[k][a'][a] W[k][l][s'][s] A[a s b] (library kernel)."""
+    return EnvUpdate.apply(lib_ctx, compute, 1, L, A, W)
+
+
+def env_right(lib_ctx, compute, R, A, W):
+    """R'[k][a][a'] = sum A[a s b] W[k][l][s'][s] R[l][b][b'] conj(A[a' s' b']) (library kernel)."""
+    return EnvUpdate.apply(lib_ctx, compute, -1, R, A, W)
 
 
 class Project(torch.autograd.Function):
@@ -152,14 +190,24 @@ def _lq(M):
     return R.conj().T, Q.conj().T
 
 
-def right_envs(T, Ws):
+def right_envs(lib_ctx, T, Ws, compute):
     N = len(T)
-    one = torch.ones((1, 1, 1), dtype=T[0].dtype, device=T[0].device)
+    one = torch.ones((1, 1, 1), dtype=compute, device=T[0].device)
     R = [None] * N
     R[N - 1] = one
     for j in range(N - 1, 0, -1):
-        R[j - 1] = env_right(R[j], T[j], Ws[j])
+        R[j - 1] = env_right(lib_ctx, compute, R[j], T[j], Ws[j])
     return R
+
+
+def _absorb_left(C, A):
+    """C[a][b] A[b][s][c] (bond matrix into the next site)."""
+    return (C @ A.reshape(A.shape[0], -1)).reshape(C.shape[0], A.shape[1], A.shape[2])
+
+
+def _absorb_right(A, C):
+    """A[a][s][b] C[b][c] (bond matrix into the previous site)."""
+    return (A.reshape(-1, A.shape[2]) @ C).reshape(A.shape[0], A.shape[1], C.shape[1])
 
 
 def tdvp1_step(lib_ctx, T, Ws, dt, compute=torch.complex128, kmax=40, tol=1e-13):
@@ -171,10 +219,10 @@ def tdvp1_step(lib_ctx, T, Ws, dt, compute=torch.complex128, kmax=40, tol=1e-13)
     T = list(T)
     N = len(T)
     tau = dt / 2.0
-    one = torch.ones((1, 1, 1), dtype=T[0].dtype, device=T[0].device)
+    one = torch.ones((1, 1, 1), dtype=compute, device=T[0].device)
     L = [None] * N
     L[0] = one
-    R = right_envs(T, Ws)
+    R = right_envs(lib_ctx, T, Ws, compute)
     h1 = lambda j: (lambda x: ApplyHeff.apply(lib_ctx, compute, x, L[j], Ws[j], R[j]))
     h0 = lambda j: (lambda x: ApplyHeff.apply(lib_ctx, compute, x, L[j + 1], None, R[j]))
     for j in range(N - 1):
@@ -182,32 +230,38 @@ def tdvp1_step(lib_ctx, T, Ws, dt, compute=torch.complex128, kmax=40, tol=1e-13)
         chil, d, chir = T[j].shape
         Q, C = torch.linalg.qr(T[j].reshape(chil * d, chir))
         T[j] = Q.reshape(chil, d, chir)
-        L[j + 1] = env_left(L[j], T[j], Ws[j])
+        L[j + 1] = env_left(lib_ctx, compute, L[j], T[j], Ws[j])
         C = expm_lanczos(h0(j), C, -tau, kmax, tol)
-        T[j + 1] = torch.einsum("ab,bsc->asc", C, T[j + 1])
+        T[j + 1] = _absorb_left(C, T[j + 1])
     T[N - 1] = expm_lanczos(h1(N - 1), T[N - 1], dt, kmax, tol)
     for j in range(N - 1, 0, -1):
         chil, d, chir = T[j].shape
         Lf, Q = _lq(T[j].reshape(chil, d * chir))
         T[j] = Q.reshape(chil, d, chir)
-        R[j - 1] = env_right(R[j], T[j], Ws[j])
+        R[j - 1] = env_right(lib_ctx, compute, R[j], T[j], Ws[j])
         Lf = expm_lanczos(h0(j - 1), Lf, -tau, kmax, tol)
-        T[j - 1] = torch.einsum("asb,bc->asc", T[j - 1], Lf)
+        T[j - 1] = _absorb_right(T[j - 1], Lf)
         T[j - 1] = expm_lanczos(h1(j - 1), T[j - 1], tau, kmax, tol)
     return T
 
 
-def expect_site(T, site, O):
-    """<psi|O_site|psi>/<psi|psi> (differentiable transfer contraction, 0-based site)."""
-    E = torch.ones((1, 1), dtype=T[0].dtype, device=T[0].device)
+def expect_site(lib_ctx, T, site, O):
+    """<psi|O_site|psi>/<psi|psi> (0-based site) as two chains of left
+    environment updates with one-channel MPOs (identity, and O on ``site``),
+    run by the library's kernels in complex128."""
+    dev, cdt = T[0].device, torch.complex128
+    d = T[0].shape[1]
+    eye = torch.eye(d, dtype=cdt, device=dev).reshape(1, 1, d, d)
+    Oj = torch.as_tensor(O, dtype=cdt, device=dev).reshape(1, 1, d, d)
+    E = torch.ones((1, 1, 1), dtype=cdt, device=dev)
     num = None
     for j, A in enumerate(T):
         if j == site:
-            num = torch.einsum("xy,xtb,ts,ysc->bc", E, A.conj(), O, A)
+            num = env_left(lib_ctx, cdt, E, A, Oj)
         elif num is not None:
-            num = torch.einsum("xy,xsb,ysc->bc", num, A.conj(), A)
-        E = torch.einsum("xy,xsb,ysc->bc", E, A.conj(), A)
-    return (num[0, 0] / E[0, 0]).real
+            num = env_left(lib_ctx, cdt, num, A, eye)
+        E = env_left(lib_ctx, cdt, E, A, eye)
+    return (num[0, 0, 0] / E[0, 0, 0]).real
 
 
 def evolve(lib_ctx, T, Ws, dt, steps, compute=torch.complex128, checkpoint_every=5, kmax=40, tol=1e-13):

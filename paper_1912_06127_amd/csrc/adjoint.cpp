@@ -185,11 +185,73 @@ void heff_adjoint(tdvp_ctx ctx, const AdjointArgs& a) {
     }
 }
 
+// Adjoint of the environment update (Sec. III A, Fig. environments).  Left:
+// L'[l][b'][b] = sum conj(A[a' s' b']) L[k][a'][a] W[k][l][s'][s] A[a s b];
+// right: R'[k][a][a'] = sum A[a s b] W[k][l][s'][s] R[l][b][b'] conj(A[a' s' b']).
+// Given out_bar = the gradient of R' (or L'), with Hb the blockwise conjugate
+// transpose of out_bar and H = the one-site effective Hamiltonian built from
+// (L, W, Hb) (left) or (Hb, W, R) (right):
+//   env_bar = the opposite-direction update of out_bar with the blockwise
+//             conjugate transpose of W (the map is linear in the environment),
+//   A_bar   = H^dagger A + H A  (A enters once as ket, once conjugated as bra),
+//   W_bar   = the MPO-tensor gradient of Re<A, H A>.
+void env_adjoint(tdvp_ctx ctx, int dir, Dt dt, int chil, int chir, int d, int wl, int wr, const void* env_in,
+                 const void* A, const void* W, const void* out_bar, void* env_bar, void* A_bar, void* W_bar) {
+    const bool fp64 = dt == Dt::C128;
+    const size_t esz = elem_bytes(dt);
+    if (env_bar) {
+        void* WH = ctx->workspace("envadj_WH", esz * (size_t)wl * wr * d * d);
+        conj_transpose_batched(WH, W, dt, d, wl * wr, ctx->stream);
+        Mop m;
+        mop_make(ctx, m, dir == 1 ? 3 : 1, WH, nullptr, dt, wl, wl, wr, d, fp64, false);
+        EnvArgs a{chil, chir, chil, chir, d, wl, wr, A, A, dt, &m, fp64, raw_gemm_form(ctx, fp64)};
+        if (dir == 1) env_right(ctx, a, out_bar, dt, env_bar, dt);
+        else env_left(ctx, a, out_bar, dt, env_bar, dt);
+    }
+    if (!A_bar && !W_bar) return;
+    const int wo = dir == 1 ? wr : wl, co = dir == 1 ? chir : chil;
+    void* Hb = ctx->workspace("envadj_Hb", esz * (size_t)wo * co * co);
+    conj_transpose_batched(Hb, out_bar, dt, co, wo, ctx->stream);
+    const void* Luse = dir == 1 ? env_in : Hb;
+    const void* Ruse = dir == 1 ? Hb : env_in;
+    AdjointArgs g{1, chil, chir, d, wl, wl, wr, Luse, W, nullptr, Ruse, A, A, A_bar, nullptr, W_bar, nullptr, dt};
+    heff_adjoint(ctx, g);  // A_bar = H^dagger A, W_bar
+    if (A_bar) {
+        const int64_t n = (int64_t)chil * d * chir;
+        void* HA = ctx->workspace("envadj_HA", esz * (size_t)n);
+        Mop m;
+        mop_make(ctx, m, 1, W, nullptr, dt, wl, wl, wr, d, fp64, false);
+        HeffArgs h{1, chil, chir, d, wl, wr, Luse, Ruse, dt, &m, fp64, raw_gemm_form(ctx, fp64)};
+        heff_apply(ctx, h, A, dt, HA, dt);
+        add_inplace(A_bar, HA, dt, n, ctx->stream);
+    }
+}
+
 }  // namespace tdvp
 
 using namespace tdvp;
 
 extern "C" {
+
+int env_update_adjoint(tdvp_ctx ctx, int dir, tdvp_dtype dtype, int chil, int chir, int d, int wl, int wr,
+                       const void* env_in, const void* A, const void* W, const void* out_bar, void* env_bar,
+                       void* A_bar, void* W_bar) {
+    if (!ctx) return TDVP_E_ARG;
+    return guarded(ctx, [&] {
+        const Dt dt = to_dt(dtype);
+        TDVP_REQUIRE(dir == 1 || dir == -1, TDVP_E_ARG, "env_update_adjoint: dir must be +1 or -1");
+        TDVP_REQUIRE(chil >= 1 && chir >= 1 && d >= 1 && wl >= 1 && wr >= 1, TDVP_E_SHAPE,
+                     "env_update_adjoint: dimensions must be positive");
+        TDVP_REQUIRE(env_in && A && W && out_bar, TDVP_E_ARG, "env_update_adjoint: null input");
+        const void* ins[] = {env_in, A, W, out_bar};
+        void* outs[] = {env_bar, A_bar, W_bar};
+        for (void* o : outs)
+            for (const void* i : ins)
+                TDVP_REQUIRE(!o || o != i, TDVP_E_ARG, "env_update_adjoint: an output aliases an input");
+        env_adjoint(ctx, dir, dt, chil, chir, d, wl, wr, env_in, A, W, out_bar, env_bar, A_bar, W_bar);
+    });
+}
+
 
 int apply_heff_adjoint(tdvp_ctx ctx, int nsite, tdvp_dtype dtype, int chil, int chir, int d, int wl, int wm,
                        int wr, const void* L, const void* W1, const void* W2, const void* R, const void* theta,

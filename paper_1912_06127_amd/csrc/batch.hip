@@ -183,7 +183,7 @@ __global__ void lz_start_kernel(int n, int K, const double2* nrm2, double* beta0
                                 double* beta, double* scale, int* done, int* bad) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const double b = sqrt(fmax(0.0, nrm2[(int64_t)i * (K + 1)].x));
+    const double b = sqrt_or_nan(nrm2[(int64_t)i * (K + 1)].x);
     beta0[i] = b;
     inv[i] = b > 0.0 ? 1.0 / b : 0.0;
     done[i] = b > 0.0 ? 0 : 1;
@@ -211,7 +211,7 @@ __global__ void lz_beta_kernel(int n, int K, int k, const double2* nrm2, double*
                                int* done, int* bad) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const double b = sqrt(fmax(0.0, nrm2[(int64_t)i * (K + 1)].x));
+    const double b = sqrt_or_nan(nrm2[(int64_t)i * (K + 1)].x);
     if (!isfinite(b)) bad[i] = 1;
     const double sc = scale[i];
     if (done[i] || !(b > 1e-14 * sc) || sc == 0.0) {

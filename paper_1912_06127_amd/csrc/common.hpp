@@ -70,6 +70,12 @@ struct tdvp_prof_total {
 };
 
 namespace tdvp {
+// Square root of a squared norm: negative rounding noise gives 0, while NaN
+// stays NaN (fmax/std::max would turn it into 0 and hide a non-finite value).
+__host__ __device__ inline double sqrt_or_nan(double x) { return x > 0.0 ? sqrt(x) : (x <= 0.0 ? 0.0 : x); }
+}  // namespace tdvp
+
+namespace tdvp {
 // Fixed device region handed out by workspace() while a call runs without
 // allocating (apply_heff_noalloc): requests are carved from it in order, a
 // name asked for twice gets the same block, and a request that does not fit
@@ -334,6 +340,8 @@ void mop_build(int kind, const void* W1, Dt w1dt, const void* W2, Dt w2dt, int w
                bool val_fp64, hipStream_t s);
 // out[z] = in[z]^dagger for `batch` n x n blocks of dtype dt.
 void conj_transpose_batched(void* out, const void* in, Dt dt, int n, int batch, hipStream_t s);
+// y += x elementwise over n complex entries of dtype dt.
+void add_inplace(void* y, const void* x, Dt dt, int64_t n, hipStream_t s);
 // out[k][l][s'][s] = sum_{a',b} conj(T1[k][a'][s][b]) Z[l][a'][s'][b] (T1 [wl][chil][d][chir],
 // Z [wr][chil][d][chir], out [wl][wr][d][d], all of dtype dt).
 void wgrad(const void* T1, const void* Z, Dt dt, int wl, int wr, int d, int chil, int chir, void* out,

@@ -361,7 +361,7 @@ __global__ void __launch_bounds__(kSmallThreads) lanczos_small_kernel(double2* V
                                                                       double beta_prev, const double* nn_prev,
                                                                       double* out) {
     // beta_{k-1} from the previous step's ||w||^2 when it is still on the device
-    if (nn_prev) beta_prev = sqrt(fmax(0.0, *nn_prev));
+    if (nn_prev) beta_prev = sqrt_or_nan(*nn_prev);
     __shared__ double sre[kSmallMaxK + 1][kSmallWaves], sim[kSmallMaxK + 1][kSmallWaves];
     __shared__ double coef_re[kSmallMaxK + 1], coef_im[kSmallMaxK + 1];
     __shared__ double part[kSmallWaves];
@@ -750,6 +750,16 @@ __global__ void conj_transpose_batched_kernel(void* out, const void* in, int c12
     double re, im;
     ld<double>(in, c128, base + (int64_t)i * n + j, re, im);
     st<double>(out, c128, base + (int64_t)j * n + i, re, -im);
+}
+
+// y[i] += x[i] for n complex entries of one dtype
+__global__ void add_inplace_kernel(void* y, const void* x, int c128, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double yr, yi, xr, xi;
+        ld<double>(y, c128, i, yr, yi);
+        ld<double>(x, c128, i, xr, xi);
+        st<double>(y, c128, i, yr + xr, yi + xi);
+    }
 }
 
 // MPO-tensor gradient of the one-site effective Hamiltonian:
@@ -1255,6 +1265,13 @@ void conj_transpose_batched(void* out, const void* in, Dt dt, int n, int batch, 
     TDVP_REQUIRE(n <= 65535 && batch <= 65535, TDVP_E_SHAPE, "conj_transpose_batched: too large");
     dim3 grid((n + 127) / 128, n, batch);
     hipLaunchKernelGGL(conj_transpose_batched_kernel, grid, dim3(128), 0, s, out, in, (int)(dt == Dt::C128), n);
+    TDVP_CHECK_HIP(hipGetLastError());
+}
+
+void add_inplace(void* y, const void* x, Dt dt, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(add_inplace_kernel, dim3(blocks), dim3(256), 0, s, y, x, (int)(dt == Dt::C128), n);
     TDVP_CHECK_HIP(hipGetLastError());
 }
 

@@ -114,7 +114,7 @@ KrylovInfo krylov_run(tdvp_ctx ctx, const MatVec& op, double2* theta, int64_t n,
     const bool small = n <= kSmallLanczos && kmax < 64;
     double beta0 = 0.0;
     auto check_beta0 = [&](double nn0) {
-        beta0 = std::sqrt(std::max(0.0, nn0));
+        beta0 = sqrt_or_nan(nn0);
         TDVP_REQUIRE(std::isfinite(beta0), TDVP_E_NUMERIC, "Krylov: non-finite input norm");
     };
     if (!small) {
@@ -163,7 +163,7 @@ KrylovInfo krylov_run(tdvp_ctx ctx, const MatVec& op, double2* theta, int64_t n,
     // Consumes iteration k's alpha_k and ||w||^2; returns true when the
     // iteration stops here.
     auto consume = [&](int k, double a, double nn) -> bool {
-        const double b = std::sqrt(std::max(0.0, nn));
+        const double b = sqrt_or_nan(nn);
         ++info.matvecs;
         TDVP_REQUIRE(std::isfinite(a) && std::isfinite(b), TDVP_E_NUMERIC,
                      "Krylov: non-finite value in H_eff application");
@@ -363,8 +363,8 @@ KrylovInfo expm_taylor(tdvp_ctx ctx, const MatVec& op, double2* theta, int64_t n
         vdot_multi(ctx, F, 0, 1, F, n, nrm + 1);
         TDVP_CHECK_HIP(hipMemcpyAsync(h, nrm, sizeof(h), hipMemcpyDeviceToHost, st));
         TDVP_CHECK_HIP(hipStreamSynchronize(st));
-        nb = std::sqrt(std::max(0.0, h[0].x));
-        nf = std::sqrt(std::max(0.0, h[1].x));
+        nb = sqrt_or_nan(h[0].x);
+        nf = sqrt_or_nan(h[1].x);
         TDVP_REQUIRE(std::isfinite(nb) && std::isfinite(nf), TDVP_E_NUMERIC,
                      "Taylor exponential: non-finite value in H_eff application");
     };

@@ -867,16 +867,19 @@ struct SegRun {
     void step(double dt) {
         reset_flag(ctx, sg->flag.as<int>());
         const auto t0 = std::chrono::steady_clock::now();
-        for (int half = 0; half < 2; ++half) {
+        int done = 0;  // phases run so far (o.max_phases > 0 stops the step early)
+        auto more = [&] { return o.max_phases <= 0 || done < o.max_phases; };
+        for (int half = 0; half < 2 && more(); ++half) {
             const bool first = half == 0;
             if (o.one_site) {
                 sg->mixed_gauge = true;
                 const std::vector<SPhase> phases = seg_schedule1(sg->sizes, dt, first);
-                for (size_t idx = 0; idx < phases.size(); ++idx) run_one_site_phase(phases[idx], first, (int)idx);
+                for (size_t idx = 0; idx < phases.size() && more(); ++idx, ++done)
+                    run_one_site_phase(phases[idx], first, (int)idx);
                 continue;
             }
             const std::vector<SPhase> phases = seg_schedule(sg->sizes, dt, first);
-            for (size_t idx = 0; idx < phases.size(); ++idx) {
+            for (size_t idx = 0; idx < phases.size() && more(); ++idx, ++done) {
                 const SPhase& ph = phases[idx];
                 const bool pair = ph[0].pair;
                 for (const auto& op : ph)
@@ -1099,6 +1102,7 @@ int tdvp_seg_opts_default(tdvp_seg_opts* o) {
     o->use_graph = 0;
     o->svd_mode = 0;
     o->one_site = 0;
+    o->max_phases = 0;
     return TDVP_OK;
 }
 
@@ -1168,6 +1172,7 @@ int seg_step(tdvp_ctx ctx, tdvp_seg sg, tdvp_mpo mpo, double dt, const tdvp_seg_
                      "seg_step: graphs need the batched path with static shapes");
         TDVP_REQUIRE(o.svd_mode >= 0 && o.svd_mode <= 2, TDVP_E_ARG, "seg_step: svd_mode must be 0, 1 or 2");
         TDVP_REQUIRE(o.one_site >= 0 && o.one_site <= 2, TDVP_E_ARG, "seg_step: one_site must be 0, 1 or 2");
+        TDVP_REQUIRE(o.max_phases >= 0, TDVP_E_ARG, "seg_step: max_phases must be >= 0");
         if (o.one_site)
             for (size_t s = 1; s + 1 < sg->sizes.size(); ++s)
                 TDVP_REQUIRE(sg->sizes[s] >= 3, TDVP_E_SHAPE,

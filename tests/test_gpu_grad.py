@@ -76,6 +76,51 @@ def test_apply_heff_adjoint_matches_oracle(ctx, dt, nsite):
         assert rel_err(_h(g["W"]), wb) <= TOL[dt]
 
 
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("direction", [1, -1])
+def test_env_update_adjoint_matches_oracle(ctx, dt, direction):
+    """Adjoint identity Re<gbar, dF> = Re<g_x, dx> for each input x of the
+    environment update, with dF from the oracle's forward update: central
+    differences with step 1 are exact (the update is linear in the environment
+    and the MPO tensor, quadratic in the site tensor)."""
+    import paper_1912_06127_amd as pkg
+    from oracle import env as oenv
+    rng = np.random.default_rng(300 + direction)
+    chil, chir, d, wl_, wr = 37, 29, 2, 5, 6
+    A = wl.cgauss(rng, (chil, d, chir))
+    W = wl.cgauss(rng, (wl_, wr, d, d))
+    if direction == 1:
+        env = wl.cgauss(rng, (chil, wl_, chil))                      # beta [a', k, a]
+        fwd = lambda e, a, w: L_from_beta(oenv.update_left(e, a, w))  # L' [l][b'][b]
+        env_lib = L_from_beta(env)
+        to_lib = L_from_beta
+        gbar = wl.cgauss(rng, (wr, chir, chir))
+    else:
+        env = wl.cgauss(rng, (chir, wr, chir))                        # gamma [b', l, b]
+        fwd = lambda e, a, w: R_from_gamma(oenv.update_right(e, a, w))
+        env_lib = R_from_gamma(env)
+        to_lib = R_from_gamma
+        gbar = wl.cgauss(rng, (wl_, chil, chil))
+    print(f"env adjoint dir={direction} {dt}", flush=True)
+    g = pkg.env_update_adjoint(ctx, direction, _t(env_lib, dt), _t(A, dt), _t(W, dt), _t(gbar, dt))
+    ctx.sync()
+    tol = TOL[dt] * 10
+    for name in ("env", "A", "W"):
+        for rep in range(3):
+            dx = wl.cgauss(rng, {"env": env.shape, "A": A.shape, "W": W.shape}[name])
+            args_p = [env, A, W]
+            args_m = [env, A, W]
+            i = ("env", "A", "W").index(name)
+            args_p[i] = args_p[i] + dx
+            args_m[i] = args_m[i] - dx
+            dF = (fwd(*args_p) - fwd(*args_m)) / 2.0
+            lhs = float(np.real(np.vdot(gbar, dF)))
+            dx_lib = to_lib(dx) if name == "env" else dx
+            rhs = float(np.real(np.vdot(_h(g[name]), dx_lib)))
+            scale = np.linalg.norm(gbar) * np.linalg.norm(dF)
+            assert abs(lhs - rhs) <= tol * scale, (name, rep, lhs, rhs)
+
+
 def ising_fit(N, K=3, alpha=2.0, rmax=16):
     """1/r^alpha fitted on r = 1..max(rmax, N-1): a well-posed pencil for any N."""
     c, lam, _ = ompo.fit_exponentials(1.0 / np.arange(1, max(rmax, N - 1) + 1) ** alpha, K)
@@ -98,7 +143,7 @@ def gpu_grad(ctx, bulk_np, T0, N, dt, steps, site, compute, checkpoint_every=2):
     Ws = ad.sites_from_bulk(bulk, N)
     T = [torch.from_numpy(A).to("cuda") for A in T0]
     T = ad.evolve(ctx, T, Ws, dt, steps, compute=cdt, checkpoint_every=checkpoint_every)
-    loss = ad.expect_site(T, site, torch.from_numpy(spin.SZ).to("cuda"))
+    loss = ad.expect_site(ctx, T, site, torch.from_numpy(spin.SZ).to("cuda"))
     loss.backward()
     return float(loss.detach()), bulk.grad.detach().cpu().numpy()
 
@@ -190,7 +235,7 @@ def test_gradient_flows_to_couplings(ctx):
     Ws, _ = ad.mpo_sum_of_exponentials(N, c, lam, spin.ising_pairs(), spin.SX, J, h)
     T0 = omps.normalize_centre(omps.right_canonicalize(wl.random_site_tensors(8, wl.full_rank_bonds(N, 2, 4), 2)))
     T = ad.evolve(ctx, [torch.from_numpy(A).to("cuda") for A in T0], Ws, dt, steps)
-    loss = ad.expect_site(T, site, torch.from_numpy(spin.SZ).to("cuda"))
+    loss = ad.expect_site(ctx, T, site, torch.from_numpy(spin.SZ).to("cuda"))
     loss.backward()
     bulk = ompo.mpo_exponentials(4, c, lam, spin.ising_pairs(), spin.SX, 1.0)[1]
     dirs = directions(c, lam, N)
