@@ -489,6 +489,36 @@ int env_update(tdvp_ctx ctx, int dir, tdvp_dtype dtype, int chil, int chir, int 
                int wl, int wr, const void* env_in, const void* A, const void* W,
                void* env_out);
 
+/* U(1) block-sparse H_eff application (quantum-number blocks; the S^z
+ * conservation of the XY and XXX chains of Sec. IV, which the paper's
+ * largest runs exploit through block-sparse tensors).  Same arguments,
+ * layouts and result as apply_heff, plus integer charge labels (host
+ * arrays): q_left [chil] and q_right [chir] of the bond indices (the charge
+ * of the block to their left; each must be non-decreasing, so every charge
+ * sector is a contiguous index range), q_phys [d] of the physical index, and
+ * c_left [wl], c_right [wr] of the outer MPO bonds (the charge the operator
+ * string to their left adds).  The inputs must obey the charge rules
+ *   theta[a][s..][b]: q(a) + q(s..) = q(b);  W[k][l][s'][s]: c(l) = c(k) + q(s') - q(s);
+ *   L[k][a'][a]: q(a') - q(a) = c(k);        R[l][b][b']: q(b') - q(b) = c(l);
+ * entries outside the allowed blocks are never read (except that the MPO
+ * must be exactly zero there), and the output is written in full (zero
+ * outside its allowed blocks).  Only the allowed blocks are multiplied: the
+ * two GEMM stages run as block products and the MPO stage on the sector
+ * rectangles some term can reach.  Synchronises the context stream (the
+ * block tables are built on the host per call).  Errors as apply_heff, plus
+ * TDVP_E_ARG for unsorted labels. */
+int apply_heff_u1(tdvp_ctx ctx, int nsite, tdvp_dtype dtype, int chil, int chir, int d, int wl, int wm, int wr,
+                  const int* q_left, const int* q_right, const int* q_phys, const int* c_left, const int* c_right,
+                  const void* L, const void* W1, const void* W2, const void* R, const void* theta, void* out);
+/* U(1) block-sparse env_update: same arguments and result as env_update
+ * (A [chil][d][chir], W [wl][wr][d][d]), charge labels as for
+ * apply_heff_u1 (q_left [chil], q_right [chir], q_phys [d], c_left [wl],
+ * c_right [wr]); inputs must obey the charge rules, the output is written in
+ * full.  Synchronises the context stream. */
+int env_update_u1(tdvp_ctx ctx, int dir, tdvp_dtype dtype, int chil, int chir, int d, int wl, int wr,
+                  const int* q_left, const int* q_right, const int* q_phys, const int* c_left, const int* c_right,
+                  const void* env_in, const void* A, const void* W, void* env_out);
+
 /* Adjoint of env_update (reverse mode; Sec. III A, Fig. environments): for a
  * real loss and gradients in the convention g = dl/dRe z + i dl/dIm z,
  * given out_bar = the gradient of env_out, writes the gradients of the

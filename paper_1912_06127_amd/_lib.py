@@ -101,6 +101,8 @@ SIGNATURES = {
     "apply_heff_noalloc_max_bytes": (C.c_size_t, []),
     "env_update": (_I, [_P, _I, _I, _I, _I, _I, _I, _I, _P, _P, _P, _P]),
     "env_update_adjoint": (_I, [_P, _I, _I, _I, _I, _I, _I, _I] + [_P] * 7),
+    "apply_heff_u1": (_I, [_P, _I, _I, _I, _I, _I, _I, _I, _I, _PI, _PI, _PI, _PI, _PI] + [_P] * 6),
+    "env_update_u1": (_I, [_P, _I, _I, _I, _I, _I, _I, _I, _PI, _PI, _PI, _PI, _PI] + [_P] * 4),
     "apply_heff_adjoint": (_I, [_P, _I, _I, _I, _I, _I, _I, _I, _I] + [_P] * 11),
     "expect": (_I, [_P, _P, _I, _PI, _PD, _PD]),
     "transition_expect": (_I, [_P, _P, _P, _I, _PI, _PD, _PD]),

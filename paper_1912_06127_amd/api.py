@@ -270,6 +270,52 @@ def env_update(ctx: Context, direction: int, env, A, W, out=None) -> torch.Tenso
     return out
 
 
+def _labels(q, n, what):
+    a = np.ascontiguousarray(q, dtype=np.int32)
+    if a.shape != (n,):
+        raise ValueError(f"{what}: expected {n} charge labels")
+    return a
+
+
+def apply_heff_u1(ctx: Context, L, R, theta, W1=None, W2=None, *, q_left, q_right, q_phys, c_left, c_right,
+                  out=None) -> torch.Tensor:
+    """U(1) block-sparse H_eff theta (tensors as for apply_heff; integer charge
+    labels of the bond, physical and outer MPO indices, bond labels sorted)."""
+    nsite = theta.dim() - 2
+    dt = theta.dtype
+    wl, chil = L.shape[0], L.shape[1]
+    wr, chir = R.shape[0], R.shape[1]
+    d = theta.shape[1] if nsite >= 1 else 1
+    wm = W1.shape[1] if nsite == 2 else wl
+    if out is None:
+        out = torch.empty_like(theta)
+    keep = [_labels(q_left, chil, "q_left"), _labels(q_right, chir, "q_right"),
+            _labels(q_phys if nsite else [0], d, "q_phys"), _labels(c_left, wl, "c_left"),
+            _labels(c_right, wr, "c_right")]
+    ptr = lambda t: _dev(t, dt) if t is not None else C.c_void_p()
+    rc = _lib.load().apply_heff_u1(ctx.handle, nsite, _dtype_code(theta), chil, chir, d, wl, wm, wr,
+                                   *[_iptr(k) for k in keep], ptr(L), ptr(W1), ptr(W2), ptr(R), ptr(theta), ptr(out))
+    _check(ctx.handle, rc)
+    return out
+
+
+def env_update_u1(ctx: Context, direction: int, env, A, W, *, q_left, q_right, q_phys, c_left, c_right,
+                  out=None) -> torch.Tensor:
+    """U(1) block-sparse environment update (as env_update, with charge labels)."""
+    dt = A.dtype
+    chil, d, chir = A.shape
+    wl, wr = W.shape[0], W.shape[1]
+    if out is None:
+        shape = (wr, chir, chir) if direction == 1 else (wl, chil, chil)
+        out = torch.empty(shape, dtype=dt, device=A.device)
+    keep = [_labels(q_left, chil, "q_left"), _labels(q_right, chir, "q_right"), _labels(q_phys, d, "q_phys"),
+            _labels(c_left, wl, "c_left"), _labels(c_right, wr, "c_right")]
+    rc = _lib.load().env_update_u1(ctx.handle, direction, _dtype_code(A), chil, chir, d, wl, wr,
+                                   *[_iptr(k) for k in keep], _dev(env, dt), _dev(A, dt), _dev(W, dt), _dev(out, dt))
+    _check(ctx.handle, rc)
+    return out
+
+
 def env_update_adjoint(ctx: Context, direction: int, env, A, W, out_bar, need=("env", "A", "W")) -> dict:
     """Gradients of Re<out_bar, env_update(direction, env, A, W)> with respect to
     env, A and W (the requested entries of "env", "A", "W")."""

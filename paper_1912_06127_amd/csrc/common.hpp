@@ -194,6 +194,26 @@ struct GroupedGemm {
 void grouped_gemm_plan(tdvp_ctx ctx, const std::vector<GemmDesc>& g, bool fp64, int form, GroupedGemm& out);
 void grouped_gemm_run(tdvp_ctx ctx, const GroupedGemm& gg);
 
+// Block-sparse products (U(1) quantum-number blocks).  Every problem is one
+// output block C (g.batch entries: entry z reads A + z A.stride, B + z
+// B.stride and writes C + z strideC) summed over a list of K chunks: chunk c
+// adds the product of A + offA + i strideA and B + offB + i strideB over k in
+// [0, K), for i = 0..count-1 (element offsets).  nchunk = 0: one chunk over
+// g.K.  All problems of one call share the operand layouts (kcontig) and
+// dtypes; C blocks must not overlap.
+struct BlockChunk {
+    int64_t offA = 0, offB = 0, strideA = 0, strideB = 0;
+    int K = 0, count = 1;
+};
+struct BlockGemm {
+    GemmDesc g;
+    int chunk0 = 0, nchunk = 0;
+};
+void block_gemm(tdvp_ctx ctx, const std::vector<BlockGemm>& probs, const std::vector<BlockChunk>& chunks, bool fp64,
+                int form, const char* tag);
+// Fills `bytes` (a multiple of 8) with zero by a kernel (no memset node under graph capture).
+void zero_fill(void* p, size_t bytes, hipStream_t s);
+
 // Sparse local-operator stage.  For every grid point (p, q):
 //   out[n][s'](p, q) = sum_{k,s} M[(n,s'),(k,s)] in[k][s](p, q)
 // with in offset  k*ik + s*is + p*ip + q  and out offset n*on + s'*os + p*op + q.

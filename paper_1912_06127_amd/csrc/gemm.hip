@@ -119,11 +119,34 @@ struct TileSmem {
     T b[2][2][SB];
 };
 
-// One output tile (m0, n0) of batch entry z over k in [kbeg, kend).
+// Accumulators of one output tile: NA planes (3M: P1, P2, P3; 4M: re, im)
+// of TM x TN MFMA tiles per wave.
+template <typename T, int BM, int BN, int WM, int WN, bool M3>
+struct TileAcc {
+    using F = Mfma<T>;
+    static constexpr int TM = BM / (WM * F::MT);
+    static constexpr int TN = BN / (WN * F::MT);
+    static constexpr int NA = M3 ? 3 : 2;
+    typename F::acc_t v[NA][TM][TN];
+    __device__ __forceinline__ void zero() {
+#pragma unroll
+        for (int q = 0; q < NA; ++q)
+#pragma unroll
+            for (int mi = 0; mi < TM; ++mi)
+#pragma unroll
+                for (int ni = 0; ni < TN; ++ni)
+#pragma unroll
+                    for (int e = 0; e < F::NACC; ++e) v[q][mi][ni][e] = T(0);
+    }
+};
+
+// Accumulates the products of output tile (m0, n0) over k in [kbeg, kend)
+// (operands offset by zA, zB elements) into acc.
 // PF: k-tiles the global loads run ahead of the MFMAs (1 or 2).
 template <typename T, int BM, int BN, int BK, int WM, int WN, bool M3, bool AK, bool BKC, int PF>
-__device__ __forceinline__ void gemm_block(const KParams& p, TileSmem<T, BM, BN, BK, AK, BKC>& sm, int m0, int n0,
-                                           int64_t zA, int64_t zB, int64_t zC, int kbeg, int kend) {
+__device__ __forceinline__ void gemm_tile_acc(const KParams& p, TileSmem<T, BM, BN, BK, AK, BKC>& sm, int m0, int n0,
+                                              int64_t zA, int64_t zB, int kbeg, int kend,
+                                              TileAcc<T, BM, BN, WM, WN, M3>& accs) {
     using F = Mfma<T>;
     using acc_t = typename F::acc_t;
     constexpr int NT = 64 * WM * WN;
@@ -207,15 +230,8 @@ __device__ __forceinline__ void gemm_block(const KParams& p, TileSmem<T, BM, BN,
         }
     };
 
-    acc_t acc[NA][TM][TN];
-#pragma unroll
-    for (int q = 0; q < NA; ++q)
-#pragma unroll
-        for (int mi = 0; mi < TM; ++mi)
-#pragma unroll
-            for (int ni = 0; ni < TN; ++ni)
-#pragma unroll
-                for (int v = 0; v < F::NACC; ++v) acc[q][mi][ni][v] = T(0);
+    auto& acc = accs.v;
+    (void)sizeof(acc_t);
 
     const int nk = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
     if (nk > 0) {
@@ -281,7 +297,23 @@ __device__ __forceinline__ void gemm_block(const KParams& p, TileSmem<T, BM, BN,
         body(kt + 1, I1{});
     }
     if (kt < nk) body(kt, I0{});
+}
 
+// Writes the accumulated tile (m0, n0) to C (offset zC), combining the 3M
+// products or taking the 4M real / imaginary planes.
+template <typename T, int BM, int BN, int WM, int WN, bool M3>
+__device__ __forceinline__ void gemm_tile_store(const KParams& p, int m0, int n0, int64_t zC,
+                                                const TileAcc<T, BM, BN, WM, WN, M3>& accs) {
+    using F = Mfma<T>;
+    constexpr int MT = F::MT;
+    constexpr int TM = BM / (WM * MT);
+    constexpr int TN = BN / (WN * MT);
+    const auto& acc = accs.v;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wm = wave / WN;
+    const int wn = wave % WN;
 #pragma unroll
     for (int mi = 0; mi < TM; ++mi) {
 #pragma unroll
@@ -309,6 +341,16 @@ __device__ __forceinline__ void gemm_block(const KParams& p, TileSmem<T, BM, BN,
             }
         }
     }
+}
+
+// One output tile (m0, n0) of batch entry z over k in [kbeg, kend).
+template <typename T, int BM, int BN, int BK, int WM, int WN, bool M3, bool AK, bool BKC, int PF>
+__device__ __forceinline__ void gemm_block(const KParams& p, TileSmem<T, BM, BN, BK, AK, BKC>& sm, int m0, int n0,
+                                           int64_t zA, int64_t zB, int64_t zC, int kbeg, int kend) {
+    TileAcc<T, BM, BN, WM, WN, M3> acc;
+    acc.zero();
+    gemm_tile_acc<T, BM, BN, BK, WM, WN, M3, AK, BKC, PF>(p, sm, m0, n0, zA, zB, kbeg, kend, acc);
+    gemm_tile_store<T, BM, BN, WM, WN, M3>(p, m0, n0, zC, acc);
 }
 
 // Tile t (0 <= t < tiles_m * tiles_n) -> (tm, tn): runs of kGroupM m-tiles
@@ -367,6 +409,61 @@ __global__ void __launch_bounds__(64 * WM * WN) cgemm2_grouped_kernel(const GPro
     const int m0 = tm * BM;
     const int n0 = tn * BN;
     gemm_block<T, BM, BN, BK, WM, WN, M3, AK, BKC, 1>(p, sm, m0, n0, 0, 0, 0, 0, p.K);  // measured faster here
+}
+
+// Block-sparse form: one problem per output block, batched over z and
+// accumulated over its list of K chunks before the single store.
+struct BProblem {
+    KParams p;
+    int64_t tile_begin;
+    int batch, chunk0, nchunk, pad;
+};
+struct BChunkDev {
+    int64_t offA, offB, strideA, strideB;
+    int K, count;
+};
+
+template <typename T, int BM, int BN, int BK, int WM, int WN, bool M3, bool AK, bool BKC>
+__global__ void __launch_bounds__(64 * WM * WN) cgemm2_blocks_kernel(const BProblem* __restrict__ probs, int nprob,
+                                                                     const BChunkDev* __restrict__ chunks,
+                                                                     int64_t total) {
+    __shared__ __align__(16) TileSmem<T, BM, BN, BK, AK, BKC> sm;
+    int64_t t = blockIdx.x;
+    if ((total & 7) == 0) t = (t & 7) * (total >> 3) + (t >> 3);
+    int lo = 0, hi = nprob - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (probs[mid].tile_begin <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    const BProblem& bp = probs[lo];
+    const KParams p = bp.p;
+    const int per = p.tiles_m * p.tiles_n;
+    const int tl = (int)(t - bp.tile_begin);
+    const int z = tl / per;
+    int tm, tn;
+    grouped_tile(tl % per, p.tiles_m, p.tiles_n, tm, tn);
+    const int m0 = tm * BM;
+    const int n0 = tn * BN;
+    const int64_t zA = (int64_t)z * p.A.stride, zB = (int64_t)z * p.B.stride;
+    TileAcc<T, BM, BN, WM, WN, M3> acc;
+    acc.zero();
+    if (bp.nchunk == 0) {
+        gemm_tile_acc<T, BM, BN, BK, WM, WN, M3, AK, BKC, 1>(p, sm, m0, n0, zA, zB, 0, p.K, acc);
+    } else {
+        for (int c = bp.chunk0; c < bp.chunk0 + bp.nchunk; ++c) {
+            const BChunkDev ch = chunks[c];
+            for (int i = 0; i < ch.count; ++i)
+                gemm_tile_acc<T, BM, BN, BK, WM, WN, M3, AK, BKC, 1>(
+                    p, sm, m0, n0, zA + ch.offA + i * ch.strideA, zB + ch.offB + i * ch.strideB, 0, ch.K, acc);
+        }
+    }
+    gemm_tile_store<T, BM, BN, WM, WN, M3>(p, m0, n0, (int64_t)z * p.strideC, acc);
+}
+
+__global__ void zero_fill_kernel(uint2* p, int64_t n8) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n8; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = make_uint2(0u, 0u);
 }
 
 // Sum of split-K partials in a fixed order (deterministic), converted to
@@ -889,6 +986,115 @@ void grouped_gemm_plan(tdvp_ctx ctx, const std::vector<GemmDesc>& g, bool fp64, 
         }
     }
     upload(cfg);
+}
+
+namespace {
+
+template <typename T, int BM, int BN, int BK, int WM, int WN, bool M3>
+void launch_blocks(tdvp_ctx ctx, const BProblem* probs, int nprob, const BChunkDev* chunks, int64_t total, bool ak,
+                   bool bkc, double flops, const char* tag) {
+    char name[80];
+    snprintf(name, sizeof(name), "cgemm2_blocks_%s_%s_%s_%dx%dx%d", tag, sizeof(T) == 4 ? "f32" : "f64",
+             M3 ? "3m" : "4m", BM, BN, BK);
+    ProfScope prof(ctx, name, flops, 0.0);
+    const dim3 grid((unsigned)total), blk(64 * WM * WN);
+    if (ak && !bkc)
+        hipLaunchKernelGGL((cgemm2_blocks_kernel<T, BM, BN, BK, WM, WN, M3, true, false>), grid, blk, 0, ctx->stream,
+                           probs, nprob, chunks, total);
+    else if (ak && bkc)
+        hipLaunchKernelGGL((cgemm2_blocks_kernel<T, BM, BN, BK, WM, WN, M3, true, true>), grid, blk, 0, ctx->stream,
+                           probs, nprob, chunks, total);
+    else if (!ak && !bkc)
+        hipLaunchKernelGGL((cgemm2_blocks_kernel<T, BM, BN, BK, WM, WN, M3, false, false>), grid, blk, 0, ctx->stream,
+                           probs, nprob, chunks, total);
+    else
+        hipLaunchKernelGGL((cgemm2_blocks_kernel<T, BM, BN, BK, WM, WN, M3, false, true>), grid, blk, 0, ctx->stream,
+                           probs, nprob, chunks, total);
+    TDVP_CHECK_HIP(hipGetLastError());
+}
+
+}  // namespace
+
+void zero_fill(void* p, size_t bytes, hipStream_t s) {
+    if (bytes == 0) return;
+    TDVP_REQUIRE(bytes % 8 == 0 && ((uintptr_t)p & 7) == 0, TDVP_E_ARG, "zero_fill: 8-byte granules only");
+    const int64_t n8 = (int64_t)(bytes / 8);
+    const unsigned blocks = (unsigned)std::min<int64_t>((n8 + 255) / 256, 8192);
+    hipLaunchKernelGGL(zero_fill_kernel, dim3(blocks), dim3(256), 0, s, static_cast<uint2*>(p), n8);
+    TDVP_CHECK_HIP(hipGetLastError());
+}
+
+void block_gemm(tdvp_ctx ctx, const std::vector<BlockGemm>& probs, const std::vector<BlockChunk>& chunks, bool fp64,
+                int form, const char* tag) {
+    if (probs.empty()) return;
+    const bool m3 = fp64 ? false : form == 3;
+    std::vector<BProblem> hp;
+    hp.reserve(probs.size());
+    int64_t total = 0;
+    double flops = 0.0;
+    int maxmn = 0;
+    const bool ak = probs[0].g.A.kcontig, bkc = probs[0].g.B.kcontig;
+    for (const auto& q : probs) {
+        const GemmDesc& d = q.g;
+        TDVP_REQUIRE(d.A.kcontig == ak && d.B.kcontig == bkc, TDVP_E_ARG, "block gemm: mixed operand layouts");
+        TDVP_REQUIRE(d.M >= 0 && d.N >= 0 && d.K >= 0 && d.batch >= 1, TDVP_E_SHAPE, "block gemm: bad sizes");
+        if (d.M == 0 || d.N == 0) continue;
+        TDVP_REQUIRE(q.chunk0 >= 0 && q.nchunk >= 0 && q.chunk0 + q.nchunk <= (int)chunks.size(), TDVP_E_ARG,
+                     "block gemm: chunk range out of bounds");
+        maxmn = std::max(maxmn, std::max(d.M, d.N));
+        BProblem b{};
+        b.p.M = d.M;
+        b.p.N = d.N;
+        b.p.K = d.K;
+        b.p.A = to_k(d.A);
+        b.p.B = to_k(d.B);
+        b.p.C = d.C;
+        b.p.c128C = d.cdt == Dt::C128;
+        b.p.ldc = d.ldc;
+        b.p.strideC = d.strideC;
+        b.p.ksplit = 1;
+        b.p.kchunk = d.K;
+        b.batch = d.batch;
+        b.chunk0 = q.chunk0;
+        b.nchunk = q.nchunk;
+        double kk = q.nchunk == 0 ? (double)d.K : 0.0;
+        for (int c = q.chunk0; c < q.chunk0 + q.nchunk; ++c) kk += (double)chunks[c].K * chunks[c].count;
+        flops += 8.0 * d.M * (double)d.N * kk * d.batch;
+        hp.push_back(b);
+    }
+    if (hp.empty()) return;
+    const bool small = maxmn <= 32;
+    const int BM = small ? 32 : 64, BN = 64;
+    for (auto& b : hp) {
+        b.p.tiles_m = (b.p.M + BM - 1) / BM;
+        b.p.tiles_n = (b.p.N + BN - 1) / BN;
+        b.tile_begin = total;
+        total += (int64_t)b.p.tiles_m * b.p.tiles_n * b.batch;
+    }
+    TDVP_REQUIRE(total <= 0x7fffffff, TDVP_E_SHAPE, "block gemm: too many tiles");
+    std::vector<BChunkDev> hc(chunks.size());
+    for (size_t c = 0; c < chunks.size(); ++c)
+        hc[c] = BChunkDev{chunks[c].offA, chunks[c].offB, chunks[c].strideA, chunks[c].strideB, chunks[c].K,
+                          chunks[c].count};
+    const std::string key = std::string("blk_") + tag;
+    auto* dp = static_cast<BProblem*>(ctx->workspace(key + "_p", sizeof(BProblem) * hp.size()));
+    auto* dc = static_cast<BChunkDev*>(ctx->workspace(key + "_c", sizeof(BChunkDev) * std::max<size_t>(1, hc.size())));
+    TDVP_CHECK_HIP(hipMemcpyAsync(dp, hp.data(), sizeof(BProblem) * hp.size(), hipMemcpyHostToDevice, ctx->stream));
+    if (!hc.empty())
+        TDVP_CHECK_HIP(hipMemcpyAsync(dc, hc.data(), sizeof(BChunkDev) * hc.size(), hipMemcpyHostToDevice, ctx->stream));
+    const int n = (int)hp.size();
+    if (fp64) {
+        if (small) launch_blocks<double, 32, 64, 8, 1, 2, false>(ctx, dp, n, dc, total, ak, bkc, flops, tag);
+        else launch_blocks<double, 64, 64, 8, 2, 2, false>(ctx, dp, n, dc, total, ak, bkc, flops, tag);
+    } else if (m3) {
+        if (small) launch_blocks<float, 32, 64, 16, 1, 2, true>(ctx, dp, n, dc, total, ak, bkc, flops, tag);
+        else launch_blocks<float, 64, 64, 16, 2, 2, true>(ctx, dp, n, dc, total, ak, bkc, flops, tag);
+    } else {
+        if (small) launch_blocks<float, 32, 64, 16, 1, 2, false>(ctx, dp, n, dc, total, ak, bkc, flops, tag);
+        else launch_blocks<float, 64, 64, 16, 2, 2, false>(ctx, dp, n, dc, total, ak, bkc, flops, tag);
+    }
+    // the host tables above are read by the copies queued on the stream
+    TDVP_CHECK_HIP(hipStreamSynchronize(ctx->stream));
 }
 
 void grouped_gemm_run(tdvp_ctx ctx, const GroupedGemm& gg) {

@@ -120,3 +120,17 @@ def heff_micro_inputs(D: int, w: int = 10, d: int = 2):
     Rk = hermitian_stack(HEFF_MICRO["seed_R"] + D, w, D)
     theta = unit_vector(HEFF_MICRO["seed_theta"] + D, (D, d, d, D))
     return Lk, Rk, theta
+
+
+def u1_labels(chi: int, centre: int, spread: float, seed: int):
+    """Sorted integer charge labels of a bond of dimension chi: sector sizes
+    drawn around `centre` with a Gaussian profile of width `spread` (the shape
+    of the S^z sector distribution of a half chain), every label at least
+    once in [centre - 3 spread, centre + 3 spread] when chi allows."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    qs = np.arange(int(np.floor(centre - 3 * spread)), int(np.ceil(centre + 3 * spread)) + 1)
+    wgt = np.exp(-0.5 * ((qs - centre) / max(spread, 1e-9)) ** 2)
+    wgt = wgt / wgt.sum()
+    labels = rng.choice(qs, size=chi, p=wgt)
+    return np.sort(labels)
