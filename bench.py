@@ -456,6 +456,60 @@ def gradient_timing(pkg, ctx, torch, np, steps=2):
     return res
 
 
+def u1_timing(pkg, ctx, torch, np, chi=512, K=6, reps=10):
+    """Two-site H_eff at the N = 64 quench's bond cap (chi = 512 on both bonds,
+    XXX with K = 6 exponentials, w = 20) on charge-symmetric inputs: the dense
+    path against the U(1) block-sparse path (half-chain S^z sector profiles),
+    complex64.  Dense: HIP-event time per call; blocked: kernel time per call
+    from the library's profiler and wall time per call (the block tables are
+    built on the host each call)."""
+    import workloads as wl
+    sp = np.array([[0, 1], [0, 0]], dtype=np.complex128)
+    sm = sp.T.copy()
+    sz = np.diag([1.0, -1.0]).astype(np.complex128)
+    pairs = [(0.5, sp, sm), (0.5, sm, sp), (0.25, sz, sz)]
+    c, lam, _ = pkg.fit.fit_power_law(2.0, K, 63)
+    mpo = pkg.MPO.longrange(ctx, 6, pairs, c=c, lam=lam)
+    W = mpo.tensor(2)
+    mpo.close()
+    cw = [0] + [1] * K + [-1] * K + [0] * K + [0]
+    ql, qr, qs = wl.u1_labels(chi, 16, 2.5, 31), wl.u1_labels(chi, 17, 2.5, 32), [1, 0]
+    pat = wl.u1_patterns(ql, qr, qs, cw)
+    to = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to("cuda", torch.complex64)
+    L, R = to(wl.u1_symmetric(41, pat["L"])), to(wl.u1_symmetric(42, pat["R"]))
+    th, Wd = to(wl.u1_symmetric(43, pat["two_site"])), to(W)
+    out = torch.empty_like(th)
+    kw = dict(q_left=ql, q_right=qr, q_phys=qs, c_left=cw, c_right=cw, out=out)
+    for _ in range(2):
+        pkg.apply_heff(ctx, L, R, th, Wd, Wd, out=out)
+        pkg.apply_heff_u1(ctx, L, R, th, Wd, Wd, **kw)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(ctx.stream)
+    for _ in range(reps):
+        pkg.apply_heff(ctx, L, R, th, Wd, Wd, out=out)
+    e1.record(ctx.stream)
+    torch.cuda.synchronize()
+    dense_ms = e0.elapsed_time(e1) / reps
+    ctx.profile(True)
+    ctx.profile_read()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        pkg.apply_heff_u1(ctx, L, R, th, Wd, Wd, **kw)
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - t0) * 1e3 / reps
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    kern_ms = sum(v["ms"] for v in prof.values()) / reps
+    block_flops = sum(v["flops"] for k, v in prof.items() if k.startswith("cgemm2_blocks")) / reps
+    nsec = len(set(int(q) for q in ql))
+    return {"dense_ms": round(dense_ms, 3), "u1_kernel_ms": round(kern_ms, 3), "u1_wall_ms": round(wall_ms, 3),
+            "speedup_kernel": round(dense_ms / kern_ms, 2), "speedup_wall": round(dense_ms / wall_ms, 2),
+            "dense_flops": heff2_flops(chi, 20), "block_gemm_flops": block_flops, "sectors_left": nsec,
+            "workload": f"two-site H_eff, chi={chi} both bonds, XXX K={K} (w=20), complex64, S^z sectors "
+                        f"(Gaussian profile, spread 2.5), dense path vs U(1) blocks"}
+
+
 def copy_calibration(torch, gib=1):
     """Plain device copy of known size, used to scale HBM byte counters."""
     n = gib * (1 << 30) // 4
@@ -490,6 +544,7 @@ def main():
     ap.add_argument("--only-sweep", action="store_true",
                     help="run only the N=64 2TDVP quench sweep and print its timings (for profiling)")
     ap.add_argument("--grad-steps", type=int, default=2)
+    ap.add_argument("--only-u1", action="store_true", help="run only the U(1) block-sparse H_eff timing")
     ap.add_argument("--only-grad", action="store_true",
                     help="run only the differentiable 1TDVP workload (--grad-steps steps) and print its timings")
     args = ap.parse_args()
@@ -510,6 +565,12 @@ def main():
     if args.only_sweep:
         ctx = pkg.Context(0)
         print(json.dumps({"sweep": sweep_timing(pkg, ctx, args.sweep_steps, taylor=not args.sweep_no_taylor)}))
+        ctx.close()
+        return
+
+    if args.only_u1:
+        ctx = pkg.Context(0)
+        print(json.dumps({"u1": u1_timing(pkg, ctx, torch, np)}))
         ctx.close()
         return
 
@@ -613,6 +674,8 @@ def main():
         if not args.no_segments:
             progress("segment-parallel step (N=201, 32 segments)")
             line["segments"] = segments_timing(pkg, ctx, np)
+        progress("U(1) block-sparse H_eff at chi = 512")
+        line["u1"] = u1_timing(pkg, ctx, torch, np)
         if args.grad_steps > 0:
             progress("differentiable 1TDVP timing")
             line["gradient"] = gradient_timing(pkg, ctx, torch, np, args.grad_steps)

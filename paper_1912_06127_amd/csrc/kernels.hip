@@ -917,25 +917,28 @@ __global__ void mop_dense_kernel(int kind, const void* W1, int w1_128, const voi
     M[idx] = make_double2(re, im);
 }
 
-// Compress the dense operator to CSR (exact zeros dropped).  One block.
+// Dense operator -> CSR (exact zeros dropped), one block: row counts and
+// their prefix sum in LDS, then the column indices and values per row.
 __global__ void mop_csr_kernel(const double2* M, int rows, int cols, int* row_ptr, int* col,
                                void* val, int val128) {
+    extern __shared__ int cnt[];  // rows + 1
     for (int r = threadIdx.x; r < rows; r += blockDim.x) {
         int c = 0;
         for (int j = 0; j < cols; ++j) {
             const double2 v = M[(int64_t)r * cols + j];
             c += (v.x != 0.0 || v.y != 0.0);
         }
-        row_ptr[r + 1] = c;
+        cnt[r + 1] = c;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        row_ptr[0] = 0;
-        for (int r = 0; r < rows; ++r) row_ptr[r + 1] += row_ptr[r];
+        cnt[0] = 0;
+        for (int r = 0; r < rows; ++r) cnt[r + 1] += cnt[r];
     }
     __syncthreads();
+    for (int r = threadIdx.x; r <= rows; r += blockDim.x) row_ptr[r] = cnt[r];
     for (int r = threadIdx.x; r < rows; r += blockDim.x) {
-        int e = row_ptr[r];
+        int e = cnt[r];
         for (int j = 0; j < cols; ++j) {
             const double2 v = M[(int64_t)r * cols + j];
             if (v.x != 0.0 || v.y != 0.0) {
@@ -1252,11 +1255,12 @@ void mop_build(int kind, const void* W1, Dt w1dt, const void* W2, Dt w2dt, int w
                bool val_fp64, hipStream_t s) {
     const int tot = rows * cols;
     if (tot == 0) return;
+    TDVP_REQUIRE((size_t)(rows + 1) * sizeof(int) <= 64 * 1024, TDVP_E_SHAPE, "MPO stage operator: too many rows");
     hipLaunchKernelGGL(mop_dense_kernel, dim3((tot + 255) / 256), dim3(256), 0, s, kind, W1,
                        (int)(w1dt == Dt::C128), W2, (int)(w2dt == Dt::C128), wl, wm, wr, d, rows,
                        cols, dense);
-    hipLaunchKernelGGL(mop_csr_kernel, dim3(1), dim3(256), 0, s, dense, rows, cols, row_ptr, col,
-                       val, (int)val_fp64);
+    hipLaunchKernelGGL(mop_csr_kernel, dim3(1), dim3(256), sizeof(int) * (rows + 1), s, dense, rows, cols, row_ptr,
+                       col, val, (int)val_fp64);
     TDVP_CHECK_HIP(hipGetLastError());
 }
 

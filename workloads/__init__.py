@@ -134,3 +134,24 @@ def u1_labels(chi: int, centre: int, spread: float, seed: int):
     wgt = wgt / wgt.sum()
     labels = rng.choice(qs, size=chi, p=wgt)
     return np.sort(labels)
+
+
+def u1_symmetric(seed: int, mask):
+    """Complex Gaussian entries where the boolean `mask` (a charge-selection
+    pattern) is set, zeros elsewhere."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    return np.where(mask, cgauss(rng, mask.shape), 0.0)
+
+
+def u1_patterns(ql, qr, qs, cw):
+    """Charge-selection patterns (integer labels; see u1_labels): site / local
+    state T[a][s][b] with q(a) + q(s) = q(b), two-site T[a][s1][s2][b], and the
+    environments L[k][a'][a] (q(a') - q(a) = c(k)) and R[l][b][b'] (q(b') - q(b) = c(l))."""
+    import numpy as np
+    ql, qr, qs, cw = (np.asarray(x) for x in (ql, qr, qs, cw))
+    site = (ql[:, None, None] + qs[None, :, None]) == qr[None, None, :]
+    two = (ql[:, None, None, None] + qs[None, :, None, None] + qs[None, None, :, None]) == qr[None, None, None, :]
+    envL = (ql[None, :, None] - ql[None, None, :]) == cw[:, None, None]
+    envR = (qr[None, None, :] - qr[None, :, None]) == cw[:, None, None]
+    return {"site": site, "two_site": two, "L": envL, "R": envR}
