@@ -71,6 +71,7 @@ constexpr size_t wstage_op_bytes() {
 // for several blocks per CU, so many loads are in flight.
 constexpr int kWSub = 4;
 constexpr int kWPts = 64;
+constexpr int kWRowsInFlight = 16;  // input rows per wave loaded back to back (nin <= 64)
 constexpr int kWThreads = kWSub * kWPts;
 
 template <typename T>
@@ -81,12 +82,30 @@ __device__ __forceinline__ void wstage_tile(const WParams& w, int p, int q0, typ
     const int q = q0 + lane;
     const bool live = q < w.Q;
     const int64_t pin = (int64_t)p * w.ip + q;
+    if (w.nin <= kWSub * kWRowsInFlight) {
+        // every input row of this wave loaded before any is stored: all the
+        // wave's loads are in flight together
+        C buf[kWRowsInFlight];
+#pragma unroll
+        for (int i = 0; i < kWRowsInFlight; ++i) {
+            const int c = sub + kWSub * i;
+            T re = 0, im = 0;
+            if (live && c < w.nin) ld<T>(w.in, w.in128, pin + (c / w.D) * w.ik + (c % w.D) * w.is, re, im);
+            buf[i] = C{re, im};
+        }
+#pragma unroll
+        for (int i = 0; i < kWRowsInFlight; ++i) {
+            const int c = sub + kWSub * i;
+            if (c < w.nin) xin[c * kWPts + lane] = buf[i];
+        }
+    } else {
 #pragma unroll 4
-    for (int c = sub; c < w.nin; c += kWSub) {
-        const int k = c / w.D, s = c % w.D;
-        T re = 0, im = 0;
-        if (live) ld<T>(w.in, w.in128, pin + k * w.ik + s * w.is, re, im);
-        xin[c * kWPts + lane] = C{re, im};
+        for (int c = sub; c < w.nin; c += kWSub) {
+            const int k = c / w.D, s = c % w.D;
+            T re = 0, im = 0;
+            if (live) ld<T>(w.in, w.in128, pin + k * w.ik + s * w.is, re, im);
+            xin[c * kWPts + lane] = C{re, im};
+        }
     }
     __syncthreads();
     if (!live) return;  // no barrier below
