@@ -545,6 +545,8 @@ def main():
                     help="run only the N=64 2TDVP quench sweep and print its timings (for profiling)")
     ap.add_argument("--grad-steps", type=int, default=2)
     ap.add_argument("--only-u1", action="store_true", help="run only the U(1) block-sparse H_eff timing")
+    ap.add_argument("--only-D", type=int, default=0,
+                    help="run only the two-site H_eff timing at this bond dimension (both precisions; for profiling)")
     ap.add_argument("--only-grad", action="store_true",
                     help="run only the differentiable 1TDVP workload (--grad-steps steps) and print its timings")
     args = ap.parse_args()
@@ -577,6 +579,19 @@ def main():
     if args.only_grad:
         ctx = pkg.Context(0)
         print(json.dumps({"gradient": gradient_timing(pkg, ctx, torch, np, args.grad_steps)}))
+        ctx.close()
+        return
+
+    if args.only_D:
+        ctx = pkg.Context(0)
+        W = xy_bulk_tensor(pkg, ctx)
+        r = {}
+        for name, dt in (("c64", torch.complex64), ("c128", torch.complex128)):
+            xs = device_inputs(torch, wl, W, args.only_D, 10, dt)
+            msx, _, _ = time_heff(pkg, ctx, torch, xs, args.steps, args.warmup)
+            r[name] = {"gflops": round(heff2_flops(args.only_D, 10) / (msx * 1e-3) * 1e-9, 1), "ms": round(msx, 5)}
+            del xs
+        print(json.dumps({"heff_D": args.only_D, **r}))
         ctx.close()
         return
 

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 #include <rocblas/rocblas.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <cstdint>
 #include <cstring>
@@ -126,6 +127,16 @@ struct ProfScope {
     size_t idx = (size_t)-1;
     ProfScope(tdvp_ctx c, const char* name, double flops, double bytes);
     ~ProfScope();
+};
+
+// Named range of the calling thread on the ROC-TX marker stream (shown by a
+// marker trace, e.g. rocprofv3 --marker-trace); without a tool attached the
+// push and pop return at once.
+struct TxRange {
+    explicit TxRange(const char* name) { roctxRangePushA(name); }
+    ~TxRange() { roctxRangePop(); }
+    TxRange(const TxRange&) = delete;
+    TxRange& operator=(const TxRange&) = delete;
 };
 
 // RAII device allocation through the context allocator.

@@ -321,7 +321,10 @@ int apply_heff(tdvp_ctx ctx, int nsite, tdvp_dtype dtype, int chil, int chir, in
                int wr, const void* L, const void* W1, const void* W2, const void* R,
                const void* theta, void* out) {
     if (!ctx) return TDVP_E_ARG;
-    return guarded(ctx, [&] { heff_raw_call(ctx, nsite, dtype, chil, chir, d, wl, wm, wr, L, W1, W2, R, theta, out); });
+    return guarded(ctx, [&] {
+        TxRange tx("apply_heff");
+        heff_raw_call(ctx, nsite, dtype, chil, chir, d, wl, wm, wr, L, W1, W2, R, theta, out);
+    });
 }
 
 int apply_heff_batched(tdvp_ctx ctx, tdvp_dtype dtype, int n, const tdvp_heff_desc* descs) {
@@ -408,6 +411,7 @@ int env_update(tdvp_ctx ctx, int dir, tdvp_dtype dtype, int chil, int chir, int 
                const void* env_in, const void* A, const void* W, void* env_out) {
     if (!ctx) return TDVP_E_ARG;
     return guarded(ctx, [&] {
+        TxRange tx("env_update");
         const Dt dt = to_dt(dtype);
         TDVP_REQUIRE(dir == 1 || dir == -1, TDVP_E_ARG, "env_update: dir must be +1 or -1");
         TDVP_REQUIRE(chil >= 1 && chir >= 1 && d >= 1 && wl >= 1 && wr >= 1, TDVP_E_SHAPE,

@@ -887,13 +887,11 @@ __global__ void apply_site_kernel(double2* A, const double2* O, int chil, int d,
 }
 
 // --------------------------------------------- MPO stage operator (device)
-// Dense operator M[row][col] of the sparse MPO stage, built in FP64 from the
-// device MPO tensors (kind as in MopKind).
-__global__ void mop_dense_kernel(int kind, const void* W1, int w1_128, const void* W2, int w2_128,
-                                 int wl, int wm, int wr, int d, int rows, int cols, double2* M) {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= rows * cols) return;
-    const int row = idx / cols, col = idx % cols;
+// Entry M[row][col] of the dense operator of the sparse MPO stage, in FP64,
+// from the MPO tensors (kind as in MopKind).  W1/W2 are either the device
+// tensors (w1_128/w2_128 give their precision) or complex128 copies in LDS.
+__device__ __forceinline__ double2 mop_entry(int kind, const void* W1, int w1_128, const void* W2, int w2_128,
+                                             int wm, int wr, int d, int row, int col) {
     double re = 0.0, im = 0.0;
     if (kind == 0) {  // zero-site: identity on the MPO bond
         re = (row == col) ? 1.0 : 0.0;
@@ -933,7 +931,86 @@ __global__ void mop_dense_kernel(int kind, const void* W1, int w1_128, const voi
             im += ar * bi + ai * br;
         }
     }
-    M[idx] = make_double2(re, im);
+    return make_double2(re, im);
+}
+
+__global__ void mop_dense_kernel(int kind, const void* W1, int w1_128, const void* W2, int w2_128,
+                                 int wm, int wr, int d, int rows, int cols, double2* M) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= rows * cols) return;
+    M[idx] = mop_entry(kind, W1, w1_128, W2, w2_128, wm, wr, d, idx / cols, idx % cols);
+}
+
+// The whole operator build in one block when it is small (the common case):
+// the MPO tensors are copied to LDS in complex128, every thread computes up
+// to kMopPerThread entries (kept in registers) and marks the non-zeros in an
+// LDS bit mask, the row counts and their prefix sum follow from the mask,
+// and each thread writes its non-zeros at their rank within the row, so the
+// column order inside a row is ascending as in the two-kernel path.
+constexpr int kMopThreads = 1024;
+constexpr int kMopPerThread = 8;
+constexpr int kMopMaxEntries = kMopThreads * kMopPerThread;
+constexpr int kMopMaxRows = 2048;
+constexpr int kMopLdsW = 2560;  // complex128 MPO entries staged (40 KiB)
+
+// number of set bits of the LDS bit mask in positions [a, b)
+__device__ __forceinline__ int mask_count(const unsigned* mask, int a, int b) {
+    int c = 0;
+    while (a < b) {
+        const int w = a >> 5, lo = a & 31;
+        const int hi = min(32, lo + (b - a));  // bits [lo, hi) of word w
+        const unsigned m = (hi == 32 ? ~0u : ((1u << hi) - 1u)) & ~((1u << lo) - 1u);
+        c += __popc(mask[w] & m);
+        a += hi - lo;
+    }
+    return c;
+}
+
+__global__ void __launch_bounds__(kMopThreads) mop_fused_kernel(int kind, const void* W1, int w1_128, int n1,
+                                                                const void* W2, int w2_128, int n2, int wm, int wr,
+                                                                int d, int rows, int cols, int* row_ptr, int* col,
+                                                                void* val, int val128) {
+    __shared__ double2 sw[kMopLdsW];
+    __shared__ unsigned mask[kMopMaxEntries / 32];
+    __shared__ int cnt[kMopMaxRows + 1];
+    const int tid = threadIdx.x, tot = rows * cols;
+    for (int i = tid; i < n1 + n2; i += kMopThreads) {
+        double re, im;
+        if (i < n1) ld<double>(W1, w1_128, i, re, im);
+        else ld<double>(W2, w2_128, i - n1, re, im);
+        sw[i] = make_double2(re, im);
+    }
+    for (int i = tid; i < kMopMaxEntries / 32; i += kMopThreads) mask[i] = 0u;
+    __syncthreads();
+    double2 v[kMopPerThread];
+#pragma unroll
+    for (int t = 0; t < kMopPerThread; ++t) {
+        const int idx = tid + t * kMopThreads;
+        v[t] = make_double2(0.0, 0.0);
+        if (idx < tot) {
+            v[t] = mop_entry(kind, sw, 1, sw + n1, 1, wm, wr, d, idx / cols, idx % cols);
+            if (v[t].x != 0.0 || v[t].y != 0.0) atomicOr(&mask[idx >> 5], 1u << (idx & 31));
+        }
+    }
+    __syncthreads();
+    // row counts from the mask (rows may straddle 32-bit words)
+    for (int r = tid; r < rows; r += kMopThreads) cnt[r + 1] = mask_count(mask, r * cols, (r + 1) * cols);
+    __syncthreads();
+    if (tid == 0) {
+        cnt[0] = 0;
+        for (int r = 0; r < rows; ++r) cnt[r + 1] += cnt[r];
+    }
+    __syncthreads();
+    for (int r = tid; r <= rows; r += kMopThreads) row_ptr[r] = cnt[r];
+#pragma unroll
+    for (int t = 0; t < kMopPerThread; ++t) {
+        const int idx = tid + t * kMopThreads;
+        if (idx >= tot || !((mask[idx >> 5] >> (idx & 31)) & 1u)) continue;
+        const int r = idx / cols, c0 = r * cols;
+        const int e = cnt[r] + mask_count(mask, c0, idx);
+        col[e] = idx - c0;
+        st<double>(val, val128, e, v[t].x, v[t].y);
+    }
 }
 
 // Dense operator -> CSR (exact zeros dropped), one block: row counts and
@@ -1274,9 +1351,19 @@ void mop_build(int kind, const void* W1, Dt w1dt, const void* W2, Dt w2dt, int w
                bool val_fp64, hipStream_t s) {
     const int tot = rows * cols;
     if (tot == 0) return;
+    // element counts of the tensors the entries read (kinds 0, 1, 3, 4 read W1 only)
+    const int n1 = kind == 0 ? 0 : (kind == 2 || kind == 5 || kind == 6) ? wl * wm * d * d : wl * wr * d * d;
+    const int n2 = (kind == 2 || kind == 5 || kind == 6) ? wm * wr * d * d : 0;
+    if (tot <= kMopMaxEntries && rows <= kMopMaxRows && n1 + n2 <= kMopLdsW) {
+        hipLaunchKernelGGL(mop_fused_kernel, dim3(1), dim3(kMopThreads), 0, s, kind, W1, (int)(w1dt == Dt::C128), n1,
+                           W2, (int)(w2dt == Dt::C128), n2, wm, wr, d, rows, cols, row_ptr, col, val,
+                           (int)val_fp64);
+        TDVP_CHECK_HIP(hipGetLastError());
+        return;
+    }
     TDVP_REQUIRE((size_t)(rows + 1) * sizeof(int) <= 64 * 1024, TDVP_E_SHAPE, "MPO stage operator: too many rows");
     hipLaunchKernelGGL(mop_dense_kernel, dim3((tot + 255) / 256), dim3(256), 0, s, kind, W1,
-                       (int)(w1dt == Dt::C128), W2, (int)(w2dt == Dt::C128), wl, wm, wr, d, rows,
+                       (int)(w1dt == Dt::C128), W2, (int)(w2dt == Dt::C128), wm, wr, d, rows,
                        cols, dense);
     hipLaunchKernelGGL(mop_csr_kernel, dim3(1), dim3(256), sizeof(int) * (rows + 1), s, dense, rows, cols, row_ptr,
                        col, val, (int)val_fp64);

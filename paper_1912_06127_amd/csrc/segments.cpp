@@ -675,6 +675,7 @@ struct SegRun {
         }
         if (P.gen != ctx->ws_gen) build_plan(P, ph, pair);
         {
+            TxRange tx("seg_phase_expm");
             ProfScope ps(ctx, o.use_graph ? "seg_batched_expm_graph" : "seg_batched_expm",
                          P.flops_per_matvec * o.krylov_k, 0.0);
             exec_batched(P, pair, tau);
@@ -685,6 +686,7 @@ struct SegRun {
         if (pair) {
             const double2* theta =
                 static_cast<const double2*>(ctx->workspace("segb_theta", sizeof(double2) * (size_t)P.L.total));
+            TxRange tx("seg_phase_splits");
             ProfScope ps(ctx, "seg_splits", 0.0, 0.0);
             split_concurrent(ph, theta, P.L.off);
         }
@@ -736,6 +738,7 @@ struct SegRun {
         for (int l = 0; l < nl; ++l) {
             pool.emplace_back([&, l] {
                 try {
+                    TxRange tx("seg_lane");
                     SegLane& L = *sg->lanes[l];
                     TDVP_CHECK_HIP(hipSetDevice(L.c.device));
                     TDVP_CHECK_HIP(hipStreamWaitEvent(L.c.stream, sg->ready, 0));
@@ -791,6 +794,7 @@ struct SegRun {
     // The bond steps of a phase (one per segment at most, on disjoint
     // tensors and environments), concurrently on the split lanes.
     void bonds_concurrent(const SPhase& ph) {
+        TxRange tx("seg_phase_bonds");
         const int n = (int)ph.size();
         const int nl = std::min(lane_count(), n);
         if (nl <= 1) {
@@ -865,6 +869,7 @@ struct SegRun {
     }
 
     void step(double dt) {
+        TxRange tx("seg_step");
         reset_flag(ctx, sg->flag.as<int>());
         const auto t0 = std::chrono::steady_clock::now();
         int done = 0;  // phases run so far (o.max_phases > 0 stops the step early)
@@ -1111,6 +1116,7 @@ int seg_init(tdvp_ctx ctx, tdvp_mpo mpo, int N, int d, const int* chi, const voi
     if (!ctx || !out) return TDVP_E_ARG;
     *out = nullptr;
     return guarded(ctx, [&] {
+        TxRange tx("seg_init");
         TDVP_REQUIRE(mpo && chi && tensors && seg_sizes, TDVP_E_ARG, "seg_init: null argument");
         TDVP_REQUIRE(N >= 4 && d >= 1, TDVP_E_SHAPE, "seg_init: need N >= 4 sites");
         TDVP_REQUIRE(mpo->N == N && mpo->d == d, TDVP_E_SHAPE, "seg_init: MPO size differs from the state");
@@ -1222,6 +1228,7 @@ int seg_get_bond(tdvp_seg sg, int j, double* out) {
 int seg_norm2(tdvp_ctx ctx, tdvp_seg sg, double* out) {
     if (!ctx || !sg) return TDVP_E_ARG;
     return guarded(ctx, [&] {
+        TxRange tx("seg_norm2");
         TDVP_REQUIRE(out, TDVP_E_ARG, "seg_norm2: null argument");
         TDVP_REQUIRE(sg->ctx == ctx, TDVP_E_ARG, "seg_norm2: state belongs to another context");
         *out = state_norm2(ctx, sg);
@@ -1231,6 +1238,7 @@ int seg_norm2(tdvp_ctx ctx, tdvp_seg sg, double* out) {
 int seg_reorthonormalize(tdvp_ctx ctx, tdvp_seg sg, tdvp_mpo mpo) {
     if (!ctx || !sg) return TDVP_E_ARG;
     return guarded(ctx, [&] {
+        TxRange tx("seg_reorthonormalize");
         TDVP_REQUIRE(sg->ctx == ctx, TDVP_E_ARG, "seg_reorthonormalize: state belongs to another context");
         TDVP_REQUIRE(mpo && mpo->N == sg->N && mpo->d == sg->d, TDVP_E_SHAPE,
                      "seg_reorthonormalize: MPO does not match");

@@ -118,6 +118,7 @@ struct Stepper {
 
     // theta <- exp(-i tau H) theta for the local operator described by a.
     void evolve(const HeffArgs& a, double2* theta, double tau) {
+        TxRange tx("expm");
         const int D = a.nsite == 0 ? 1 : (a.nsite == 1 ? m->d : m->d * m->d);
         const int64_t n = (int64_t)a.chil * D * a.chir;
         const double f = heff_flops(a.nsite, a.chil, a.chir, m->d, a.wl, a.wr);
@@ -177,6 +178,7 @@ struct Stepper {
 
     // ------------------------------------------------------------- 1TDVP
     void step1(double dt) {
+        TxRange tx("tdvp1_step");
         const int N = m->N, d = m->d;
         const double tau = dt / 2.0;
         ensure_envs();
@@ -231,6 +233,7 @@ struct Stepper {
     // Split of theta into sites j, j+1 (Fig. postupdate); centre_left puts the
     // singular values into site j, otherwise into site j+1.
     void split(int j, double2* th, bool centre_left) {
+        TxRange tx("split");
         const int d = m->d;
         const int rows = m->chi[j] * d, cols = d * m->chi[j + 2];
         const bool gram = o.svd_mode == 2 || (o.svd_mode == 0 && o.w_max >= 1e-13);
@@ -275,6 +278,7 @@ struct Stepper {
     }
 
     void step2(double dt) {
+        TxRange tx("tdvp2_step");
         const int N = m->N;
         TDVP_REQUIRE(N >= 2, TDVP_E_SHAPE, "tdvp2_step needs at least two sites");
         const double tau = dt / 2.0;
