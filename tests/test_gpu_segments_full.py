@@ -4,12 +4,71 @@ complex64 matvecs), checked through properties that hold at any size: the
 one-site step keeps every bond dimension, a two-site step is refused until
 the repair, and the repair brings the norm back to one without changing a
 bond dimension (Sec. III D, Fig. reorth)."""
+import json
+import os
+
 import numpy as np
 import pytest
 
 import workloads as wl
 
 pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "segments_n201_phase0.json")
+
+
+def _golden():
+    if not os.path.exists(GOLDEN):  # the oracle run that writes it takes hours
+        pytest.skip("oracle reference not written yet: python tests/golden/make_segments_n201_phase.py")
+    with open(GOLDEN) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("compute", ["c128", "c64"])
+def test_first_phase_at_full_size_matches_oracle(compute):
+    """The first phase of a segment step at the full N = 201 workload (17
+    departing boundary pairs with bonds up to 1009, w = 14, 8 Lanczos vectors,
+    static shapes) against the oracle's pair updates on the same seeded state
+    (tests/golden/segments_n201_phase0.json, written from the oracle only):
+    every pair's largest and smallest kept Schmidt values and their sum of
+    squares, and the phase's discarded weight (gauge-invariant quantities)."""
+    from oracle import mpo as ompo
+    from oracle import spin
+    import paper_1912_06127_amd as pkg
+    g = _golden()
+    p = wl.XY_N201
+    N, sizes = p["N"], p["segments"]
+    chi = wl.segment_bond_profile(sizes, 2, p["chi_lo"], p["chi_hi"], p["seed_chi"])
+    c = np.array([complex(*z) for z in g["fit_c"]])
+    lam = np.array([complex(*z) for z in g["fit_lam"]])
+    Ws = ompo.mpo_exponentials(N, c, lam, spin.xy_pairs())
+    T = wl.random_site_tensors(p["seed_state"], chi, 2)
+    ctx = pkg.Context(0)
+    try:
+        mpo = pkg.MPO.from_tensors(ctx, Ws)
+        print(f"full-size segments N={N} {compute}: init", flush=True)
+        sg = pkg.Segments.init(ctx, mpo, T, sizes, compute=compute)
+        del T
+        print("first phase", flush=True)
+        st = sg.step(mpo, p["dt"], pkg.SegmentOptions(compute=compute, max_phases=1))
+        assert st["matvecs"] == 8 * len(g["pairs"])
+        rtol = 1e-9 if compute == "c128" else 1e-4
+        for q in g["pairs"]:
+            j = q["j"]
+            s = np.sort(1.0 / sg.bond(j))[::-1]
+            assert len(s) == q["kept"] == chi[j + 1]
+            top, bottom = np.array(q["s_top"]), np.array(q["s_bottom"])
+            e_top = np.max(np.abs(s[:len(top)] - top)) / top[0]
+            e_bot = np.max(np.abs(s[-len(bottom):] - bottom)) / top[0]
+            print(f"  pair ({j}, {j + 1}) {q['chi']}: top {e_top:.1e} bottom {e_bot:.1e}", flush=True)
+            assert e_top <= rtol and e_bot <= rtol, (j, e_top, e_bot)
+            assert abs(np.sum(s ** 2) - q["sum_s2"]) <= rtol * q["sum_s2"]
+        assert abs(st["w_step"] - g["w_phase"]) <= max(rtol * g["w_phase"], 1e-14)
+        sg.close()
+        mpo.close()
+    finally:
+        ctx.sync()
+        ctx.close()
 
 
 def test_one_site_step_and_repair_at_full_size():
