@@ -123,3 +123,4 @@ def test_segment_step_eight_lanes_equal_one_lane(ctx, dt_, monkeypatch):
         runs.append([sg.psi(j) for j in range(N)])
     for j in range(N):
         assert np.array_equal(runs[0][j], runs[1][j]), j
+
