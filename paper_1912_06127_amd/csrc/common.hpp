@@ -8,6 +8,7 @@
 #include <cstdint>
 #include <cstring>
 #include <functional>
+#include <initializer_list>
 #include <map>
 #include <memory>
 #include <stdexcept>
@@ -105,6 +106,8 @@ struct tdvp_ctx_s {
     std::map<int64_t, int> krylov_hint;         // Lanczos iterations last used per vector length
     void* pinned = nullptr;                     // page-locked host staging (pinned_host)
     size_t pinned_bytes = 0;
+    void* pinned_rd = nullptr;                  // page-locked landing area of read_back
+    size_t pinned_rd_bytes = 0;
     std::vector<tdvp_prof_rec> prof_pending;
     std::map<std::string, tdvp_prof_total> prof_total;
 
@@ -115,6 +118,18 @@ struct tdvp_ctx_s {
     // Page-locked host buffer of at least `bytes` bytes (grow-only; growing
     // synchronises the stream first).
     void* pinned_host(size_t bytes);
+    // Small device-to-host read-backs: every span is copied into page-locked
+    // memory on the context stream, the stream is awaited (polled for a
+    // short while before blocking: the waits on the serial path are a few
+    // microseconds of queued work) and the values are copied to dst.
+    struct ReadSpan {
+        void* dst;
+        const void* src;
+        size_t bytes;
+    };
+    void read_back(std::initializer_list<ReadSpan> spans);
+    // Waits for the context stream like hipStreamSynchronize.
+    void wait_stream();
     void release_all();
 };
 

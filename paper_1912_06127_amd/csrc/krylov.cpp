@@ -119,8 +119,7 @@ KrylovInfo krylov_run(tdvp_ctx ctx, const MatVec& op, double2* theta, int64_t n,
     };
     if (!small) {
         vdot_multi(ctx, theta, 0, 1, theta, n, scal + 1);
-        TDVP_CHECK_HIP(hipMemcpyAsync(host, scal + 1, sizeof(double2), hipMemcpyDeviceToHost, s));
-        TDVP_CHECK_HIP(hipStreamSynchronize(s));
+        ctx->read_back({{host, scal + 1, sizeof(double2)}});
         check_beta0(host[0].x);
         if (beta0 == 0.0) return info;
         scale_copy(V, theta, 1.0 / beta0, n, s);
@@ -247,9 +246,7 @@ KrylovInfo krylov_run(tdvp_ctx ctx, const MatVec& op, double2* theta, int64_t n,
                 lanczos_small_step(V, n, k, w, 0.0, k > 0 ? sc + 2 * k : nullptr, sc + 1 + 2 * k, s);
             }
             const int lo = queued == 0 ? 0 : 1 + 2 * queued;
-            TDVP_CHECK_HIP(hipMemcpyAsync(hs.data() + lo, sc + lo, sizeof(double) * (1 + 2 * end - lo),
-                                          hipMemcpyDeviceToHost, s));
-            TDVP_CHECK_HIP(hipStreamSynchronize(s));
+            ctx->read_back({{hs.data() + lo, sc + lo, sizeof(double) * (1 + 2 * end - lo)}});
             if (queued == 0) {
                 check_beta0(hs[0]);
                 if (beta0 == 0.0) return info;  // the queued steps ran on zero vectors
@@ -270,8 +267,7 @@ KrylovInfo krylov_run(tdvp_ctx ctx, const MatVec& op, double2* theta, int64_t n,
                 axpy_multi(V, n, k + 1, coef, w, n, s);
             }
             vdot_multi(ctx, w, 0, 1, w, n, scal + 1);
-            TDVP_CHECK_HIP(hipMemcpyAsync(host, scal, 2 * sizeof(double2), hipMemcpyDeviceToHost, s));
-            TDVP_CHECK_HIP(hipStreamSynchronize(s));
+            ctx->read_back({{host, scal, 2 * sizeof(double2)}});
             if (consume(k, host[0].x, host[1].x)) break;
             scale_copy(V + (size_t)(k + 1) * n, w, 1.0 / betas.back(), n, s);
         }

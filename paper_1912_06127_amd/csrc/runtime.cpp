@@ -73,10 +73,47 @@ void* tdvp_ctx_s::pinned_host(size_t bytes) {
     return pinned;
 }
 
+void tdvp_ctx_s::wait_stream() {
+    for (int i = 0; i < 4096; ++i) {
+        const hipError_t e = hipStreamQuery(stream);
+        if (e == hipSuccess) return;
+        if (e != hipErrorNotReady) TDVP_CHECK_HIP(e);
+    }
+    TDVP_CHECK_HIP(hipStreamSynchronize(stream));
+}
+
+void tdvp_ctx_s::read_back(std::initializer_list<ReadSpan> spans) {
+    size_t total = 0;
+    for (const auto& r : spans) total += (r.bytes + 15) / 16 * 16;
+    if (pinned_rd_bytes < total) {
+        if (pinned_rd) (void)hipHostFree(pinned_rd);  // no copy into it is pending between calls
+        pinned_rd = nullptr;
+        pinned_rd_bytes = 0;
+        const size_t cap = std::max<size_t>(total, 16384);
+        TDVP_CHECK_HIP(hipHostMalloc(&pinned_rd, cap, hipHostMallocDefault));
+        pinned_rd_bytes = cap;
+    }
+    char* p = static_cast<char*>(pinned_rd);
+    size_t off = 0;
+    for (const auto& r : spans) {
+        if (r.bytes) TDVP_CHECK_HIP(hipMemcpyAsync(p + off, r.src, r.bytes, hipMemcpyDeviceToHost, stream));
+        off += (r.bytes + 15) / 16 * 16;
+    }
+    wait_stream();
+    off = 0;
+    for (const auto& r : spans) {
+        if (r.bytes) std::memcpy(r.dst, p + off, r.bytes);
+        off += (r.bytes + 15) / 16 * 16;
+    }
+}
+
 void tdvp_ctx_s::release_all() {
     if (pinned) (void)hipHostFree(pinned);
     pinned = nullptr;
     pinned_bytes = 0;
+    if (pinned_rd) (void)hipHostFree(pinned_rd);
+    pinned_rd = nullptr;
+    pinned_rd_bytes = 0;
     for (auto& kv : work) dev_free(kv.second.ptr, kv.second.bytes);
     work.clear();
 }

@@ -76,9 +76,7 @@ SvdResult svd_rowmajor(tdvp_ctx ctx, const double2* M, int rows, int cols) {
              "zgesvdj");
     int hinfo = 0;
     r.S.resize(k);
-    TDVP_CHECK_HIP(hipMemcpyAsync(r.S.data(), S, sizeof(double) * k, hipMemcpyDeviceToHost, ctx->stream));
-    TDVP_CHECK_HIP(hipMemcpyAsync(&hinfo, dinfo, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
-    TDVP_CHECK_HIP(hipStreamSynchronize(ctx->stream));
+    ctx->read_back({{r.S.data(), S, sizeof(double) * k}, {&hinfo, dinfo, sizeof(int)}});
     TDVP_REQUIRE(hinfo == 0, TDVP_E_SOLVER, "zgesvdj did not converge (info = " + std::to_string(hinfo) + ")");
     for (double v : r.S) TDVP_REQUIRE(std::isfinite(v), TDVP_E_NUMERIC, "SVD: non-finite singular value");
     r.U = Vbuf;   // row-major [rows][k]
@@ -146,8 +144,7 @@ GramResult gram_eigen(tdvp_ctx ctx, const double2* M, int rows, int cols, bool l
         cgemm(ctx, p, true, 4);
         vec_norms2(P, left ? cols : n, n, len, left, ev, ctx->stream);
         std::vector<double> s2(n);
-        TDVP_CHECK_HIP(hipMemcpyAsync(s2.data(), ev, sizeof(double) * n, hipMemcpyDeviceToHost, ctx->stream));
-        TDVP_CHECK_HIP(hipStreamSynchronize(ctx->stream));
+        ctx->read_back({{s2.data(), ev, sizeof(double) * n}});
         r.s.resize(n);
         for (int c = 0; c < n; ++c) {
             TDVP_REQUIRE(std::isfinite(s2[c]), TDVP_E_NUMERIC, "density-matrix split: non-finite singular value");
@@ -161,9 +158,7 @@ GramResult gram_eigen(tdvp_ctx ctx, const double2* M, int rows, int cols, bool l
              "zheevd");
     std::vector<double> lam(n);
     int hinfo = 0;
-    TDVP_CHECK_HIP(hipMemcpyAsync(lam.data(), ev, sizeof(double) * n, hipMemcpyDeviceToHost, ctx->stream));
-    TDVP_CHECK_HIP(hipMemcpyAsync(&hinfo, dinfo, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
-    TDVP_CHECK_HIP(hipStreamSynchronize(ctx->stream));
+    ctx->read_back({{lam.data(), ev, sizeof(double) * n}, {&hinfo, dinfo, sizeof(int)}});
     TDVP_REQUIRE(hinfo == 0, TDVP_E_SOLVER, "zheevd did not converge (info = " + std::to_string(hinfo) + ")");
     r.s.resize(n);
     for (int c = 0; c < n; ++c) {
