@@ -354,6 +354,14 @@ void taylor_rescale(double2* F, double2* b, int64_t n, double2 eta, hipStream_t 
 // out = sum_j coef[j] V[j]
 void combine(double2* out, const double2* V, int64_t vstride, int nv, const double2* coef,
              int64_t n, hipStream_t s);
+// The same with at most kCombineArgs host coefficients passed by value in the
+// launch (no device copy of the coefficients).
+constexpr int kCombineArgs = 32;
+struct CombineCoef {
+    double2 c[kCombineArgs];
+};
+void combine_args(double2* out, const double2* V, int64_t vstride, int nv, const double2* coef_host, int64_t n,
+                  hipStream_t s);
 // strided 2-D copy of complex128: dst[r*ldd + c] = src[r*lds + c] for c < cols;
 // mask: 0 none, 1 zero where c < r (keep upper), 2 zero where c > r (keep lower)
 void copy2d(double2* dst, int64_t ldd, const double2* src, int64_t lds, int rows, int cols,

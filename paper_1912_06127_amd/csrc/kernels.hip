@@ -739,6 +739,20 @@ __global__ void combine_kernel(double2* out, const double2* V, int64_t vstride, 
     out[i] = make_double2(re, im);
 }
 
+// combine_kernel with the coefficients passed by value (no upload)
+__global__ void combine_args_kernel(double2* out, const double2* V, int64_t vstride, int nv, CombineCoef coef,
+                                    int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
+    if (i >= n) return;
+    double re = 0.0, im = 0.0;
+    for (int j = 0; j < nv; ++j) {
+        const double2 c = coef.c[j], v = V[j * vstride + i];
+        re += c.x * v.x - c.y * v.y;
+        im += c.x * v.y + c.y * v.x;
+    }
+    out[i] = make_double2(re, im);
+}
+
 __global__ void copy2d_kernel(double2* dst, int64_t ldd, const double2* src, int64_t lds, int rows,
                               int cols, int mask) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1291,6 +1305,16 @@ void combine(double2* out, const double2* V, int64_t vstride, int nv, const doub
     if (n == 0) return;
     hipLaunchKernelGGL(combine_kernel, dim3(nblk(n)), dim3(kVecThreads), 0, s, out, V, vstride, nv,
                        coef, n);
+    TDVP_CHECK_HIP(hipGetLastError());
+}
+
+void combine_args(double2* out, const double2* V, int64_t vstride, int nv, const double2* coef_host, int64_t n,
+                  hipStream_t s) {
+    TDVP_REQUIRE(nv <= kCombineArgs, TDVP_E_ARG, "combine_args: too many vectors");
+    if (n == 0) return;
+    CombineCoef c{};
+    for (int j = 0; j < nv; ++j) c.c[j] = coef_host[j];
+    hipLaunchKernelGGL(combine_args_kernel, dim3(nblk(n)), dim3(kVecThreads), 0, s, out, V, vstride, nv, c, n);
     TDVP_CHECK_HIP(hipGetLastError());
 }
 

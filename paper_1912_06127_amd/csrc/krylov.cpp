@@ -279,12 +279,16 @@ KrylovInfo krylov_run(tdvp_ctx ctx, const MatVec& op, double2* theta, int64_t n,
             c.y *= beta0;
         }
     }
-    // Pinned staging: the copy runs asynchronously, and every call
-    // synchronises the stream before it writes the staging buffer again.
-    double2* pin = static_cast<double2*>(ctx->pinned_host(sizeof(double2) * (size_t)k_used));
-    std::copy(y.begin(), y.begin() + k_used, pin);
-    TDVP_CHECK_HIP(hipMemcpyAsync(coef, pin, sizeof(double2) * k_used, hipMemcpyHostToDevice, s));
-    combine(theta, V, n, k_used, coef, n, s);
+    if (k_used <= kCombineArgs) {
+        combine_args(theta, V, n, k_used, y.data(), n, s);
+    } else {
+        // Pinned staging: the copy runs asynchronously, and every call
+        // synchronises the stream before it writes the staging buffer again.
+        double2* pin = static_cast<double2*>(ctx->pinned_host(sizeof(double2) * (size_t)k_used));
+        std::copy(y.begin(), y.begin() + k_used, pin);
+        TDVP_CHECK_HIP(hipMemcpyAsync(coef, pin, sizeof(double2) * k_used, hipMemcpyHostToDevice, s));
+        combine(theta, V, n, k_used, coef, n, s);
+    }
     info.k = k_used;
     return info;
 }
