@@ -20,6 +20,7 @@ environments L[k][a'][a] and R[l][b][b'].
 """
 from __future__ import annotations
 
+import numpy as np
 import torch
 from torch.utils.checkpoint import checkpoint
 
@@ -141,18 +142,32 @@ class Project(torch.autograd.Function):
         return (gw, *gV.unbind(0))
 
 
+def _tail_weight(alphas, betas, tau):
+    """|e_k^T exp(-i tau T) e_1| for the host tridiagonal T (convergence test)."""
+    k = len(alphas)
+    T = np.diag(np.asarray(alphas, dtype=np.float64))
+    if k > 1:
+        off = np.asarray(betas, dtype=np.float64)
+        T = T + np.diag(off, 1) + np.diag(off, -1)
+    lam, Z = np.linalg.eigh(T)
+    return abs(np.sum(Z[k - 1] * np.exp(-1j * tau * lam) * Z[0]))
+
+
 def expm_lanczos(op, x, tau, kmax=40, tol=1e-13, extra=5):
     """exp(-i tau H) x by Lanczos with two Gram-Schmidt passes (differentiable).
 
     The derivative of a Krylov approximation converges one order later than
     its value, so ``extra`` iterations run past the convergence point (unless
-    the space is exhausted) to keep gradients as accurate as the forward."""
+    the space is exhausted) to keep gradients as accurate as the forward.
+    The stopping test reads alpha_k and beta_k once per iteration and works on
+    the host copy of the tridiagonal matrix; the exponential that enters the
+    result is the differentiable one of the final tridiagonal matrix."""
     shape = x.shape
     v = x.reshape(-1)
     beta0 = torch.linalg.vector_norm(v)
     V = [v / beta0]
     alphas, betas = [], []
-    y = None
+    ha, hb = [], []  # host copies of alphas, betas
     stop_at = kmax
     for k in range(kmax):
         w = op(V[k].reshape(shape)).reshape(-1)
@@ -164,22 +179,23 @@ def expm_lanczos(op, x, tau, kmax=40, tol=1e-13, extra=5):
             w = Project.apply(w, *V)
         b = torch.linalg.vector_norm(w)
         alphas.append(a)
-        n = len(alphas)
-        T = torch.diag(torch.stack(alphas))
-        if n > 1:
-            off = torch.stack(betas)
-            T = T + torch.diag(off, 1) + torch.diag(off, -1)
-        E = torch.linalg.matrix_exp((-1j * tau) * T.to(x.dtype))
-        y = E[:, 0]
         with torch.no_grad():
-            scale = max(max(abs(float(t)) for t in alphas), max((float(t) for t in betas), default=0.0))
-            exhausted = float(b) <= 1e-14 * scale or scale == 0.0 or len(alphas) >= v.numel()
-            if float(b) * float(abs(y[-1])) <= tol and stop_at == kmax:
-                stop_at = min(kmax, k + 1 + extra)
+            a_h, b_h = torch.stack([a.detach(), b.detach()]).tolist()
+        ha.append(a_h)
+        scale = max(max(abs(t) for t in ha), max(hb, default=0.0))
+        exhausted = b_h <= 1e-14 * scale or scale == 0.0 or len(alphas) >= v.numel()
+        if stop_at == kmax and b_h * _tail_weight(ha, hb, tau) <= tol:
+            stop_at = min(kmax, k + 1 + extra)
         if exhausted or k + 1 >= stop_at:
             break
         betas.append(b)
+        hb.append(b_h)
         V.append(w / b)
+    T = torch.diag(torch.stack(alphas))
+    if len(alphas) > 1:
+        off = torch.stack(betas)
+        T = T + torch.diag(off, 1) + torch.diag(off, -1)
+    y = torch.linalg.matrix_exp((-1j * tau) * T.to(x.dtype))[:, 0]
     out = beta0 * (torch.stack(V[: len(alphas)]).T @ y)
     return out.reshape(shape)
 
