@@ -84,7 +84,7 @@ def to_inverse_canonical(tensors):
         chil, d, chir = T[j].shape
         Q, R = np.linalg.qr(T[j].reshape(chil, d * chir).conj().T)
         T[j] = Q.conj().T.reshape(Q.shape[1], d, chir)
-        T[j - 1] = np.einsum("asb,bc->asc", T[j - 1], R.conj().T)
+        T[j - 1] = np.einsum("asb,bc->asc", T[j - 1], R.conj().T, optimize=True)
         T[j - 1] /= np.linalg.norm(T[j - 1])
     Psi, V = [], []
     M = T[0]
@@ -94,7 +94,7 @@ def to_inverse_canonical(tensors):
         S = S / np.linalg.norm(S)
         Psi.append((U * S[None, :]).reshape(chil, d, len(S)))
         V.append(1.0 / S)
-        M = np.einsum("ab,bsc->asc", S[:, None] * Vh, T[j + 1])
+        M = np.einsum("ab,bsc->asc", S[:, None] * Vh, T[j + 1], optimize=True)
     Psi.append(M)
     return Psi, V
 
@@ -219,7 +219,7 @@ def local_pair_update(Psi_l, V, Psi_r, heff2, tau: float, tr: Truncation, kmax: 
     Theta <- exp(-i tau H_eff) Theta by Lanczos (heff2 applies H_eff), then the
     truncated SVD Theta = U S Vh.  Returns (U [chil, d, chi], S, Vh [chi, d, chir],
     discarded weight); the new tensors are Psi_l = U S, V = 1/S, Psi_r = S Vh."""
-    theta = np.einsum("asb,b,btc->astc", Psi_l, V, Psi_r)
+    theta = np.einsum("asb,b,btc->astc", Psi_l, V, Psi_r, optimize=True)
     theta = expm_krylov(heff2, theta, tau, kmax=kmax, tol=tol)
     chil, d1, d2, chir = theta.shape
     U, S, Vh = np.linalg.svd(theta.reshape(chil * d1, d2 * chir), full_matrices=False)
