@@ -86,22 +86,39 @@ struct KParams {
     int64_t ldc, strideC;
 };
 
-template <typename T>
-__device__ inline void load_elem(const KOperand& o, int64_t idx, bool valid, T& re, T& im) {
-    re = T(0);
-    im = T(0);
-    if (valid) {
-        if (o.c128) {
-            double2 v = reinterpret_cast<const double2*>(o.p)[idx];
-            re = static_cast<T>(v.x);
-            im = static_cast<T>(v.y);
-        } else {
-            float2 v = reinterpret_cast<const float2*>(o.p)[idx];
-            re = static_cast<T>(v.x);
-            im = static_cast<T>(v.y);
-        }
-        if (o.conj) im = -im;
+// Element idx of an operand as stored (re, im), without the validity and
+// conjugation fix-up (applied where the value goes to LDS).  Branch-free: an
+// invalid element reads element `base` (the operand's first element, which
+// exists whenever the product is non-empty), so the loads of a staging pass
+// issue back to back and are only waited for where the values are stored
+// (a load under a branch, or a select right after it, makes the compiler
+// wait for it at once).  NATIVE: the operand is stored in the compute
+// precision (the common case, chosen once per tile outside the k loop);
+// otherwise its precision is read from the descriptor at run time.
+template <typename T, bool NATIVE>
+__device__ inline void load_raw(const KOperand& o, int64_t base, int64_t idx, bool valid, T& re, T& im) {
+    const int64_t at = valid ? idx : base;
+    if constexpr (NATIVE) {
+        using V2 = typename std::conditional<sizeof(T) == 4, float2, double2>::type;
+        const V2 v = reinterpret_cast<const V2*>(o.p)[at];
+        re = v.x;
+        im = v.y;
+    } else if (o.c128) {
+        const double2 v = reinterpret_cast<const double2*>(o.p)[at];
+        re = static_cast<T>(v.x);
+        im = static_cast<T>(v.y);
+    } else {
+        const float2 v = reinterpret_cast<const float2*>(o.p)[at];
+        re = static_cast<T>(v.x);
+        im = static_cast<T>(v.y);
     }
+}
+
+// Operands stored in the compute precision (complex64 for T = float,
+// complex128 for T = double).
+template <typename T>
+__device__ inline bool native_operands(const KParams& p) {
+    return sizeof(T) == 4 ? (!p.A.c128 && !p.B.c128) : (p.A.c128 && p.B.c128);
 }
 
 // Second-generation tile: two LDS planes (re, im) per operand, the third 3M
@@ -143,7 +160,7 @@ struct TileAcc {
 // Accumulates the products of output tile (m0, n0) over k in [kbeg, kend)
 // (operands offset by zA, zB elements) into acc.
 // PF: k-tiles the global loads run ahead of the MFMAs (1 or 2).
-template <typename T, int BM, int BN, int BK, int WM, int WN, bool M3, bool AK, bool BKC, int PF>
+template <typename T, int BM, int BN, int BK, int WM, int WN, bool M3, bool AK, bool BKC, int PF, bool NATIVE>
 __device__ __forceinline__ void gemm_tile_acc(const KParams& p, TileSmem<T, BM, BN, BK, AK, BKC>& sm, int m0, int n0,
                                               int64_t zA, int64_t zB, int kbeg, int kend,
                                               TileAcc<T, BM, BN, WM, WN, M3>& accs) {
@@ -182,11 +199,15 @@ __device__ __forceinline__ void gemm_tile_acc(const KParams& p, TileSmem<T, BM, 
     // the next one is written to LDS
     static_assert(PF == 1 || PF == 2, "prefetch distance");
     T ar[PF][AE], ai[PF][AE], br[PF][BE], bi[PF][BE];
+    static_assert(AE <= 32 && BE <= 32, "validity masks");
+    unsigned am[PF], bm[PF];  // bit i: element i of the staged set is inside the operand
     using I0 = std::integral_constant<int, 0>;
     using I1 = std::integral_constant<int, 1>;
 
     auto gload = [&](int k0, auto setc) {
         constexpr int SET = decltype(setc)::value;
+        am[SET] = 0u;
+        bm[SET] = 0u;
 #pragma unroll
         for (int i = 0; i < AE / 2; ++i) {  // pairs along the contiguous index
             const int e = 2 * (tid + NT * i);
@@ -196,8 +217,9 @@ __device__ __forceinline__ void gemm_tile_acc(const KParams& p, TileSmem<T, BM, 
             const int64_t idx = AK ? (int64_t)gm * p.A.ld + gk : (int64_t)gk * p.A.ld + gm;
             const bool v0 = gm < p.M && gk < kend;
             const bool v1 = AK ? (gm < p.M && gk + 1 < kend) : (gm + 1 < p.M && gk < kend);
-            load_elem<T>(p.A, zA + idx, v0, ar[SET][2 * i], ai[SET][2 * i]);
-            load_elem<T>(p.A, zA + idx + 1, v1, ar[SET][2 * i + 1], ai[SET][2 * i + 1]);
+            load_raw<T, NATIVE>(p.A, zA, zA + idx, v0, ar[SET][2 * i], ai[SET][2 * i]);
+            load_raw<T, NATIVE>(p.A, zA, zA + idx + 1, v1, ar[SET][2 * i + 1], ai[SET][2 * i + 1]);
+            am[SET] |= (v0 ? 1u : 0u) << (2 * i) | (v1 ? 1u : 0u) << (2 * i + 1);
         }
 #pragma unroll
         for (int i = 0; i < BE / 2; ++i) {
@@ -208,8 +230,9 @@ __device__ __forceinline__ void gemm_tile_acc(const KParams& p, TileSmem<T, BM, 
             const int64_t idx = BKC ? (int64_t)gn * p.B.ld + gk : (int64_t)gk * p.B.ld + gn;
             const bool v0 = gn < p.N && gk < kend;
             const bool v1 = BKC ? (gn < p.N && gk + 1 < kend) : (gn + 1 < p.N && gk < kend);
-            load_elem<T>(p.B, zB + idx, v0, br[SET][2 * i], bi[SET][2 * i]);
-            load_elem<T>(p.B, zB + idx + 1, v1, br[SET][2 * i + 1], bi[SET][2 * i + 1]);
+            load_raw<T, NATIVE>(p.B, zB, zB + idx, v0, br[SET][2 * i], bi[SET][2 * i]);
+            load_raw<T, NATIVE>(p.B, zB, zB + idx + 1, v1, br[SET][2 * i + 1], bi[SET][2 * i + 1]);
+            bm[SET] |= (v0 ? 1u : 0u) << (2 * i) | (v1 ? 1u : 0u) << (2 * i + 1);
         }
     };
     auto lstore = [&](int buf, auto setc) {
@@ -218,15 +241,17 @@ __device__ __forceinline__ void gemm_tile_acc(const KParams& p, TileSmem<T, BM, 
         for (int i = 0; i < AE; ++i) {
             const int e = 2 * (tid + NT * (i / 2)) + (i & 1);
             const int off = AK ? (e / BK) * LDAk + e % BK : (e / BM) * LDAo + e % BM;
-            sA[buf][0][off] = ar[SET][i];
-            sA[buf][1][off] = ai[SET][i];
+            const bool v = (am[SET] >> i) & 1u;
+            sA[buf][0][off] = v ? ar[SET][i] : T(0);
+            sA[buf][1][off] = v ? (p.A.conj ? -ai[SET][i] : ai[SET][i]) : T(0);
         }
 #pragma unroll
         for (int i = 0; i < BE; ++i) {
             const int e = 2 * (tid + NT * (i / 2)) + (i & 1);
             const int off = BKC ? (e / BK) * LDAk + e % BK : (e / BN) * LDBo + e % BN;
-            sB[buf][0][off] = br[SET][i];
-            sB[buf][1][off] = bi[SET][i];
+            const bool v = (bm[SET] >> i) & 1u;
+            sB[buf][0][off] = v ? br[SET][i] : T(0);
+            sB[buf][1][off] = v ? (p.B.conj ? -bi[SET][i] : bi[SET][i]) : T(0);
         }
     };
 
@@ -349,7 +374,10 @@ __device__ __forceinline__ void gemm_block(const KParams& p, TileSmem<T, BM, BN,
                                            int64_t zA, int64_t zB, int64_t zC, int kbeg, int kend) {
     TileAcc<T, BM, BN, WM, WN, M3> acc;
     acc.zero();
-    gemm_tile_acc<T, BM, BN, BK, WM, WN, M3, AK, BKC, PF>(p, sm, m0, n0, zA, zB, kbeg, kend, acc);
+    if (native_operands<T>(p))
+        gemm_tile_acc<T, BM, BN, BK, WM, WN, M3, AK, BKC, PF, true>(p, sm, m0, n0, zA, zB, kbeg, kend, acc);
+    else
+        gemm_tile_acc<T, BM, BN, BK, WM, WN, M3, AK, BKC, PF, false>(p, sm, m0, n0, zA, zB, kbeg, kend, acc);
     gemm_tile_store<T, BM, BN, WM, WN, M3>(p, m0, n0, zC, acc);
 }
 
@@ -449,12 +477,12 @@ __global__ void __launch_bounds__(64 * WM * WN) cgemm2_blocks_kernel(const BProb
     TileAcc<T, BM, BN, WM, WN, M3> acc;
     acc.zero();
     if (bp.nchunk == 0) {
-        gemm_tile_acc<T, BM, BN, BK, WM, WN, M3, AK, BKC, 1>(p, sm, m0, n0, zA, zB, 0, p.K, acc);
+        gemm_tile_acc<T, BM, BN, BK, WM, WN, M3, AK, BKC, 1, false>(p, sm, m0, n0, zA, zB, 0, p.K, acc);
     } else {
         for (int c = bp.chunk0; c < bp.chunk0 + bp.nchunk; ++c) {
             const BChunkDev ch = chunks[c];
             for (int i = 0; i < ch.count; ++i)
-                gemm_tile_acc<T, BM, BN, BK, WM, WN, M3, AK, BKC, 1>(
+                gemm_tile_acc<T, BM, BN, BK, WM, WN, M3, AK, BKC, 1, false>(
                     p, sm, m0, n0, zA + ch.offA + i * ch.strideA, zB + ch.offB + i * ch.strideB, 0, ch.K, acc);
         }
     }
