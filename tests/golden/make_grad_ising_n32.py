@@ -10,7 +10,7 @@ respect to J and h from the oracle's forward-mode JVP (oracle/grad.py).
 
 Only ``oracle/`` and the seeded input generators of ``workloads/`` are used.
 Run from the repository root: ``python tests/golden/make_grad_ising_n32.py``
-(about an hour of CPU time).
+(about three hours on 8 cores).
 """
 import json
 import os
