@@ -13,7 +13,7 @@ smallest kept Schmidt values, their sum of squares and the discarded
 weight.  Environments are streamed (only those the phase reads are kept).
 
 Only ``oracle/`` and the seeded input generators of ``workloads/`` are used.
-Run from the repository root (about half an hour of CPU time, ~20 GB).
+Run from the repository root (about ten minutes on 8 cores, ~20 GB).
 """
 import json
 import os

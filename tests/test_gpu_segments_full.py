@@ -63,7 +63,13 @@ def test_first_phase_at_full_size_matches_oracle(compute):
             print(f"  pair ({j}, {j + 1}) {q['chi']}: top {e_top:.1e} bottom {e_bot:.1e}", flush=True)
             assert e_top <= rtol and e_bot <= rtol, (j, e_top, e_bot)
             assert abs(np.sum(s ** 2) - q["sum_s2"]) <= rtol * q["sum_s2"]
-        assert abs(st["w_step"] - g["w_phase"]) <= max(rtol * g["w_phase"], 1e-14)
+        # the discarded weight (Eq. discweight) is the squared norm of the cut
+        # part of each pair's state: an error e in the state (the FP32 matvec
+        # bar is 1e-5 relative) moves it by at most 2 sqrt(w) e per pair, so
+        # complex64 is held to 2 sqrt(17 w_phase) 1e-5 (5e-7 here) in absolute
+        # terms; complex128 to 1e-9 relative
+        w_tol = rtol * g["w_phase"] if compute == "c128" else 2e-5 * np.sqrt(len(g["pairs"]) * g["w_phase"])
+        assert abs(st["w_step"] - g["w_phase"]) <= max(w_tol, 1e-14), (st["w_step"], g["w_phase"])
         sg.close()
         mpo.close()
     finally:
