@@ -100,7 +100,8 @@ void heff_apply(tdvp_ctx ctx, const HeffArgs& a, const void* x, Dt x_dt, void* y
     const char* xb = static_cast<const char*>(x);
     const char* yb = static_cast<const char*>(y);
     const bool overlap = xb < yb + ybytes && yb < xb + xbytes;
-    if (!overlap && heff_small_fits(a.chil, a.chir, D, a.wl, a.wr, a.fp64)) {
+    const bool env_native = (a.env_dt == Dt::C128) == a.fp64;
+    if (!overlap && env_native && heff_small_fits(a.chil, a.chir, D, a.wl, a.wr, a.fp64)) {
         HeffSmallDesc h;
         h.L = a.L; h.L_dt = a.env_dt;
         h.R = a.R; h.R_dt = a.env_dt;

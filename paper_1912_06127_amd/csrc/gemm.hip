@@ -476,16 +476,21 @@ __global__ void __launch_bounds__(64 * WM * WN) cgemm2_blocks_kernel(const BProb
     const int64_t zA = (int64_t)z * p.A.stride, zB = (int64_t)z * p.B.stride;
     TileAcc<T, BM, BN, WM, WN, M3> acc;
     acc.zero();
-    if (bp.nchunk == 0) {
-        gemm_tile_acc<T, BM, BN, BK, WM, WN, M3, AK, BKC, 1, false>(p, sm, m0, n0, zA, zB, 0, p.K, acc);
-    } else {
-        for (int c = bp.chunk0; c < bp.chunk0 + bp.nchunk; ++c) {
-            const BChunkDev ch = chunks[c];
-            for (int i = 0; i < ch.count; ++i)
-                gemm_tile_acc<T, BM, BN, BK, WM, WN, M3, AK, BKC, 1, false>(
-                    p, sm, m0, n0, zA + ch.offA + i * ch.strideA, zB + ch.offB + i * ch.strideB, 0, ch.K, acc);
+    auto run = [&](auto native) {
+        constexpr bool NAT = decltype(native)::value;
+        if (bp.nchunk == 0) {
+            gemm_tile_acc<T, BM, BN, BK, WM, WN, M3, AK, BKC, 1, NAT>(p, sm, m0, n0, zA, zB, 0, p.K, acc);
+        } else {
+            for (int c = bp.chunk0; c < bp.chunk0 + bp.nchunk; ++c) {
+                const BChunkDev ch = chunks[c];
+                for (int i = 0; i < ch.count; ++i)
+                    gemm_tile_acc<T, BM, BN, BK, WM, WN, M3, AK, BKC, 1, NAT>(
+                        p, sm, m0, n0, zA + ch.offA + i * ch.strideA, zB + ch.offB + i * ch.strideB, 0, ch.K, acc);
+            }
         }
-    }
+    };
+    if (native_operands<T>(p)) run(std::true_type{});
+    else run(std::false_type{});
     gemm_tile_store<T, BM, BN, WM, WN, M3>(p, m0, n0, (int64_t)z * p.strideC, acc);
 }
 

@@ -234,7 +234,23 @@ size_t heff_small_smem(int chil, int chir, int D, int wl, int wr, int rows) {
            sizeof(typename cplx<T>::t) * (wl * nc + (size_t)wr * chir + red + (size_t)wl * chil + (size_t)rows * nc);
 }
 
-template <typename T>
+// Element i of a complex array stored as S (float2 or double2), as C.
+template <typename C, typename S>
+__device__ __forceinline__ C ld_as(const void* p, int64_t i) {
+    const S v = reinterpret_cast<const S*>(p)[i];
+    C c;
+    c.x = v.x;
+    c.y = v.y;
+    return c;
+}
+
+// L and R are in the compute precision (the launcher checks it); x is stored
+// as XS.  All loads have a compile-time width and no branch around them, so
+// the staging loops issue kHsLoads loads before their first wait and the
+// stage-B loop over b can keep several R loads in flight.
+constexpr int kHsLoads = 4;
+
+template <typename T, typename XS>
 __global__ void __launch_bounds__(kHsThreads) heff_small_kernel(HsParams h) {
     using C = typename cplx<T>::t;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -255,11 +271,20 @@ __global__ void __launch_bounds__(kHsThreads) heff_small_kernel(HsParams h) {
     C* red = T3 + (size_t)h.wr * h.chir;                             // [NR]
     C* Ls = red + NR;                                                // [wl][chil]
     C* xb = Ls + (size_t)h.wl * h.chil;                              // [rows][NC]
-    for (int i = tid; i < h.wl * h.chil; i += kHsThreads) {
-        const int k = i / h.chil, a = i % h.chil;
-        T re, im;
-        ld<T>(h.L, h.L128, ((int64_t)k * h.chil + ap) * h.chil + a, re, im);
-        Ls[i] = C{re, im};
+    for (int i0 = 0; i0 < h.wl * h.chil; i0 += kHsThreads * kHsLoads) {
+        C buf[kHsLoads];
+#pragma unroll
+        for (int u = 0; u < kHsLoads; ++u) {
+            const int i = i0 + u * kHsThreads + tid;
+            const int ii = i < h.wl * h.chil ? i : 0;
+            const int k = ii / h.chil, a = ii % h.chil;
+            buf[u] = ld_as<C, C>(h.L, ((int64_t)k * h.chil + ap) * h.chil + a);
+        }
+#pragma unroll
+        for (int u = 0; u < kHsLoads; ++u) {
+            const int i = i0 + u * kHsThreads + tid;
+            if (i < h.wl * h.chil) Ls[i] = buf[u];
+        }
     }
     for (int i = tid; i < h.wl * NC; i += kHsThreads) T1[i] = C{T(0), T(0)};
 
@@ -268,10 +293,18 @@ __global__ void __launch_bounds__(kHsThreads) heff_small_kernel(HsParams h) {
     for (int a0 = 0; a0 < h.chil; a0 += h.rows) {
         const int na = min(h.rows, h.chil - a0);
         if (a0 > 0) __syncthreads();  // the previous chunk is consumed
-        for (int i = tid; i < na * NC; i += kHsThreads) {
-            T re, im;
-            ld<T>(h.x, h.x128, (int64_t)a0 * NC + i, re, im);
-            xb[i] = C{re, im};
+        for (int i0 = 0; i0 < na * NC; i0 += kHsThreads * kHsLoads) {
+            C buf[kHsLoads];
+#pragma unroll
+            for (int u = 0; u < kHsLoads; ++u) {
+                const int i = i0 + u * kHsThreads + tid;
+                buf[u] = ld_as<C, XS>(h.x, (int64_t)a0 * NC + (i < na * NC ? i : 0));
+            }
+#pragma unroll
+            for (int u = 0; u < kHsLoads; ++u) {
+                const int i = i0 + u * kHsThreads + tid;
+                if (i < na * NC) xb[i] = buf[u];
+            }
         }
         if (a0 == 0) wstage_stage_op<T>(w, smem_raw, rp, cl, vl);  // its barrier also publishes Ls, T1, xb
         else __syncthreads();
@@ -325,13 +358,13 @@ __global__ void __launch_bounds__(kHsThreads) heff_small_kernel(HsParams h) {
         T ar = 0, ai = 0;
         for (int n = g; n < h.wr; n += G) {
             const C* t3 = T3 + (size_t)n * h.chir;
-            const int64_t rbase = (int64_t)n * h.chir * h.chir + bp;
+            const C* Rn = reinterpret_cast<const C*>(h.R) + (int64_t)n * h.chir * h.chir + bp;
+#pragma unroll 8
             for (int b = 0; b < h.chir; ++b) {
-                T rr, ri;
-                ld<T>(h.R, h.R128, rbase + (int64_t)b * h.chir, rr, ri);
+                const C r = Rn[(int64_t)b * h.chir];
                 const C t = t3[b];
-                ar += t.x * rr - t.y * ri;
-                ai += t.x * ri + t.y * rr;
+                ar += t.x * r.x - t.y * r.y;
+                ai += t.x * r.y + t.y * r.x;
             }
         }
         red[item] = C{ar, ai};
@@ -1212,6 +1245,8 @@ bool heff_small_fits(int chil, int chir, int D, int wl, int wr, bool fp64) {
 void heff_small(tdvp_ctx ctx, const HeffSmallDesc& d) {
     TDVP_REQUIRE(heff_small_fits(d.chil, d.chir, d.D, d.wl, d.wr, d.fp64), TDVP_E_SHAPE,
                  "heff_small: shape outside the fused kernel's limits");
+    TDVP_REQUIRE((d.L_dt == Dt::C128) == d.fp64 && (d.R_dt == Dt::C128) == d.fp64, TDVP_E_ARG,
+                 "heff_small: environments must be in the compute precision");
     HsParams h;
     h.L = d.L; h.L128 = d.L_dt == Dt::C128;
     h.R = d.R; h.R128 = d.R_dt == Dt::C128;
@@ -1229,8 +1264,14 @@ void heff_small(tdvp_ctx ctx, const HeffSmallDesc& d) {
                    elem_bytes(d.x_dt) * d.chil * nc + elem_bytes(d.y_dt) * d.chil * nc +
                        elem_bytes(d.L_dt) * (double)d.wl * d.chil * d.chil + elem_bytes(d.R_dt) * (double)d.wr * d.chir * d.chir);
     const dim3 grid(d.chil, d.D);
-    if (d.fp64) hipLaunchKernelGGL(heff_small_kernel<double>, grid, dim3(kHsThreads), shmem, ctx->stream, h);
-    else hipLaunchKernelGGL(heff_small_kernel<float>, grid, dim3(kHsThreads), shmem, ctx->stream, h);
+    const bool x128 = d.x_dt == Dt::C128;
+    if (d.fp64) {
+        if (x128) hipLaunchKernelGGL((heff_small_kernel<double, double2>), grid, dim3(kHsThreads), shmem, ctx->stream, h);
+        else hipLaunchKernelGGL((heff_small_kernel<double, float2>), grid, dim3(kHsThreads), shmem, ctx->stream, h);
+    } else {
+        if (x128) hipLaunchKernelGGL((heff_small_kernel<float, double2>), grid, dim3(kHsThreads), shmem, ctx->stream, h);
+        else hipLaunchKernelGGL((heff_small_kernel<float, float2>), grid, dim3(kHsThreads), shmem, ctx->stream, h);
+    }
     TDVP_CHECK_HIP(hipGetLastError());
 }
 
