@@ -64,21 +64,32 @@ constexpr size_t wstage_op_bytes() {
            16 * 16;
 }
 
-// A block handles kWPts consecutive q of one p with kWSub waves: every wave
-// loads every kWSub-th input row of the 64 points (coalesced along q) into
-// the shared [nin][kWPts] tile, then computes every kWSub-th output row.
+// A block handles wpts<T>() consecutive q of one p with kWSub groups of
+// threads: every group loads every kWSub-th input row of those points
+// (coalesced along q) into the shared [nin][points] tile, then computes every
+// kWSub-th output row.
 // Sharing each point over four waves keeps the LDS per thread small enough
 // for several blocks per CU, so many loads are in flight.
 constexpr int kWSub = 4;
-constexpr int kWPts = 64;
+// points per block: 128 in complex64 (each row of a block is 1 KiB of
+// contiguous memory), 64 in complex128 (the same bytes; keeps the LDS tile
+// within bounds for the widest MPO bonds)
+template <typename T>
+constexpr int wpts() {
+    return sizeof(T) == 4 ? 128 : 64;
+}
 constexpr int kWRowsInFlight = 16;  // input rows per wave loaded back to back (nin <= 64)
-constexpr int kWThreads = kWSub * kWPts;
+template <typename T>
+constexpr int wthreads() {
+    return kWSub * wpts<T>();
+}
 
 template <typename T>
 __device__ __forceinline__ void wstage_tile(const WParams& w, int p, int q0, typename cplx<T>::t* xin, const int* rp,
                                             const int* cl, const typename cplx<T>::t* vl) {
     using C = typename cplx<T>::t;
-    const int lane = threadIdx.x & 63, sub = threadIdx.x >> 6;
+    constexpr int kWPts = wpts<T>();
+    const int lane = threadIdx.x % kWPts, sub = threadIdx.x / kWPts;
     const int q = q0 + lane;
     const bool live = q < w.Q;
     const int64_t pin = (int64_t)p * w.ip + q;
@@ -151,7 +162,7 @@ __device__ __forceinline__ void wstage_stage_op(const WParams& w, unsigned char*
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kWThreads) wstage_kernel(WParams w) {
+__global__ void __launch_bounds__(wthreads<T>()) wstage_kernel(WParams w) {
     using C = typename cplx<T>::t;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int* rp;
@@ -159,7 +170,7 @@ __global__ void __launch_bounds__(kWThreads) wstage_kernel(WParams w) {
     const C* vl;
     wstage_stage_op<T>(w, smem_raw, rp, cl, vl);
     C* xin = reinterpret_cast<C*>(smem_raw + wstage_op_bytes<T>());  // [nin][kWPts]
-    wstage_tile<T>(w, blockIdx.y, blockIdx.x * kWPts, xin, rp, cl, vl);
+    wstage_tile<T>(w, blockIdx.y, blockIdx.x * wpts<T>(), xin, rp, cl, vl);
 }
 
 // Grouped MPO stage: problem g owns blocks [blk_begin, blk_begin + P*qblocks).
@@ -170,7 +181,8 @@ struct GWProblem {
 };
 
 template <typename T>
-__global__ void __launch_bounds__(kWThreads) wstage_grouped_kernel(const GWProblem* __restrict__ probs, int nprob) {
+__global__ void __launch_bounds__(wthreads<T>()) wstage_grouped_kernel(const GWProblem* __restrict__ probs,
+                                                                        int nprob) {
     using C = typename cplx<T>::t;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int64_t b = blockIdx.x;
@@ -183,7 +195,7 @@ __global__ void __launch_bounds__(kWThreads) wstage_grouped_kernel(const GWProbl
     const int qb = probs[lo].qblocks;
     const int64_t local = b - probs[lo].blk_begin;
     const int p = (int)(local / qb);
-    const int q0 = (int)(local % qb) * kWPts;
+    const int q0 = (int)(local % qb) * wpts<T>();
     const WParams w = probs[lo].w;
     const int* rp;
     const int* cl;
@@ -1142,11 +1154,12 @@ void wstage(tdvp_ctx ctx, const WStageDesc& d) {
     w.col = d.col;
     w.val = d.val;
     const size_t esz = d.fp64 ? sizeof(double2) : sizeof(float2);
-    const size_t shmem = (size_t)kWPts * w.nin * esz + (d.fp64 ? wstage_op_bytes<double>() : wstage_op_bytes<float>());
+    const int bpts = d.fp64 ? wpts<double>() : wpts<float>();  // points per block
+    const size_t shmem = (size_t)bpts * w.nin * esz + (d.fp64 ? wstage_op_bytes<double>() : wstage_op_bytes<float>());
     TDVP_REQUIRE(shmem <= 160 * 1024, TDVP_E_SHAPE, "wstage: MPO bond dimension too large");
     TDVP_REQUIRE(d.P <= 65535, TDVP_E_SHAPE, "wstage: grid too large");
-    const int nt = kWThreads;
-    dim3 grid((d.Q + kWPts - 1) / kWPts, d.P);
+    const int nt = d.fp64 ? wthreads<double>() : wthreads<float>();
+    dim3 grid((d.Q + bpts - 1) / bpts, d.P);
     const double pts = (double)d.P * d.Q;
     ProfScope prof(ctx, d.fp64 ? "wstage_f64" : "wstage_f32", 0.0,
                    pts * (w.nin * elem_bytes(d.in_dt) + w.nout * elem_bytes(d.out_dt)));
@@ -1169,9 +1182,9 @@ void grouped_wstage_plan(tdvp_ctx ctx, const std::vector<WStageDesc>& ds, Groupe
         nin_max = std::max(nin_max, d.w_in * d.D);
     }
     const size_t esz = out.fp64 ? sizeof(double2) : sizeof(float2);
-    const int nt = kWPts;  // points per block (kWThreads threads)
-    out.nt = kWThreads;
-    out.shmem = (size_t)kWPts * nin_max * esz + (out.fp64 ? wstage_op_bytes<double>() : wstage_op_bytes<float>());
+    const int nt = out.fp64 ? wpts<double>() : wpts<float>();  // points per block
+    out.nt = out.fp64 ? wthreads<double>() : wthreads<float>();
+    out.shmem = (size_t)nt * nin_max * esz + (out.fp64 ? wstage_op_bytes<double>() : wstage_op_bytes<float>());
     TDVP_REQUIRE(out.shmem <= 160 * 1024, TDVP_E_SHAPE, "wstage: MPO bond dimension too large");
     int64_t blocks = 0;
     for (const auto& d : ds) {
