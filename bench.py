@@ -627,6 +627,9 @@ def main():
         "kernel": kname, "launches": kp["count"], "avg_launch_us": round(per_launch_ms * 1e3, 1),
         "algorithmic_flops_per_launch": per_launch_flops,
         "mfma_executed_frac": round(0.75 * achieved / PEAK_FP32_MFMA_TFLOPS, 4),
+        "note": "3M form: three real products per complex product, so the matrix cores execute 3/4 of the "
+                "algorithmic flops and frac can exceed 1; mfma_executed_frac is the fraction of the "
+                "instruction peak actually issued",
         "kernel_share_of_step": round(kp["ms"] / (ms64 * args.steps), 3),
         "other_kernels_ms_per_step": {k: round(v["ms"] / args.steps, 4) for k, v in prof64.items() if k != kname},
     }
