@@ -159,6 +159,20 @@ int tdvp_fit_power_law(double alpha, int K, int rmax, int refine, double* c_out,
 int mpo_from_tensors(tdvp_ctx ctx, int N, int d, const int* w, const double* W_host,
                      tdvp_mpo* out);
 int mpo_get_info(tdvp_mpo mpo, int* N, int* d, int* w /* [N+1], nullable */);
+/* U(1) charges of the MPO bond indices (the quantum-number blocks the
+ * paper's symmetric tensors use, Supplemental Material, Implementation):
+ * charges = the concatenation of bonds 0..N, w_j integers each; index k of
+ * bond j carries the charge its operator string adds, so W_j[k][l][s'][s]
+ * may be non-zero only where c(l) = c(k) + q(s') - q(s).  Both boundary
+ * bonds must carry 0.  NULL clears them.  With charges on both the MPO and
+ * the MPS (mps_set_charges), tdvp2_step and dmrg2_sweep run in U(1) mode:
+ * block-sparse matvecs and environment updates (as apply_heff_u1 /
+ * env_update_u1) and, in the two-site splits, one SVD per charge sector of
+ * the new bond with one truncation over all sectors.  tdvp1_step (and the
+ * one-site part of tdvp_hybrid_step) refuses U(1) mode with TDVP_E_ARG: its
+ * dense QR / LQ gauge moves would mix the sectors.  Errors: TDVP_E_ARG for
+ * non-zero boundary charges. */
+int mpo_set_charges(tdvp_mpo mpo, const int* charges);
 int mpo_get_tensor(tdvp_mpo mpo, int site, double* W_host);
 int mpo_destroy(tdvp_mpo mpo);
 
@@ -182,8 +196,23 @@ int mps_get_tensor(tdvp_mps mps, int site, double* host);
  * responsible for the canonical form that tdvp*_step assumes (sites 2..N
  * right-orthonormal); mps_right_canonicalize restores it. */
 int mps_set_tensor(tdvp_mps mps, int site, const double* host, int chil, int chir);
+/* U(1) labels of the state: q_phys [d] the charge of each physical state,
+ * labels the concatenation of bonds 0..N, chi_j integers each, non-decreasing
+ * along every bond (a charge sector is a contiguous index range); bond j
+ * carries the charge of the block to its left, so site j may be non-zero
+ * only where q(a) + q(s) = q(b).  The caller guarantees that the tensors
+ * obey these rules (the U(1) kernels read only the allowed blocks).  Both
+ * NULL clears the labels; mps_set_tensor, mps_apply_site and a step with an
+ * MPO without charges also clear them.  Two-site steps in U(1) mode rewrite
+ * the labels of the bonds they truncate.  Errors: TDVP_E_ARG for unsorted
+ * labels or only one of the two arrays. */
+int mps_set_charges(tdvp_mps mps, const int* q_phys, const int* labels);
+/* The current labels (layout as mps_set_charges; sizes from mps_get_info);
+ * either output may be NULL.  TDVP_E_STATE if the state carries none. */
+int mps_get_charges(tdvp_mps mps, int* q_phys, int* labels);
 /* Right-orthonormalise sites N..2 by successive LQ decompositions; the
- * norm stays in site 1. */
+ * norm stays in site 1 (LQ keeps the U(1) block structure, so labels stay
+ * valid). */
 int mps_right_canonicalize(tdvp_ctx ctx, tdvp_mps mps);
 int mps_destroy(tdvp_mps mps);
 /* Apply the d x d operator op (host, complex128, op[s'][s] row-major) to

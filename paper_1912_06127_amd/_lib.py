@@ -84,6 +84,9 @@ SIGNATURES = {
     "mpo_get_info": (_I, [_P, _PI, _PI, _PI]),
     "mpo_get_tensor": (_I, [_P, _I, _PD]),
     "mpo_destroy": (_I, [_P]),
+    "mpo_set_charges": (_I, [_P, _PI]),
+    "mps_set_charges": (_I, [_P, _PI, _PI]),
+    "mps_get_charges": (_I, [_P, _PI, _PI]),
     "mps_init": (_I, [_P, _I, _I, _PI, _PI, C.c_uint64, C.POINTER(_P)]),
     "mps_get_info": (_I, [_P, _PI, _PI, _PI]),
     "mps_get_tensor": (_I, [_P, _I, _PD]),

@@ -403,6 +403,16 @@ class MPO:
         _check(ctx.handle, _lib.load().mpo_from_tensors(ctx.handle, N, d, _iptr(w), _dptr(flat), C.byref(h_)))
         return cls(ctx, h_)
 
+    def set_charges(self, charges):
+        """U(1) charges of the bond indices: a list of N+1 integer lists
+        (len w_j each, 0 on both boundary bonds); None clears them."""
+        if charges is None:
+            _check(self.ctx.handle, _lib.load().mpo_set_charges(self.handle, None))
+            return
+        assert [len(c) for c in charges] == self.w, "one charge per bond index"
+        flat = np.ascontiguousarray(np.concatenate([np.asarray(c, dtype=np.int32) for c in charges]))
+        _check(self.ctx.handle, _lib.load().mpo_set_charges(self.handle, _iptr(flat)))
+
     def tensor(self, site: int) -> np.ndarray:
         shape = (self.w[site], self.w[site + 1], self.d, self.d)
         out = np.zeros(shape, dtype=np.complex128)
@@ -460,6 +470,29 @@ class MPS:
         c = np.zeros(self.N + 1, dtype=np.int32)
         _check(self.ctx.handle, _lib.load().mps_get_info(self.handle, None, None, _iptr(c)))
         return [int(x) for x in c]
+
+    def set_charges(self, q_phys, labels):
+        """U(1) labels: q_phys [d] and one non-decreasing integer list per
+        bond (len chi_j each); (None, None) clears them."""
+        if q_phys is None and labels is None:
+            _check(self.ctx.handle, _lib.load().mps_set_charges(self.handle, None, None))
+            return
+        assert [len(q) for q in labels] == self.chi, "one label per bond index"
+        qp = np.ascontiguousarray(q_phys, dtype=np.int32)
+        flat = np.ascontiguousarray(np.concatenate([np.asarray(q, dtype=np.int32) for q in labels]))
+        _check(self.ctx.handle, _lib.load().mps_set_charges(self.handle, _iptr(qp), _iptr(flat)))
+
+    def charges(self):
+        """(q_phys, [labels of bond j for j = 0..N]) as held by the library."""
+        chi = self.chi
+        qp = np.zeros(self.d, dtype=np.int32)
+        flat = np.zeros(sum(chi), dtype=np.int32)
+        _check(self.ctx.handle, _lib.load().mps_get_charges(self.handle, _iptr(qp), _iptr(flat)))
+        out, o = [], 0
+        for c in chi:
+            out.append([int(x) for x in flat[o:o + c]])
+            o += c
+        return [int(x) for x in qp], out
 
     def tensor(self, site: int) -> np.ndarray:
         chi = self.chi

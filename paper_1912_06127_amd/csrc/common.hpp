@@ -362,6 +362,11 @@ struct CombineCoef {
 };
 void combine_args(double2* out, const double2* V, int64_t vstride, int nv, const double2* coef_host, int64_t n,
                   hipStream_t s);
+// Indexed 2-D copy of complex128: dst[dr[i]][dc[k]] = src[sr[i]][sc[k]] for
+// i < nr, k < nc (row-major, leading dimensions ldd / lds); a null index
+// array means the identity.  Index arrays are device int arrays.
+void copy_idx(double2* dst, int64_t ldd, const int* dr, const int* dc, const double2* src, int64_t lds,
+              const int* sr, const int* sc, int nr, int nc, hipStream_t s);
 // strided 2-D copy of complex128: dst[r*ldd + c] = src[r*lds + c] for c < cols;
 // mask: 0 none, 1 zero where c < r (keep upper), 2 zero where c > r (keep lower)
 void copy2d(double2* dst, int64_t ldd, const double2* src, int64_t lds, int rows, int cols,

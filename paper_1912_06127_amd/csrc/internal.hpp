@@ -174,6 +174,7 @@ struct tdvp_mpo_s {
     std::vector<std::vector<double>> host;        // c128 interleaved per site
     std::vector<tdvp::DevMem> dev128, dev64;      // device copies
     std::map<std::tuple<int, int, bool>, std::unique_ptr<tdvp::Mop>> mops;  // (kind, site, fp64)
+    std::vector<std::vector<int>> charge;         // U(1) charges of the MPO bonds [N+1][w_j] (empty: none)
     const tdvp::Mop& mop(int kind, int site, bool fp64);
     const void* W(int site, tdvp::Dt dt);
 };
@@ -189,6 +190,15 @@ struct tdvp_mps_s {
     tdvp::Dt env_dt = tdvp::Dt::C128;
     bool env_valid = false;
     std::vector<tdvp::DevMem> L, R;       // L[j]: [w_j][chi_j][chi_j], R[j]: [w_{j+1}][chi_{j+1}][chi_{j+1}]
+    // U(1) labels (empty: none): charge of each physical state and of each
+    // bond index, [N+1][chi_j], non-decreasing along every bond
+    std::vector<int> qphys;
+    std::vector<std::vector<int>> qbond;
+    bool has_charges() const { return !qbond.empty(); }
+    void clear_charges() {
+        qphys.clear();
+        qbond.clear();
+    }
     size_t tensor_elems(int j) const { return (size_t)chi[j] * d * chi[j + 1]; }
     void set_tensor_dev(int j, int chil, int chir);  // (re)allocate site j storage
 };

@@ -798,6 +798,16 @@ __global__ void combine_args_kernel(double2* out, const double2* V, int64_t vstr
     out[i] = make_double2(re, im);
 }
 
+__global__ void copy_idx_kernel(double2* dst, int64_t ldd, const int* dr, const int* dc, const double2* src,
+                                int64_t lds, const int* sr, const int* sc, int nr, int nc) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.y;
+    if (k >= nc || i >= nr) return;
+    const int64_t di = dr ? dr[i] : i, dk = dc ? dc[k] : k;
+    const int64_t si = sr ? sr[i] : i, sk = sc ? sc[k] : k;
+    dst[di * ldd + dk] = src[si * lds + sk];
+}
+
 __global__ void copy2d_kernel(double2* dst, int64_t ldd, const double2* src, int64_t lds, int rows,
                               int cols, int mask) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1369,6 +1379,15 @@ void combine_args(double2* out, const double2* V, int64_t vstride, int nv, const
     CombineCoef c{};
     for (int j = 0; j < nv; ++j) c.c[j] = coef_host[j];
     hipLaunchKernelGGL(combine_args_kernel, dim3(nblk(n)), dim3(kVecThreads), 0, s, out, V, vstride, nv, c, n);
+    TDVP_CHECK_HIP(hipGetLastError());
+}
+
+void copy_idx(double2* dst, int64_t ldd, const int* dr, const int* dc, const double2* src, int64_t lds,
+              const int* sr, const int* sc, int nr, int nc, hipStream_t s) {
+    if (nr == 0 || nc == 0) return;
+    TDVP_REQUIRE(nr <= 65535, TDVP_E_SHAPE, "copy_idx: too many rows");
+    dim3 grid((nc + 127) / 128, nr);
+    hipLaunchKernelGGL(copy_idx_kernel, grid, dim3(128), 0, s, dst, ldd, dr, dc, src, lds, sr, sc, nr, nc);
     TDVP_CHECK_HIP(hipGetLastError());
 }
 

@@ -1,6 +1,8 @@
 // MPO and MPS objects: construction, host transfer and canonical form.
 #include "internal.hpp"
 
+#include <algorithm>
+
 #include <cmath>
 
 namespace tdvp {
@@ -371,10 +373,61 @@ int mps_set_tensor(tdvp_mps mps, int site, const double* host, int chil, int chi
         mps->set_tensor_dev(site, chil, chir);
         mps->chi[site] = chil;
         mps->chi[site + 1] = chir;
+        mps->clear_charges();
         TDVP_CHECK_HIP(hipMemcpyAsync(mps->A[site].ptr, host, sizeof(double2) * (size_t)chil * mps->d * chir,
                                       hipMemcpyHostToDevice, mps->ctx->stream));
         TDVP_CHECK_HIP(hipStreamSynchronize(mps->ctx->stream));
         mps->env_valid = false;
+    });
+}
+
+int mps_set_charges(tdvp_mps mps, const int* q_phys, const int* labels) {
+    if (!mps) return TDVP_E_ARG;
+    return guarded(mps->ctx, [&] {
+        if (!q_phys && !labels) {
+            mps->clear_charges();
+            return;
+        }
+        TDVP_REQUIRE(q_phys && labels, TDVP_E_ARG, "mps_set_charges: q_phys and labels go together");
+        std::vector<std::vector<int>> q(mps->N + 1);
+        const int* p = labels;
+        for (int j = 0; j <= mps->N; ++j) {
+            q[j].assign(p, p + mps->chi[j]);
+            p += mps->chi[j];
+            for (int a = 1; a < mps->chi[j]; ++a)
+                TDVP_REQUIRE(q[j][a - 1] <= q[j][a], TDVP_E_ARG, "mps_set_charges: bond labels must be non-decreasing");
+        }
+        mps->qphys.assign(q_phys, q_phys + mps->d);
+        mps->qbond = std::move(q);
+    });
+}
+
+int mps_get_charges(tdvp_mps mps, int* q_phys, int* labels) {
+    if (!mps) return TDVP_E_ARG;
+    return guarded(mps->ctx, [&] {
+        TDVP_REQUIRE(mps->has_charges(), TDVP_E_STATE, "mps_get_charges: the state carries no charge labels");
+        if (q_phys) std::copy(mps->qphys.begin(), mps->qphys.end(), q_phys);
+        if (labels)
+            for (int j = 0; j <= mps->N; ++j) labels = std::copy(mps->qbond[j].begin(), mps->qbond[j].end(), labels);
+    });
+}
+
+int mpo_set_charges(tdvp_mpo mpo, const int* charges) {
+    if (!mpo) return TDVP_E_ARG;
+    return guarded(mpo->ctx, [&] {
+        if (!charges) {
+            mpo->charge.clear();
+            return;
+        }
+        std::vector<std::vector<int>> c(mpo->N + 1);
+        const int* p = charges;
+        for (int j = 0; j <= mpo->N; ++j) {
+            c[j].assign(p, p + mpo->w[j]);
+            p += mpo->w[j];
+        }
+        TDVP_REQUIRE(c[0].size() == 1 && c[mpo->N].size() == 1 && c[0][0] == 0 && c[mpo->N][0] == 0, TDVP_E_ARG,
+                     "mpo_set_charges: the boundary bonds must carry charge 0");
+        mpo->charge = std::move(c);
     });
 }
 

@@ -4,6 +4,8 @@
 // 1..j-1) and R_j (sites j+1..N) are cached on the MPS and updated one site
 // at a time (Sec. III A).
 #include "internal.hpp"
+#include <algorithm>
+#include <map>
 
 #include <chrono>
 #include <cmath>
@@ -39,6 +41,16 @@ int tdvp::truncation_rank(const std::vector<double>& s, const TruncRule& r, doub
     return chi;
 }
 
+// U(1) block-sparse contractions (u1.cpp); every tensor in precision dt,
+// charge labels on the host
+namespace tdvp {
+void heff_u1(tdvp_ctx ctx, int nsite, Dt dt, int chil, int chir, int d, int wl, int wm, int wr, const int* ql,
+             const int* qr, const int* qs, const int* cl, const int* cr, const void* L, const void* W1,
+             const void* W2, const void* R, const void* x, void* y);
+void env_u1(tdvp_ctx ctx, int dir, Dt dt, int chil, int chir, int d, int wl, int wr, const int* ql, const int* qr,
+            const int* qs, const int* cl, const int* cr, const void* env, const void* A, const void* W, void* out);
+}  // namespace tdvp
+
 namespace {
 
 struct Stepper {
@@ -50,6 +62,11 @@ struct Stepper {
     bool fp64;
     Dt edt;
     int form;
+    // U(1) mode: the state and the MPO carry charge labels; matvecs and
+    // environment updates visit only the charge-allowed blocks and the
+    // two-site splits decompose every charge sector of the middle bond
+    // separately (the labels of the new bond follow from the kept values)
+    bool u1 = false;
 
     Stepper(tdvp_ctx c, tdvp_mps mp, tdvp_mpo w, const tdvp_opts& opts, tdvp_stats& stats)
         : ctx(c), m(mp), W(w), o(opts), st(stats) {
@@ -66,6 +83,69 @@ struct Stepper {
             TDVP_REQUIRE(m->chi[j] <= (int64_t)m->d * m->chi[j + 1] &&
                              m->chi[j + 1] <= (int64_t)m->d * m->chi[j],
                          TDVP_E_SHAPE, "MPS bond dimensions are not consistent");
+        if (m->has_charges() && W->charge.empty()) m->clear_charges();  // a step without charges drops them
+        u1 = m->has_charges() && !W->charge.empty();
+        if (u1) {
+            TDVP_REQUIRE((int)m->qphys.size() == m->d && (int)m->qbond.size() == m->N + 1, TDVP_E_STATE,
+                         "U(1) labels do not match the state");
+            for (int j = 0; j <= m->N; ++j)
+                TDVP_REQUIRE((int)m->qbond[j].size() == m->chi[j] && (int)W->charge[j].size() == W->w[j],
+                             TDVP_E_STATE, "U(1) labels do not match the bond dimensions");
+        }
+    }
+
+    // --------------------------------------------------- U(1) contractions
+    // y = H_eff x (complex128 vectors) for the local problem of HeffArgs a at
+    // site j (two-site: sites j, j+1; zero-site: the bond after site j).
+    void heff_u1_apply(const HeffArgs& a, int j, const double2* x, double2* y) {
+        const int d = m->d;
+        const int D = a.nsite == 0 ? 1 : (a.nsite == 1 ? d : d * d);
+        const int64_t n = (int64_t)a.chil * D * a.chir;
+        const int *ql, *qr, *cl, *cr;
+        const void *W1 = nullptr, *W2 = nullptr;
+        int wm = a.wl;
+        if (a.nsite == 2) {
+            ql = m->qbond[j].data(); qr = m->qbond[j + 2].data();
+            cl = W->charge[j].data(); cr = W->charge[j + 2].data();
+            W1 = W->W(j, edt); W2 = W->W(j + 1, edt); wm = W->w[j + 1];
+        } else if (a.nsite == 1) {
+            ql = m->qbond[j].data(); qr = m->qbond[j + 1].data();
+            cl = W->charge[j].data(); cr = W->charge[j + 1].data();
+            W1 = W->W(j, edt);
+        } else {
+            ql = qr = m->qbond[j + 1].data();
+            cl = cr = W->charge[j + 1].data();
+        }
+        const int dd = a.nsite == 0 ? 1 : d;
+        if (edt == Dt::C128) {
+            heff_u1(ctx, a.nsite, edt, a.chil, a.chir, dd, a.wl, wm, a.wr, ql, qr, m->qphys.data(), cl, cr, a.L, W1, W2,
+                    a.R, x, y);
+            return;
+        }
+        void* xs = ctx->workspace("u1s_x", elem_bytes(edt) * (size_t)n);
+        void* ys = ctx->workspace("u1s_y", elem_bytes(edt) * (size_t)n);
+        convert(xs, edt, x, Dt::C128, n, ctx->stream);
+        heff_u1(ctx, a.nsite, edt, a.chil, a.chir, dd, a.wl, wm, a.wr, ql, qr, m->qphys.data(), cl, cr, a.L, W1, W2,
+                a.R, xs, ys);
+        convert(y, Dt::C128, ys, edt, n, ctx->stream);
+    }
+
+    // environment update across site j (dir +1: L[j+1] from L[j], -1: R[j-1] from R[j])
+    void env_u1_update(int dir, int j, const void* env_in, void* env_out) {
+        const int chil = m->chi[j], chir = m->chi[j + 1];
+        const void* Aj = m->A[j].ptr;
+        if (edt != Dt::C128) {
+            void* As = ctx->workspace("u1s_A", elem_bytes(edt) * m->tensor_elems(j));
+            convert(As, edt, Aj, Dt::C128, (int64_t)m->tensor_elems(j), ctx->stream);
+            Aj = As;
+        }
+        env_u1(ctx, dir, edt, chil, chir, m->d, W->w[j], W->w[j + 1], m->qbond[j].data(), m->qbond[j + 1].data(),
+               m->qphys.data(), W->charge[j].data(), W->charge[j + 1].data(), env_in, Aj, W->W(j, edt), env_out);
+    }
+
+    MatVec matvec(const HeffArgs& a, int j) {
+        if (u1) return [this, a, j](const double2* x, double2* y) { heff_u1_apply(a, j, x, y); };
+        return [this, a](const double2* x, double2* y) { heff_apply(ctx, a, x, Dt::C128, y, Dt::C128); };
     }
 
     size_t esz() const { return elem_bytes(edt); }
@@ -93,6 +173,11 @@ struct Stepper {
 
     void update_left(int j) {  // L[j+1] from L[j], A[j], W[j]
         env_buf(m->L[j + 1], (size_t)W->w[j + 1] * m->chi[j + 1] * m->chi[j + 1]);
+        if (u1) {
+            env_u1_update(1, j, m->L[j].ptr, m->L[j + 1].ptr);
+            st.flops += env_flops(m->chi[j], m->chi[j + 1], m->d, W->w[j], W->w[j + 1]);
+            return;
+        }
         EnvArgs a = env_args(j, &W->mop(1, j, fp64));
         env_left(ctx, a, m->L[j].ptr, edt, m->L[j + 1].ptr, edt);
         st.flops += env_flops(m->chi[j], m->chi[j + 1], m->d, W->w[j], W->w[j + 1]);
@@ -100,6 +185,11 @@ struct Stepper {
 
     void update_right(int j) {  // R[j-1] from R[j], A[j], W[j]
         env_buf(m->R[j - 1], (size_t)W->w[j] * m->chi[j] * m->chi[j]);
+        if (u1) {
+            env_u1_update(-1, j, m->R[j].ptr, m->R[j - 1].ptr);
+            st.flops += env_flops(m->chi[j], m->chi[j + 1], m->d, W->w[j], W->w[j + 1]);
+            return;
+        }
         EnvArgs a = env_args(j, &W->mop(3, j, fp64));
         env_right(ctx, a, m->R[j].ptr, edt, m->R[j - 1].ptr, edt);
         st.flops += env_flops(m->chi[j], m->chi[j + 1], m->d, W->w[j], W->w[j + 1]);
@@ -117,12 +207,12 @@ struct Stepper {
     }
 
     // theta <- exp(-i tau H) theta for the local operator described by a.
-    void evolve(const HeffArgs& a, double2* theta, double tau) {
+    void evolve(const HeffArgs& a, int j, double2* theta, double tau) {
         TxRange tx("expm");
         const int D = a.nsite == 0 ? 1 : (a.nsite == 1 ? m->d : m->d * m->d);
         const int64_t n = (int64_t)a.chil * D * a.chir;
         const double f = heff_flops(a.nsite, a.chil, a.chir, m->d, a.wl, a.wr);
-        MatVec op = [&](const double2* x, double2* y) { heff_apply(ctx, a, x, Dt::C128, y, Dt::C128); };
+        MatVec op = matvec(a, j);
         KrylovInfo ki = o.exp_method == 1
                             ? expm_taylor(ctx, op, theta, n, tau, std::max(0x1p-53, o.krylov_tol), o.imaginary != 0)
                             : expm_krylov(ctx, op, theta, n, tau, o.krylov_max, o.krylov_tol, o.imaginary != 0);
@@ -136,11 +226,11 @@ struct Stepper {
     }
 
     // theta <- lowest Ritz vector of the local operator (normalised); returns its Ritz value.
-    double ground(const HeffArgs& a, double2* theta) {
+    double ground(const HeffArgs& a, int j, double2* theta) {
         const int D = a.nsite == 0 ? 1 : (a.nsite == 1 ? m->d : m->d * m->d);
         const int64_t n = (int64_t)a.chil * D * a.chir;
         const double f = heff_flops(a.nsite, a.chil, a.chir, m->d, a.wl, a.wr);
-        MatVec op = [&](const double2* x, double2* y) { heff_apply(ctx, a, x, Dt::C128, y, Dt::C128); };
+        MatVec op = matvec(a, j);
         double e = 0.0;
         KrylovInfo ki = ground_krylov(ctx, op, theta, n, o.krylov_max, o.krylov_tol, &e);
         st.matvecs += ki.matvecs;
@@ -179,11 +269,14 @@ struct Stepper {
     // ------------------------------------------------------------- 1TDVP
     void step1(double dt) {
         TxRange tx("tdvp1_step");
+        // the gauge moves of the one-site step are dense QR / LQ, which mix
+        // charge sectors (a column's pivot row may carry another charge)
+        TDVP_REQUIRE(!u1, TDVP_E_ARG, "one-site steps do not run in U(1) mode: clear the state's charge labels first");
         const int N = m->N, d = m->d;
         const double tau = dt / 2.0;
         ensure_envs();
         for (int j = 0; j + 1 < N; ++j) {
-            evolve(h1(j), A(j), tau);
+            evolve(h1(j), j, A(j), tau);
             const int rows = m->chi[j] * d, cols = m->chi[j + 1];
             double2* Q = static_cast<double2*>(ctx->workspace("t1_Q", sizeof(double2) * (size_t)rows * cols));
             double2* C = static_cast<double2*>(ctx->workspace("t1_C", sizeof(double2) * (size_t)cols * cols));
@@ -191,14 +284,14 @@ struct Stepper {
             TDVP_CHECK_HIP(hipMemcpyAsync(A(j), Q, sizeof(double2) * (size_t)rows * cols,
                                           hipMemcpyDeviceToDevice, ctx->stream));
             update_left(j);
-            evolve(h0(j), C, -tau);
+            evolve(h0(j), j, C, -tau);
             const int n2 = d * m->chi[j + 2];
             double2* T = static_cast<double2*>(ctx->workspace("t1_T", sizeof(double2) * (size_t)cols * n2));
             zgemm_rowmajor(ctx, C, A(j + 1), T, cols, cols, n2);
             TDVP_CHECK_HIP(hipMemcpyAsync(A(j + 1), T, sizeof(double2) * (size_t)cols * n2,
                                           hipMemcpyDeviceToDevice, ctx->stream));
         }
-        evolve(h1(N - 1), A(N - 1), dt);  // merged turning point
+        evolve(h1(N - 1), N - 1, A(N - 1), dt);  // merged turning point
         for (int j = N - 1; j >= 1; --j) {
             const int rows = m->chi[j], cols = d * m->chi[j + 1];
             double2* Lf = static_cast<double2*>(ctx->workspace("t1_C", sizeof(double2) * (size_t)rows * rows));
@@ -207,13 +300,13 @@ struct Stepper {
             TDVP_CHECK_HIP(hipMemcpyAsync(A(j), Q, sizeof(double2) * (size_t)rows * cols,
                                           hipMemcpyDeviceToDevice, ctx->stream));
             update_right(j);
-            evolve(h0(j - 1), Lf, -tau);
+            evolve(h0(j - 1), j - 1, Lf, -tau);
             const int m1 = m->chi[j - 1] * d;
             double2* T = static_cast<double2*>(ctx->workspace("t1_T", sizeof(double2) * (size_t)m1 * rows));
             zgemm_rowmajor(ctx, A(j - 1), Lf, T, m1, rows, rows);
             TDVP_CHECK_HIP(hipMemcpyAsync(A(j - 1), T, sizeof(double2) * (size_t)m1 * rows,
                                           hipMemcpyDeviceToDevice, ctx->stream));
-            evolve(h1(j - 1), A(j - 1), tau);
+            evolve(h1(j - 1), j - 1, A(j - 1), tau);
         }
     }
 
@@ -232,7 +325,115 @@ struct Stepper {
 
     // Split of theta into sites j, j+1 (Fig. postupdate); centre_left puts the
     // singular values into site j, otherwise into site j+1.
+    // U(1) split of theta into sites j, j+1: rows (a, s1) carry q(a) + q(s1),
+    // columns (s2, b) carry q(b) - q(s2), and theta connects only equal
+    // charges (the charge of the new bond index).  Every charge sector is
+    // decomposed by its own SVD; the singular values of all sectors are
+    // truncated together by the rule of the dense split (Eq. discweight), and
+    // the kept ones, ordered by charge (then by value), label the new bond.
+    void split_u1(int j, double2* th, bool centre_left) {
+        TxRange tx("split_u1");
+        const int d = m->d, chil = m->chi[j], chir = m->chi[j + 2];
+        const int rows = chil * d, cols = d * chir;
+        const std::vector<int>& qa = m->qbond[j];
+        const std::vector<int>& qb = m->qbond[j + 2];
+        const std::vector<int>& qs = m->qphys;
+        std::map<int, std::vector<int>> rsec, csec;
+        for (int a = 0; a < chil; ++a)
+            for (int s1 = 0; s1 < d; ++s1) rsec[qa[a] + qs[s1]].push_back(a * d + s1);
+        for (int s2 = 0; s2 < d; ++s2)
+            for (int b = 0; b < chir; ++b) csec[qb[b] - qs[s2]].push_back(s2 * chir + b);
+        struct Sec {
+            int Q;
+            const std::vector<int>* r;
+            const std::vector<int>* c;
+            int k, off;
+            int64_t ri, ci;  // offsets of the index lists in the device table
+            std::vector<double> s;
+        };
+        std::vector<Sec> secs;
+        std::vector<int> idx;  // row lists, then column lists
+        int ktot = 0;
+        for (const auto& kv : rsec) {
+            auto it = csec.find(kv.first);
+            if (it == csec.end()) continue;
+            Sec sc{kv.first, &kv.second, &it->second, 0, ktot, 0, 0, {}};
+            sc.k = std::min((int)kv.second.size(), (int)it->second.size());
+            sc.ri = (int64_t)idx.size();
+            idx.insert(idx.end(), kv.second.begin(), kv.second.end());
+            sc.ci = (int64_t)idx.size();
+            idx.insert(idx.end(), it->second.begin(), it->second.end());
+            ktot += sc.k;
+            secs.push_back(sc);
+        }
+        TDVP_REQUIRE(ktot > 0, TDVP_E_NUMERIC, "U(1) split: no charge sector connects the two sites");
+        const int64_t nidx = (int64_t)idx.size();
+        int* didx = static_cast<int*>(ctx->workspace("u1s_idx", sizeof(int) * (size_t)(nidx + 2 * (int64_t)ktot)));
+        double2* Uall = static_cast<double2*>(ctx->workspace("u1s_Uall", sizeof(double2) * (size_t)rows * ktot));
+        double2* Vall = static_cast<double2*>(ctx->workspace("u1s_Vall", sizeof(double2) * (size_t)ktot * cols));
+        TDVP_CHECK_HIP(hipMemcpyAsync(didx, idx.data(), sizeof(int) * nidx, hipMemcpyHostToDevice, ctx->stream));
+        TDVP_CHECK_HIP(hipMemsetAsync(Uall, 0, sizeof(double2) * (size_t)rows * ktot, ctx->stream));
+        TDVP_CHECK_HIP(hipMemsetAsync(Vall, 0, sizeof(double2) * (size_t)ktot * cols, ctx->stream));
+        for (auto& sc : secs) {
+            const int nr = (int)sc.r->size(), nc = (int)sc.c->size();
+            double2* blk = static_cast<double2*>(ctx->workspace("u1s_blk", sizeof(double2) * (size_t)nr * nc));
+            copy_idx(blk, nc, nullptr, nullptr, th, cols, didx + sc.ri, didx + sc.ci, nr, nc, ctx->stream);
+            SvdResult r = svd_rowmajor(ctx, blk, nr, nc);
+            TDVP_REQUIRE(r.k == sc.k, TDVP_E_STATE, "U(1) split: unexpected sector rank");
+            // U_Q into the sector's rows of Uall, Vh_Q into its columns of Vall
+            copy_idx(Uall + sc.off, ktot, didx + sc.ri, nullptr, r.U, r.k, nullptr, nullptr, nr, sc.k, ctx->stream);
+            copy_idx(Vall + (int64_t)sc.off * cols, cols, nullptr, didx + sc.ci, r.Vh, nc, nullptr, nullptr, sc.k, nc,
+                     ctx->stream);
+            sc.s = r.S;
+        }
+        // all singular values, largest first, for the truncation rule
+        std::vector<std::pair<double, std::pair<int, int>>> all;  // (s, (sector, index))
+        for (int q = 0; q < (int)secs.size(); ++q)
+            for (int i = 0; i < secs[q].k; ++i) all.push_back({secs[q].s[i], {q, i}});
+        std::stable_sort(all.begin(), all.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
+        std::vector<double> sv(all.size());
+        for (size_t i = 0; i < all.size(); ++i) sv[i] = all[i].first;
+        double w = 0.0;
+        const int chi = trunc_rank(sv, w);
+        // kept values ordered by sector charge (sectors are in ascending charge), then by value
+        std::vector<std::pair<int, int>> kept(chi);
+        for (int c = 0; c < chi; ++c) kept[c] = all[c].second;
+        std::stable_sort(kept.begin(), kept.end(), [](const auto& x, const auto& y) {
+            return x.first != y.first ? x.first < y.first : x.second < y.second;
+        });
+        std::vector<int> src(chi), labels(chi);
+        std::vector<double> skept(chi);
+        for (int c = 0; c < chi; ++c) {
+            const Sec& sc = secs[kept[c].first];
+            src[c] = sc.off + kept[c].second;
+            labels[c] = sc.Q;
+            skept[c] = sc.s[kept[c].second];
+        }
+        for (double v : skept)
+            TDVP_REQUIRE(v > 0.0 && std::isfinite(v), TDVP_E_NUMERIC, "U(1) split: a kept singular value is zero or not finite");
+        int* dsrc = didx + nidx;
+        double* dS = static_cast<double*>(ctx->workspace("u1s_S", sizeof(double) * (size_t)chi));
+        double2* U = static_cast<double2*>(ctx->workspace("u1s_U", sizeof(double2) * (size_t)rows * chi));
+        double2* Vh = static_cast<double2*>(ctx->workspace("u1s_Vh", sizeof(double2) * (size_t)chi * cols));
+        TDVP_CHECK_HIP(hipMemcpyAsync(dsrc, src.data(), sizeof(int) * chi, hipMemcpyHostToDevice, ctx->stream));
+        TDVP_CHECK_HIP(hipMemcpyAsync(dS, skept.data(), sizeof(double) * chi, hipMemcpyHostToDevice, ctx->stream));
+        copy_idx(U, chi, nullptr, nullptr, Uall, ktot, nullptr, dsrc, rows, chi, ctx->stream);
+        copy_idx(Vh, cols, nullptr, nullptr, Vall, cols, dsrc, nullptr, chi, cols, ctx->stream);
+        if (centre_left) scale_cols(U, chi, dS, rows, chi, ctx->stream);
+        else scale_rows(Vh, cols, dS, chi, cols, ctx->stream);
+        store_site(j, U, m->chi[j], chi, rows, chi, chi);
+        store_site(j + 1, Vh, chi, m->chi[j + 2], chi, cols, cols);
+        TDVP_CHECK_HIP(hipStreamSynchronize(ctx->stream));  // host vectors above go out of scope
+        st.w_step += w;
+        m->chi[j + 1] = chi;
+        m->qbond[j + 1] = labels;
+    }
+
     void split(int j, double2* th, bool centre_left) {
+        if (u1) {
+            split_u1(j, th, centre_left);
+            return;
+        }
         TxRange tx("split");
         const int d = m->d;
         const int rows = m->chi[j] * d, cols = d * m->chi[j + 2];
@@ -285,22 +486,22 @@ struct Stepper {
         ensure_envs();
         for (int j = 0; j + 2 < N; ++j) {
             double2* th = form_theta(j);
-            evolve(h2(j), th, tau);
+            evolve(h2(j), j, th, tau);
             split(j, th, false);
             update_left(j);
-            evolve(h1(j + 1), A(j + 1), -tau);
+            evolve(h1(j + 1), j + 1, A(j + 1), -tau);
         }
         {
             const int j = N - 2;
             double2* th = form_theta(j);
-            evolve(h2(j), th, dt);  // right-most pair once by the full step
+            evolve(h2(j), j, th, dt);  // right-most pair once by the full step
             split(j, th, true);
             update_right(j + 1);
         }
         for (int j = N - 3; j >= 0; --j) {
-            evolve(h1(j + 1), A(j + 1), -tau);
+            evolve(h1(j + 1), j + 1, A(j + 1), -tau);
             double2* th = form_theta(j);
-            evolve(h2(j), th, tau);
+            evolve(h2(j), j, th, tau);
             split(j, th, true);
             update_right(j + 1);
         }
@@ -318,20 +519,20 @@ struct Stepper {
         double e = 0.0;
         for (int j = 0; j + 2 < N; ++j) {
             double2* th = form_theta(j);
-            e = ground(h2(j), th);
+            e = ground(h2(j), j, th);
             split(j, th, false);
             update_left(j);
         }
         {
             const int j = N - 2;
             double2* th = form_theta(j);
-            e = ground(h2(j), th);
+            e = ground(h2(j), j, th);
             split(j, th, true);
             update_right(j + 1);
         }
         for (int j = N - 3; j >= 0; --j) {
             double2* th = form_theta(j);
-            e = ground(h2(j), th);
+            e = ground(h2(j), j, th);
             split(j, th, true);
             update_right(j + 1);
         }
@@ -622,6 +823,7 @@ int mps_apply_site(tdvp_ctx ctx, tdvp_mps mps, int site, const double* op) {
         apply_site(mps->A[site].as<double2>(), O, mps->chi[site], d, mps->chi[site + 1], ctx->stream);
         TDVP_CHECK_HIP(hipStreamSynchronize(ctx->stream));  // op lives in caller memory
         mps->env_valid = false;
+        mps->clear_charges();  // op need not conserve the charge
     });
 }
 

@@ -1,0 +1,137 @@
+"""U(1) time stepping: two-site TDVP and DMRG with charge labels on the
+state and the MPO (block-sparse matvecs and environment updates, two-site
+splits sector by sector with one truncation over all sectors) against the
+dense oracle on the same S^z-conserving quench (Sec. IV: long-range XXX,
+Neel state with one flipped spin; Supplemental Material, Implementation:
+U(1) symmetric tensors).  The U(1) run must give the dense run's
+observables, bond dimensions and discarded weight, and every site tensor
+must obey the charge rule of its labels.
+
+Charges: q(up) = 1, q(down) = 0; bond j of the product state carries the
+number of up spins left of it; an MPO bond index carries the charge of the
+operator placed so far (sigma+ : +1, sigma- : -1, sigma^z : 0)."""
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import mpo as ompo
+from oracle import mps as omps
+from oracle import spin
+from oracle import tdvp as otdvp
+
+pytestmark = pytest.mark.gpu
+
+OBS_TOL = {"c128": 1e-10, "c64": 1e-4}
+Q_SPIN = [1, 0]  # up, down
+SP = np.array([[0, 1], [0, 0]], dtype=np.complex128)
+SM = SP.T.copy()
+SZ = np.diag([1.0, -1.0]).astype(np.complex128)
+PAIRS = [(0.5, SP, SM), (0.5, SM, SP), (0.25, SZ, SZ)]  # 1/4 (xx + yy + zz)
+OP_CHARGE = [1, -1, 0]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1912_06127_amd as pkg
+    c = pkg.Context(0)
+    yield c
+    c.sync()
+    c.close()
+
+
+def setup(ctx, N, K):
+    import paper_1912_06127_amd as pkg
+    c, lam, _ = ompo.fit_exponentials(1.0 / np.arange(1, N) ** 2.0, K)
+    W = pkg.MPO.longrange(ctx, N, PAIRS, c=c, lam=lam)
+    inner = [0] + [q for q in OP_CHARGE for _ in range(K)] + [0]
+    W.set_charges([[0]] + [inner] * (N - 1) + [[0]])
+    Ws = ompo.mpo_exponentials(N, c, lam, PAIRS)
+    bits = [i % 2 for i in range(N)]
+    bits[N // 2] ^= 1
+    return W, Ws, bits
+
+
+def product_labels(bits):
+    up = np.cumsum([0] + [1 - b for b in bits])
+    return [[int(u)] for u in up]
+
+
+def check_charge_rule(m):
+    q_phys, labels = m.charges()
+    for j in range(m.N):
+        A = m.tensor(j)
+        assert all(np.diff(labels[j]) >= 0)
+        allowed = (np.add.outer(labels[j], q_phys)[:, :, None] == np.asarray(labels[j + 1])[None, None, :])
+        assert np.max(np.abs(A[~allowed]), initial=0.0) == 0.0, j
+
+
+@pytest.mark.parametrize("dt_", ["c128", "c64"])
+def test_u1_two_site_quench_matches_dense_oracle(ctx, dt_):
+    import paper_1912_06127_amd as pkg
+    N = 12
+    W, Ws, bits = setup(ctx, N, 3)
+    m = pkg.MPS.init(ctx, N, 2, [1] * (N + 1), basis_state=bits)
+    m.set_charges(Q_SPIN, product_labels(bits))
+    st_o = otdvp.MPSState(omps.padded_product_state(bits, [1] * (N + 1)), Ws)
+    tr = otdvp.Truncation(chi_max=16, w_max=1e-8, eps=1e-12)
+    opts = pkg.TDVPOptions(compute=dt_, chi_max=16, w_max=1e-8, eps_rel=1e-12)
+    for s in range(8):
+        print(f"U(1) 2TDVP step {s} {dt_}", flush=True)
+        otdvp.tdvp2_step(st_o, 0.05, tr)
+        info = pkg.tdvp2_step(ctx, m, W, 0.05, opts)
+        z = pkg.expect(ctx, m, list(range(N)), spin.SZ).real
+        zref = omps.expect_sites(st_o.T, spin.SZ).real
+        assert np.max(np.abs(z - zref)) <= OBS_TOL[dt_], (s, np.max(np.abs(z - zref)))
+        if dt_ == "c128":
+            assert m.chi == [1] + [A.shape[2] for A in st_o.T], s
+    if dt_ == "c128":
+        assert abs(info["w_total"] - st_o.stats.w_total) <= 1e-12
+    check_charge_rule(m)
+    # the labels still sum to the conserved charge of the state
+    assert m.charges()[1][N] == [int(np.sum(1 - np.asarray(bits)))]
+
+
+def test_u1_dmrg_and_one_site_refusal(ctx):
+    """Two-site DMRG in U(1) mode reaches the dense oracle's ground energy
+    in the labelled sector; a one-site step refuses U(1) mode (its dense QR /
+    LQ would mix the sectors) and runs once the labels are cleared."""
+    import paper_1912_06127_amd as pkg
+    N = 8
+    W, Ws, bits = setup(ctx, N, 2)
+    m = pkg.MPS.init(ctx, N, 2, [1] * (N + 1), basis_state=bits)
+    m.set_charges(Q_SPIN, product_labels(bits))
+    opts = pkg.TDVPOptions(compute="c128", chi_max=32, eps_rel=1e-14, krylov_max=40, krylov_tol=1e-12)
+    e = None
+    for _ in range(6):
+        e = pkg.dmrg2_sweep(ctx, m, W, opts)["energy"]
+    H = ompo.mpo_to_dense(Ws)
+    # the lowest eigenvalue of H inside the sector of the initial charge
+    n_up = int(np.sum(1 - np.asarray(bits)))
+    basis = np.array([bin(i).count("1") for i in range(2 ** N)])  # bit 1 = down (index 1) in the dense order
+    sector = (N - basis) == n_up
+    e_ref = np.linalg.eigvalsh(H[np.ix_(sector, sector)])[0]
+    assert abs(e - e_ref) <= 1e-9, (e, e_ref)
+    check_charge_rule(m)
+    with pytest.raises(pkg.TDVPError):
+        pkg.tdvp1_step(ctx, m, W, 0.05, opts)
+    m.set_charges(None, None)
+    pkg.tdvp1_step(ctx, m, W, 0.05, opts)
+
+
+def test_labels_are_validated_and_cleared(ctx):
+    import paper_1912_06127_amd as pkg
+    N = 6
+    W, _, bits = setup(ctx, N, 2)
+    m = pkg.MPS.init(ctx, N, 2, wl.full_rank_bonds(N, 2, 2), seed=3)
+    bad = [[0]] + [[1, 0]] + [[0, 1]] * (N - 2) + [[0]]  # bond 1 not sorted
+    with pytest.raises(pkg.TDVPError):
+        m.set_charges(Q_SPIN, bad)
+    # an MPO whose boundary bond carries a charge is refused
+    with pytest.raises(pkg.TDVPError):
+        W.set_charges([[1]] + [[0] * w for w in W.w[1:-1]] + [[0]])
+    p = pkg.MPS.init(ctx, N, 2, [1] * (N + 1), basis_state=bits)
+    p.set_charges(Q_SPIN, product_labels(bits))
+    assert p.charges()[1] == product_labels(bits)
+    p.set_tensor(0, p.tensor(0))  # replacing a tensor drops the labels
+    with pytest.raises(pkg.TDVPError):
+        p.charges()
