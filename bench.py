@@ -313,6 +313,61 @@ def sweep_timing(pkg, ctx, steps=40, taylor=True):
     return res
 
 
+def sweep_u1_timing(pkg, ctx, steps=40):
+    """The N = 64 XXX quench of the sweep workload in the U(1) form: the MPO
+    written with sigma+ sigma- + sigma- sigma+ (+ sigma^z sigma^z) channels, each
+    of definite charge, run once dense and once with charge labels on the state
+    and the MPO (splits sector by sector; matvecs and environments on the
+    block kernels from chi_l * chi_r >= 256^2 on, "u1", or always,
+    "u1_blocks"), complex64 contractions.  Each mode runs an untimed pass (GEMM
+    autotuning) and a timed pass; the spin profiles at the end are compared."""
+    import numpy as np
+    N, cap, K = 64, 512, 6
+    c, lam, _ = pkg.fit.fit_power_law(2.0, K, N - 1)
+    sp = np.array([[0, 1], [0, 0]], dtype=np.complex128)
+    sm = sp.T.copy()
+    sz = np.array(pkg.PAULI_Z, dtype=np.complex128)
+    mpo = pkg.MPO.longrange(ctx, N, [(0.5, sp, sm), (0.5, sm, sp), (0.25, sz, sz)], c=c, lam=lam)
+    inner = [0] + [1] * K + [-1] * K + [0] * K + [0]
+    bits = [j % 2 for j in range(N)]
+    bits[31] ^= 1
+    up = np.cumsum([0] + [1 - b for b in bits])
+    labels = [[int(u)] for u in up]
+    opts = pkg.TDVPOptions(compute="c64", chi_max=cap, w_max=1e-8, eps_rel=1e-12, krylov_max=40, krylov_tol=1e-10)
+    res, prof = {}, {}
+    for mode in ("dense", "u1", "u1_blocks"):
+        mpo.set_charges([[0]] + [inner] * (N - 1) + [[0]] if mode != "dense" else None)
+        opts.u1_block_min = 1 if mode == "u1_blocks" else 0
+        for timed in (False, True):
+            mps = pkg.MPS.init(ctx, N, 2, [1] * (N + 1), basis_state=bits)
+            if mode != "dense":
+                mps.set_charges([1, 0], labels)
+            times, mv, wt = [], 0, 0.0
+            for k in range(steps):
+                st = pkg.tdvp2_step(ctx, mps, mpo, 0.05, opts)
+                times.append(st["seconds"])
+                mv += st["matvecs"]
+                wt = st["w_total"]
+                if (k + 1) % 10 == 0:
+                    progress(f"sweep {mode} {'timed' if timed else 'tuning'} pass: step {k + 1}, "
+                             f"{times[-1]:.3f} s, chi_max {max(mps.chi)}")
+            if timed:
+                prof[mode] = 0.25 * pkg.expect(ctx, mps, list(range(N)), sz).real
+                res[mode] = {"s_per_step": round(float(np.mean(times)), 4),
+                             "s_per_step_last10": round(float(np.mean(times[-10:])), 4),
+                             "matvecs_per_step": mv / steps, "chi_peak": max(mps.chi), "w_total": wt}
+                if mode != "dense":
+                    res[mode]["sectors_at_centre"] = len(set(mps.charges()[1][N // 2]))
+            mps.close()
+    mpo.close()
+    for mode in ("u1", "u1_blocks"):
+        res[f"speedup_{mode}_vs_dense"] = round(res["dense"]["s_per_step"] / res[mode]["s_per_step"], 2)
+        res[f"max_abs_obs_diff_{mode}_vs_dense"] = float(np.max(np.abs(prof[mode] - prof["dense"])))
+    res["workload"] = ("2TDVP quench, N=64 XXX 1/r^2 in sigma+- form (K=6, w=20), Neel + flip at site 32, "
+                       f"dt=0.05, {steps} steps, w_max=1e-8, eps=1e-12, chi_max=512, complex64; dense vs U(1)")
+    return res
+
+
 def segments_timing(pkg, ctx, np, graph=True, extras=True):
     """Segment-parallel 2TDVP, N=201 long-range XY (alpha 1.5, K = 6, w = 14),
     32 segments (11 | 6 x 30 | 10), uneven bond profile (one seeded draw in
@@ -506,6 +561,8 @@ def u1_timing(pkg, ctx, torch, np, chi=512, K=6, reps=10):
     return {"dense_ms": round(dense_ms, 3), "u1_kernel_ms": round(kern_ms, 3), "u1_wall_ms": round(wall_ms, 3),
             "speedup_kernel": round(dense_ms / kern_ms, 2), "speedup_wall": round(dense_ms / wall_ms, 2),
             "dense_flops": heff2_flops(chi, 20), "block_gemm_flops": block_flops, "sectors_left": nsec,
+            "u1_kernel_ms_by_kernel": {k: round(v["ms"] / reps, 4) for k, v in prof.items()},
+            "u1_launches_per_call": sum(v["count"] for v in prof.values()) / reps,
             "workload": f"two-site H_eff, chi={chi} both bonds, XXX K={K} (w=20), complex64, S^z sectors "
                         f"(Gaussian profile, spread 2.5), dense path vs U(1) blocks"}
 
@@ -545,6 +602,8 @@ def main():
                     help="run only the N=64 2TDVP quench sweep and print its timings (for profiling)")
     ap.add_argument("--grad-steps", type=int, default=2)
     ap.add_argument("--only-u1", action="store_true", help="run only the U(1) block-sparse H_eff timing")
+    ap.add_argument("--only-sweep-u1", action="store_true",
+                    help="run only the N=64 quench sweep dense against U(1) blocks and print its timings")
     ap.add_argument("--only-D", type=int, default=0,
                     help="run only the two-site H_eff timing at this bond dimension (both precisions; for profiling)")
     ap.add_argument("--only-grad", action="store_true",
@@ -572,7 +631,13 @@ def main():
 
     if args.only_u1:
         ctx = pkg.Context(0)
-        print(json.dumps({"u1": u1_timing(pkg, ctx, torch, np)}))
+        print(json.dumps({"u1": {str(chi): u1_timing(pkg, ctx, torch, np, chi=chi) for chi in (64, 128, 256, 512)}}))
+        ctx.close()
+        return
+
+    if args.only_sweep_u1:
+        ctx = pkg.Context(0)
+        print(json.dumps({"sweep_u1": sweep_u1_timing(pkg, ctx, args.sweep_steps)}))
         ctx.close()
         return
 
@@ -694,6 +759,9 @@ def main():
             line["segments"] = segments_timing(pkg, ctx, np)
         progress("U(1) block-sparse H_eff at chi = 512")
         line["u1"] = u1_timing(pkg, ctx, torch, np)
+        if args.sweep_steps > 0:
+            progress("2TDVP sweep, dense against U(1) blocks")
+            line["sweep_u1"] = sweep_u1_timing(pkg, ctx, args.sweep_steps)
         if args.grad_steps > 0:
             progress("differentiable 1TDVP timing")
             line["gradient"] = gradient_timing(pkg, ctx, torch, np, args.grad_steps)

@@ -257,6 +257,15 @@ typedef struct {
                             krylov_max does not apply; TDVP_E_ARG if |dt| ||H_eff||
                             would need more than 1e5 scaling steps.  TDVP_E_ARG for
                             other values. */
+    int u1_block_min;    /* U(1) mode (charge labels on the state and the MPO):
+                            local problems and environment updates with
+                            chi_left * chi_right >= u1_block_min run on the
+                            block-sparse kernels, smaller ones on the dense
+                            kernels, which keep the blocks exactly (an entry
+                            outside them is a sum of products with a zero factor);
+                            the splits are sector by sector either way.  0 =
+                            default (256 * 256), 1 = always blocks; TDVP_E_ARG
+                            if negative. */
 } tdvp_opts;
 
 typedef struct {

@@ -34,7 +34,7 @@ class Opts(C.Structure):
         ("compute", C.c_int), ("krylov_max", C.c_int), ("krylov_tol", C.c_double),
         ("chi_max", C.c_int), ("w_max", C.c_double), ("eps_rel", C.c_double),
         ("multiplet_guard", C.c_int), ("strict", C.c_int), ("gemm_form", C.c_int),
-        ("svd_mode", C.c_int), ("imaginary", C.c_int), ("exp_method", C.c_int),
+        ("svd_mode", C.c_int), ("imaginary", C.c_int), ("exp_method", C.c_int), ("u1_block_min", C.c_int),
     ]
 
 

@@ -548,6 +548,7 @@ class TDVPOptions:
     svd_mode: int = 0           # 1 SVD, 2 density-matrix eigen-decomposition, 0 automatic
     imaginary: bool = False     # imaginary time: exp(-dt H), state renormalised after each step
     exp_method: str = "lanczos"  # local exponentials: "lanczos" or "taylor" (Al-Mohy-Higham)
+    u1_block_min: int = 0       # U(1) mode: block kernels when chi_l * chi_r >= this (0: 256^2, 1: always)
 
     def to_c(self) -> Opts:
         o = Opts()
@@ -565,6 +566,7 @@ class TDVPOptions:
         if self.exp_method not in ("lanczos", "taylor"):
             raise ValueError(f"exp_method must be 'lanczos' or 'taylor', not {self.exp_method!r}")
         o.exp_method = 1 if self.exp_method == "taylor" else 0
+        o.u1_block_min = self.u1_block_min
         return o
 
 

@@ -205,6 +205,7 @@ int tdvp_opts_default(tdvp_opts* o) {
     o->exp_method = 0;
     o->gemm_form = 0;
     o->svd_mode = 0;
+    o->u1_block_min = 0;
     return TDVP_OK;
 }
 

@@ -67,6 +67,7 @@ struct Stepper {
     // two-site splits decompose every charge sector of the middle bond
     // separately (the labels of the new bond follow from the kept values)
     bool u1 = false;
+    int64_t u1_min = 0;  // chi_left * chi_right from which U(1) mode uses the block kernels
 
     Stepper(tdvp_ctx c, tdvp_mps mp, tdvp_mpo w, const tdvp_opts& opts, tdvp_stats& stats)
         : ctx(c), m(mp), W(w), o(opts), st(stats) {
@@ -78,6 +79,8 @@ struct Stepper {
         TDVP_REQUIRE(opts.krylov_max >= 1, TDVP_E_ARG, "krylov_max must be >= 1");
         TDVP_REQUIRE(opts.chi_max >= 1, TDVP_E_ARG, "chi_max must be >= 1");
         TDVP_REQUIRE(opts.exp_method == 0 || opts.exp_method == 1, TDVP_E_ARG, "exp_method must be 0 or 1");
+        TDVP_REQUIRE(opts.u1_block_min >= 0, TDVP_E_ARG, "u1_block_min must be >= 0");
+        u1_min = opts.u1_block_min == 0 ? 256 * 256 : opts.u1_block_min;
         TDVP_REQUIRE(m->N == W->N && m->d == W->d, TDVP_E_SHAPE, "MPS and MPO sizes differ");
         for (int j = 0; j < m->N; ++j)
             TDVP_REQUIRE(m->chi[j] <= (int64_t)m->d * m->chi[j + 1] &&
@@ -143,8 +146,14 @@ struct Stepper {
                m->qphys.data(), W->charge[j].data(), W->charge[j + 1].data(), env_in, Aj, W->W(j, edt), env_out);
     }
 
+    // U(1) mode on a local problem of these bond dimensions: block kernels
+    // from u1_min on; below it the dense kernels, which keep every entry
+    // outside the blocks exactly zero (each is a sum of products with a zero
+    // factor), so both give the same block structure
+    bool blocks(int chil, int chir) const { return u1 && (int64_t)chil * chir >= u1_min; }
+
     MatVec matvec(const HeffArgs& a, int j) {
-        if (u1) return [this, a, j](const double2* x, double2* y) { heff_u1_apply(a, j, x, y); };
+        if (blocks(a.chil, a.chir)) return [this, a, j](const double2* x, double2* y) { heff_u1_apply(a, j, x, y); };
         return [this, a](const double2* x, double2* y) { heff_apply(ctx, a, x, Dt::C128, y, Dt::C128); };
     }
 
@@ -173,7 +182,7 @@ struct Stepper {
 
     void update_left(int j) {  // L[j+1] from L[j], A[j], W[j]
         env_buf(m->L[j + 1], (size_t)W->w[j + 1] * m->chi[j + 1] * m->chi[j + 1]);
-        if (u1) {
+        if (blocks(m->chi[j], m->chi[j + 1])) {
             env_u1_update(1, j, m->L[j].ptr, m->L[j + 1].ptr);
             st.flops += env_flops(m->chi[j], m->chi[j + 1], m->d, W->w[j], W->w[j + 1]);
             return;
@@ -185,7 +194,7 @@ struct Stepper {
 
     void update_right(int j) {  // R[j-1] from R[j], A[j], W[j]
         env_buf(m->R[j - 1], (size_t)W->w[j] * m->chi[j] * m->chi[j]);
-        if (u1) {
+        if (blocks(m->chi[j], m->chi[j + 1])) {
             env_u1_update(-1, j, m->R[j].ptr, m->R[j - 1].ptr);
             st.flops += env_flops(m->chi[j], m->chi[j + 1], m->d, W->w[j], W->w[j + 1]);
             return;
@@ -323,14 +332,19 @@ struct Stepper {
         return th;
     }
 
-    // Split of theta into sites j, j+1 (Fig. postupdate); centre_left puts the
-    // singular values into site j, otherwise into site j+1.
     // U(1) split of theta into sites j, j+1: rows (a, s1) carry q(a) + q(s1),
     // columns (s2, b) carry q(b) - q(s2), and theta connects only equal
     // charges (the charge of the new bond index).  Every charge sector is
-    // decomposed by its own SVD; the singular values of all sectors are
+    // decomposed on its own; the singular values of all sectors are
     // truncated together by the rule of the dense split (Eq. discweight), and
-    // the kept ones, ordered by charge (then by value), label the new bond.
+    // the kept ones, ordered by charge (then by position in the sector),
+    // label the new bond.  Sectors go the way the dense split goes: with the
+    // density-matrix rule a sector of order <= kJacobiMaxOrder takes the
+    // one-workgroup Jacobi eigen-decomposition of its reduced density matrix
+    // (queued without a read-back; one read-back of all sectors' values),
+    // any other sector an SVD.  Uall [rows][ktot] and Vall [ktot][cols]
+    // collect every sector's factors with the singular values already on the
+    // side that keeps them (site j + 1 unless centre_left).
     void split_u1(int j, double2* th, bool centre_left) {
         TxRange tx("split_u1");
         const int d = m->d, chil = m->chi[j], chir = m->chi[j + 2];
@@ -338,6 +352,8 @@ struct Stepper {
         const std::vector<int>& qa = m->qbond[j];
         const std::vector<int>& qb = m->qbond[j + 2];
         const std::vector<int>& qs = m->qphys;
+        const bool gram = o.svd_mode == 2 || (o.svd_mode == 0 && o.w_max >= 1e-13);
+        const bool left = !centre_left;  // the side that becomes orthonormal
         std::map<int, std::vector<int>> rsec, csec;
         for (int a = 0; a < chil; ++a)
             for (int s1 = 0; s1 < d; ++s1) rsec[qa[a] + qs[s1]].push_back(a * d + s1);
@@ -348,17 +364,31 @@ struct Stepper {
             const std::vector<int>* r;
             const std::vector<int>* c;
             int k, off;
+            bool jac;        // density-matrix Jacobi path
             int64_t ri, ci;  // offsets of the index lists in the device table
+            int64_t blk, G, vecs, P, T;  // arena offsets (complex elements), Jacobi path
             std::vector<double> s;
         };
         std::vector<Sec> secs;
         std::vector<int> idx;  // row lists, then column lists
         int ktot = 0;
+        int64_t arena = 0;
         for (const auto& kv : rsec) {
             auto it = csec.find(kv.first);
             if (it == csec.end()) continue;
-            Sec sc{kv.first, &kv.second, &it->second, 0, ktot, 0, 0, {}};
-            sc.k = std::min((int)kv.second.size(), (int)it->second.size());
+            const int nr = (int)kv.second.size(), nc = (int)it->second.size();
+            Sec sc{kv.first, &kv.second, &it->second, 0, ktot, false, 0, 0, 0, 0, 0, 0, 0, {}};
+            const int n = left ? nr : nc;
+            sc.jac = gram && n <= kJacobiMaxOrder;
+            sc.k = sc.jac ? n : std::min(nr, nc);
+            if (sc.jac) {
+                const int len = left ? nc : nr;
+                sc.blk = arena; arena += (int64_t)nr * nc;
+                sc.G = arena; arena += (int64_t)n * n;
+                sc.vecs = arena; arena += (int64_t)n * n;
+                sc.P = arena; arena += (int64_t)n * len;
+                sc.T = arena; arena += left ? (int64_t)nr * n : 0;
+            }
             sc.ri = (int64_t)idx.size();
             idx.insert(idx.end(), kv.second.begin(), kv.second.end());
             sc.ci = (int64_t)idx.size();
@@ -368,23 +398,82 @@ struct Stepper {
         }
         TDVP_REQUIRE(ktot > 0, TDVP_E_NUMERIC, "U(1) split: no charge sector connects the two sites");
         const int64_t nidx = (int64_t)idx.size();
-        int* didx = static_cast<int*>(ctx->workspace("u1s_idx", sizeof(int) * (size_t)(nidx + 2 * (int64_t)ktot)));
+        int* didx = static_cast<int*>(ctx->workspace("u1s_idx", sizeof(int) * (size_t)(nidx + ktot)));
         double2* Uall = static_cast<double2*>(ctx->workspace("u1s_Uall", sizeof(double2) * (size_t)rows * ktot));
         double2* Vall = static_cast<double2*>(ctx->workspace("u1s_Vall", sizeof(double2) * (size_t)ktot * cols));
+        double2* ar = static_cast<double2*>(ctx->workspace("u1s_arena", sizeof(double2) * (size_t)std::max<int64_t>(1, arena)));
+        double* s2 = static_cast<double*>(ctx->workspace("u1s_s2", sizeof(double) * (size_t)ktot));
         TDVP_CHECK_HIP(hipMemcpyAsync(didx, idx.data(), sizeof(int) * nidx, hipMemcpyHostToDevice, ctx->stream));
         TDVP_CHECK_HIP(hipMemsetAsync(Uall, 0, sizeof(double2) * (size_t)rows * ktot, ctx->stream));
         TDVP_CHECK_HIP(hipMemsetAsync(Vall, 0, sizeof(double2) * (size_t)ktot * cols, ctx->stream));
+        auto operand = [](const double2* p, int64_t ld, bool kcontig, bool conj) {
+            GemmOperand g;
+            g.p = p; g.dt = Dt::C128; g.ld = ld; g.kcontig = kcontig; g.conj = conj;
+            return g;
+        };
         for (auto& sc : secs) {
             const int nr = (int)sc.r->size(), nc = (int)sc.c->size();
+            if (sc.jac) {
+                const int n = sc.k, len = left ? nc : nr;
+                double2 *blk = ar + sc.blk, *G = ar + sc.G, *V = ar + sc.vecs, *P = ar + sc.P;
+                copy_idx(blk, nc, nullptr, nullptr, th, cols, didx + sc.ri, didx + sc.ci, nr, nc, ctx->stream);
+                GemmDesc g;  // reduced density matrix of the orthonormal side
+                g.M = n; g.N = n; g.cdt = Dt::C128; g.ldc = n; g.C = G;
+                if (left) {  // G = B B^dag
+                    g.K = nc; g.A = operand(blk, nc, true, false); g.B = operand(blk, nc, true, true);
+                } else {     // G = B^dag B
+                    g.K = nr; g.A = operand(blk, nc, false, true); g.B = operand(blk, nc, false, false);
+                }
+                cgemm(ctx, g, true, 4);
+                jacobi_eigh_small(G, n, s2 + sc.off, V, nullptr, ctx->stream);  // row c of V = conj(vector c)
+                GemmDesc pg;  // the other side: U^dag B (left) or B V (right); its norms are the singular values
+                pg.cdt = Dt::C128; pg.C = P;
+                if (left) {
+                    pg.M = n; pg.N = nc; pg.K = nr; pg.ldc = nc;
+                    pg.A = operand(V, n, true, false); pg.B = operand(blk, nc, false, false);
+                } else {
+                    pg.M = nr; pg.N = n; pg.K = nc; pg.ldc = n;
+                    pg.A = operand(blk, nc, true, false); pg.B = operand(V, n, true, true);
+                }
+                cgemm(ctx, pg, true, 4);
+                vec_norms2(P, left ? nc : n, n, len, left, s2 + sc.off, ctx->stream);
+                if (left) {
+                    double2* T = ar + sc.T;  // T[i][c] = u_c[i]
+                    conj_transpose(T, n, V, n, n, nr, ctx->stream);
+                    copy_idx(Uall + sc.off, ktot, didx + sc.ri, nullptr, T, n, nullptr, nullptr, nr, n, ctx->stream);
+                    copy_idx(Vall + (int64_t)sc.off * cols, cols, nullptr, didx + sc.ci, P, nc, nullptr, nullptr, n, nc,
+                             ctx->stream);
+                } else {
+                    copy_idx(Vall + (int64_t)sc.off * cols, cols, nullptr, didx + sc.ci, V, n, nullptr, nullptr, n, nc,
+                             ctx->stream);
+                    copy_idx(Uall + sc.off, ktot, didx + sc.ri, nullptr, P, n, nullptr, nullptr, nr, n, ctx->stream);
+                }
+                continue;
+            }
             double2* blk = static_cast<double2*>(ctx->workspace("u1s_blk", sizeof(double2) * (size_t)nr * nc));
             copy_idx(blk, nc, nullptr, nullptr, th, cols, didx + sc.ri, didx + sc.ci, nr, nc, ctx->stream);
             SvdResult r = svd_rowmajor(ctx, blk, nr, nc);
             TDVP_REQUIRE(r.k == sc.k, TDVP_E_STATE, "U(1) split: unexpected sector rank");
+            if (centre_left) scale_cols(r.U, r.k, r.S_dev, nr, r.k, ctx->stream);
+            else scale_rows(r.Vh, nc, r.S_dev, r.k, nc, ctx->stream);
             // U_Q into the sector's rows of Uall, Vh_Q into its columns of Vall
             copy_idx(Uall + sc.off, ktot, didx + sc.ri, nullptr, r.U, r.k, nullptr, nullptr, nr, sc.k, ctx->stream);
             copy_idx(Vall + (int64_t)sc.off * cols, cols, nullptr, didx + sc.ci, r.Vh, nc, nullptr, nullptr, sc.k, nc,
                      ctx->stream);
             sc.s = r.S;
+        }
+        // the Jacobi sectors' squared singular values, in one read-back
+        std::vector<double> hs2(ktot, 0.0);
+        if (std::any_of(secs.begin(), secs.end(), [](const Sec& x) { return x.jac; }))
+            ctx->read_back({{hs2.data(), s2, sizeof(double) * (size_t)ktot}});
+        for (auto& sc : secs) {
+            if (!sc.jac) continue;
+            sc.s.resize(sc.k);
+            for (int c = 0; c < sc.k; ++c) {
+                const double v = hs2[sc.off + c];
+                TDVP_REQUIRE(std::isfinite(v), TDVP_E_NUMERIC, "U(1) split: non-finite singular value");
+                sc.s[c] = std::sqrt(std::max(v, 0.0));
+            }
         }
         // all singular values, largest first, for the truncation rule
         std::vector<std::pair<double, std::pair<int, int>>> all;  // (s, (sector, index))
@@ -395,40 +484,36 @@ struct Stepper {
         for (size_t i = 0; i < all.size(); ++i) sv[i] = all[i].first;
         double w = 0.0;
         const int chi = trunc_rank(sv, w);
-        // kept values ordered by sector charge (sectors are in ascending charge), then by value
+        // kept values ordered by sector charge (sectors are in ascending charge), then by position
         std::vector<std::pair<int, int>> kept(chi);
         for (int c = 0; c < chi; ++c) kept[c] = all[c].second;
         std::stable_sort(kept.begin(), kept.end(), [](const auto& x, const auto& y) {
             return x.first != y.first ? x.first < y.first : x.second < y.second;
         });
         std::vector<int> src(chi), labels(chi);
-        std::vector<double> skept(chi);
         for (int c = 0; c < chi; ++c) {
             const Sec& sc = secs[kept[c].first];
             src[c] = sc.off + kept[c].second;
             labels[c] = sc.Q;
-            skept[c] = sc.s[kept[c].second];
-        }
-        for (double v : skept)
+            const double v = sc.s[kept[c].second];
             TDVP_REQUIRE(v > 0.0 && std::isfinite(v), TDVP_E_NUMERIC, "U(1) split: a kept singular value is zero or not finite");
+        }
         int* dsrc = didx + nidx;
-        double* dS = static_cast<double*>(ctx->workspace("u1s_S", sizeof(double) * (size_t)chi));
         double2* U = static_cast<double2*>(ctx->workspace("u1s_U", sizeof(double2) * (size_t)rows * chi));
         double2* Vh = static_cast<double2*>(ctx->workspace("u1s_Vh", sizeof(double2) * (size_t)chi * cols));
         TDVP_CHECK_HIP(hipMemcpyAsync(dsrc, src.data(), sizeof(int) * chi, hipMemcpyHostToDevice, ctx->stream));
-        TDVP_CHECK_HIP(hipMemcpyAsync(dS, skept.data(), sizeof(double) * chi, hipMemcpyHostToDevice, ctx->stream));
         copy_idx(U, chi, nullptr, nullptr, Uall, ktot, nullptr, dsrc, rows, chi, ctx->stream);
         copy_idx(Vh, cols, nullptr, nullptr, Vall, cols, dsrc, nullptr, chi, cols, ctx->stream);
-        if (centre_left) scale_cols(U, chi, dS, rows, chi, ctx->stream);
-        else scale_rows(Vh, cols, dS, chi, cols, ctx->stream);
         store_site(j, U, m->chi[j], chi, rows, chi, chi);
         store_site(j + 1, Vh, chi, m->chi[j + 2], chi, cols, cols);
-        TDVP_CHECK_HIP(hipStreamSynchronize(ctx->stream));  // host vectors above go out of scope
+        TDVP_CHECK_HIP(hipStreamSynchronize(ctx->stream));  // the host index list above goes out of scope
         st.w_step += w;
         m->chi[j + 1] = chi;
         m->qbond[j + 1] = labels;
     }
 
+    // Split of theta into sites j, j+1 (Fig. postupdate); centre_left puts the
+    // singular values into site j, otherwise into site j+1.
     void split(int j, double2* th, bool centre_left) {
         if (u1) {
             split_u1(j, th, centre_left);

@@ -65,8 +65,11 @@ def check_charge_rule(m):
         assert np.max(np.abs(A[~allowed]), initial=0.0) == 0.0, j
 
 
-@pytest.mark.parametrize("dt_", ["c128", "c64"])
-def test_u1_two_site_quench_matches_dense_oracle(ctx, dt_):
+@pytest.mark.parametrize("dt_,bmin", [("c128", 1), ("c64", 1), ("c128", 0)])
+def test_u1_two_site_quench_matches_dense_oracle(ctx, dt_, bmin):
+    """bmin = 1: every matvec and environment update on the block kernels;
+    bmin = 0 (default threshold): at these bond dimensions all of them on the
+    dense kernels, the splits sector by sector."""
     import paper_1912_06127_amd as pkg
     N = 12
     W, Ws, bits = setup(ctx, N, 3)
@@ -74,9 +77,9 @@ def test_u1_two_site_quench_matches_dense_oracle(ctx, dt_):
     m.set_charges(Q_SPIN, product_labels(bits))
     st_o = otdvp.MPSState(omps.padded_product_state(bits, [1] * (N + 1)), Ws)
     tr = otdvp.Truncation(chi_max=16, w_max=1e-8, eps=1e-12)
-    opts = pkg.TDVPOptions(compute=dt_, chi_max=16, w_max=1e-8, eps_rel=1e-12)
+    opts = pkg.TDVPOptions(compute=dt_, chi_max=16, w_max=1e-8, eps_rel=1e-12, u1_block_min=bmin)
     for s in range(8):
-        print(f"U(1) 2TDVP step {s} {dt_}", flush=True)
+        print(f"U(1) 2TDVP step {s} {dt_} block_min {bmin}", flush=True)
         otdvp.tdvp2_step(st_o, 0.05, tr)
         info = pkg.tdvp2_step(ctx, m, W, 0.05, opts)
         z = pkg.expect(ctx, m, list(range(N)), spin.SZ).real
@@ -100,7 +103,8 @@ def test_u1_dmrg_and_one_site_refusal(ctx):
     W, Ws, bits = setup(ctx, N, 2)
     m = pkg.MPS.init(ctx, N, 2, [1] * (N + 1), basis_state=bits)
     m.set_charges(Q_SPIN, product_labels(bits))
-    opts = pkg.TDVPOptions(compute="c128", chi_max=32, eps_rel=1e-14, krylov_max=40, krylov_tol=1e-12)
+    opts = pkg.TDVPOptions(compute="c128", chi_max=32, eps_rel=1e-14, krylov_max=40, krylov_tol=1e-12,
+                           u1_block_min=1)
     e = None
     for _ in range(6):
         e = pkg.dmrg2_sweep(ctx, m, W, opts)["energy"]
