@@ -497,6 +497,7 @@ def gradient_timing(pkg, ctx, torch, np, steps=2):
             ad.evolve(ctx, T0, [W.detach() for W in Ws], p["dt"], steps, compute=cdt, checkpoint_every=0)
         torch.cuda.synchronize()
         fwd = (time.perf_counter() - t0) / steps
+        progress(f"gradient {comp}: forward {fwd:.3f} s/step; forward + backward over {steps} steps")
         t0 = time.perf_counter()
         T = ad.evolve(ctx, T0, Ws, p["dt"], steps, compute=cdt, checkpoint_every=p["checkpoint_every"])
         loss = ad.expect_site(ctx, T, p["site"] - 1, sz)

@@ -128,6 +128,20 @@ struct tdvp_ctx_s {
         size_t bytes;
     };
     void read_back(std::initializer_list<ReadSpan> spans);
+    // Host-to-device copy of a small table on the context stream without
+    // waiting for it: the bytes are staged in one of kUploadSlots page-locked
+    // slots, and a slot is written again only after the copy that read it
+    // has completed (its event).  Not for use under stream capture.
+    static constexpr int kUploadSlots = 8;
+    struct UploadSlot {
+        hipEvent_t ev = nullptr;
+        bool pending = false;
+    };
+    UploadSlot up_slot[kUploadSlots];
+    char* up_base = nullptr;
+    size_t up_slot_bytes = 0;
+    int up_next = 0;
+    void upload(void* dst, const void* src, size_t bytes);
     // Waits for the context stream like hipStreamSynchronize.
     void wait_stream();
     void release_all();
@@ -276,14 +290,18 @@ bool heff_small_fits(int chil, int chir, int D, int wl, int wr, bool fp64);
 void heff_small(tdvp_ctx ctx, const HeffSmallDesc& d);
 // Many MPO stages of one precision in one launch (see GroupedGemm).
 struct GroupedWStage {
-    DevMem probs;
+    DevMem probs;                  // the problem table, unless it sits in a named workspace
+    const void* table = nullptr;   // the table the launch reads
     int nprob = 0, nt = 256;
     int64_t blocks = 0;
     size_t shmem = 0;
     bool fp64 = false;
     double bytes = 0.0;
 };
-void grouped_wstage_plan(tdvp_ctx ctx, const std::vector<WStageDesc>& ds, GroupedWStage& out);
+// The table is uploaded without waiting (tdvp_ctx_s::upload); it goes into
+// the workspace named table_ws when given, else into out.probs.
+void grouped_wstage_plan(tdvp_ctx ctx, const std::vector<WStageDesc>& ds, GroupedWStage& out,
+                         const char* table_ws = nullptr);
 void grouped_wstage_run(tdvp_ctx ctx, const GroupedWStage& g);
 
 // ------------------------------------- batched Krylov over packed instances

@@ -1112,9 +1112,8 @@ void block_gemm(tdvp_ctx ctx, const std::vector<BlockGemm>& probs, const std::ve
     const std::string key = std::string("blk_") + tag;
     auto* dp = static_cast<BProblem*>(ctx->workspace(key + "_p", sizeof(BProblem) * hp.size()));
     auto* dc = static_cast<BChunkDev*>(ctx->workspace(key + "_c", sizeof(BChunkDev) * std::max<size_t>(1, hc.size())));
-    TDVP_CHECK_HIP(hipMemcpyAsync(dp, hp.data(), sizeof(BProblem) * hp.size(), hipMemcpyHostToDevice, ctx->stream));
-    if (!hc.empty())
-        TDVP_CHECK_HIP(hipMemcpyAsync(dc, hc.data(), sizeof(BChunkDev) * hc.size(), hipMemcpyHostToDevice, ctx->stream));
+    ctx->upload(dp, hp.data(), sizeof(BProblem) * hp.size());
+    if (!hc.empty()) ctx->upload(dc, hc.data(), sizeof(BChunkDev) * hc.size());
     const int n = (int)hp.size();
     if (fp64) {
         if (small) launch_blocks<double, 32, 64, 8, 1, 2, false>(ctx, dp, n, dc, total, ak, bkc, flops, tag);
@@ -1126,8 +1125,6 @@ void block_gemm(tdvp_ctx ctx, const std::vector<BlockGemm>& probs, const std::ve
         if (small) launch_blocks<float, 32, 64, 16, 1, 2, false>(ctx, dp, n, dc, total, ak, bkc, flops, tag);
         else launch_blocks<float, 64, 64, 16, 2, 2, false>(ctx, dp, n, dc, total, ak, bkc, flops, tag);
     }
-    // the host tables above are read by the copies queued on the stream
-    TDVP_CHECK_HIP(hipStreamSynchronize(ctx->stream));
 }
 
 void grouped_gemm_run(tdvp_ctx ctx, const GroupedGemm& gg) {

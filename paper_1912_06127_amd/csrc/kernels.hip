@@ -1178,7 +1178,7 @@ void wstage(tdvp_ctx ctx, const WStageDesc& d) {
     TDVP_CHECK_HIP(hipGetLastError());
 }
 
-void grouped_wstage_plan(tdvp_ctx ctx, const std::vector<WStageDesc>& ds, GroupedWStage& out) {
+void grouped_wstage_plan(tdvp_ctx ctx, const std::vector<WStageDesc>& ds, GroupedWStage& out, const char* table_ws) {
     std::vector<GWProblem> tab;
     int nin_max = 1;
     bool first = true;
@@ -1224,18 +1224,22 @@ void grouped_wstage_plan(tdvp_ctx ctx, const std::vector<WStageDesc>& ds, Groupe
     TDVP_REQUIRE(blocks <= 0x7fffffff, TDVP_E_SHAPE, "grouped wstage: grid too large");
     out.nprob = (int)tab.size();
     out.blocks = blocks;
-    if (out.probs.bytes < sizeof(GWProblem) * tab.size()) out.probs = DevMem(ctx, sizeof(GWProblem) * tab.size());
-    if (!tab.empty()) {
-        TDVP_CHECK_HIP(hipMemcpyAsync(out.probs.ptr, tab.data(), sizeof(GWProblem) * tab.size(), hipMemcpyHostToDevice,
-                                      ctx->stream));
-        TDVP_CHECK_HIP(hipStreamSynchronize(ctx->stream));
+    const size_t tb = sizeof(GWProblem) * std::max<size_t>(1, tab.size());
+    void* dst;
+    if (table_ws) {
+        dst = ctx->workspace(table_ws, tb);
+    } else {
+        if (out.probs.bytes < tb) out.probs = DevMem(ctx, tb);
+        dst = out.probs.ptr;
     }
+    out.table = dst;
+    if (!tab.empty()) ctx->upload(dst, tab.data(), sizeof(GWProblem) * tab.size());
 }
 
 void grouped_wstage_run(tdvp_ctx ctx, const GroupedWStage& g) {
     if (g.nprob == 0 || g.blocks == 0) return;
     ProfScope prof(ctx, g.fp64 ? "wstage_grouped_f64" : "wstage_grouped_f32", 0.0, g.bytes);
-    const auto* pr = static_cast<const GWProblem*>(g.probs.ptr);
+    const auto* pr = static_cast<const GWProblem*>(g.table);
     if (g.fp64)
         hipLaunchKernelGGL(wstage_grouped_kernel<double>, dim3((unsigned)g.blocks), dim3(g.nt), g.shmem, ctx->stream,
                            pr, g.nprob);

@@ -73,6 +73,36 @@ void* tdvp_ctx_s::pinned_host(size_t bytes) {
     return pinned;
 }
 
+void tdvp_ctx_s::upload(void* dst, const void* src, size_t bytes) {
+    if (bytes == 0) return;
+    if (bytes > up_slot_bytes) {
+        // regrow: every copy out of the old slots must have completed first
+        for (auto& sl : up_slot)
+            if (sl.pending) {
+                TDVP_CHECK_HIP(hipEventSynchronize(sl.ev));
+                sl.pending = false;
+            }
+        if (up_base) (void)hipHostFree(up_base);
+        up_base = nullptr;
+        up_slot_bytes = 0;
+        const size_t cap = std::max<size_t>((bytes + 255) / 256 * 256, 64 * 1024);
+        void* p = nullptr;
+        TDVP_CHECK_HIP(hipHostMalloc(&p, cap * kUploadSlots, hipHostMallocDefault));
+        up_base = static_cast<char*>(p);
+        up_slot_bytes = cap;
+    }
+    UploadSlot& sl = up_slot[up_next];
+    char* slot = up_base + (size_t)up_next * up_slot_bytes;
+    up_next = (up_next + 1) % kUploadSlots;
+    if (!sl.ev) TDVP_CHECK_HIP(hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming));
+    if (sl.pending) TDVP_CHECK_HIP(hipEventSynchronize(sl.ev));
+    sl.pending = false;
+    std::memcpy(slot, src, bytes);
+    TDVP_CHECK_HIP(hipMemcpyAsync(dst, slot, bytes, hipMemcpyHostToDevice, stream));
+    TDVP_CHECK_HIP(hipEventRecord(sl.ev, stream));
+    sl.pending = true;
+}
+
 void tdvp_ctx_s::wait_stream() {
     for (int i = 0; i < 4096; ++i) {
         const hipError_t e = hipStreamQuery(stream);
@@ -108,6 +138,17 @@ void tdvp_ctx_s::read_back(std::initializer_list<ReadSpan> spans) {
 }
 
 void tdvp_ctx_s::release_all() {
+    for (auto& sl : up_slot) {
+        if (sl.ev) {
+            if (sl.pending) (void)hipEventSynchronize(sl.ev);
+            (void)hipEventDestroy(sl.ev);
+        }
+        sl.ev = nullptr;
+        sl.pending = false;
+    }
+    if (up_base) (void)hipHostFree(up_base);
+    up_base = nullptr;
+    up_slot_bytes = 0;
     if (pinned) (void)hipHostFree(pinned);
     pinned = nullptr;
     pinned_bytes = 0;

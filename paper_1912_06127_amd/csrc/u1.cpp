@@ -131,9 +131,8 @@ void mpo_stage(tdvp_ctx ctx, const WStageDesc& base, const std::vector<Sector>& 
         }
     if (ds.empty()) return;
     GroupedWStage g;
-    grouped_wstage_plan(ctx, ds, g);
+    grouped_wstage_plan(ctx, ds, g, "u1_wstage_tab");
     grouped_wstage_run(ctx, g);
-    TDVP_CHECK_HIP(hipStreamSynchronize(ctx->stream));  // the plan's table is freed on return
 }
 
 // Charge differences q(right index) - q(left index) = qD(s) + sign c(k) that

@@ -65,11 +65,12 @@ def check_charge_rule(m):
         assert np.max(np.abs(A[~allowed]), initial=0.0) == 0.0, j
 
 
-@pytest.mark.parametrize("dt_,bmin", [("c128", 1), ("c64", 1), ("c128", 0)])
+@pytest.mark.parametrize("dt_,bmin", [("c128", 1), ("c64", 1), ("c128", 0), ("c128", 64)])
 def test_u1_two_site_quench_matches_dense_oracle(ctx, dt_, bmin):
     """bmin = 1: every matvec and environment update on the block kernels;
     bmin = 0 (default threshold): at these bond dimensions all of them on the
-    dense kernels, the splits sector by sector."""
+    dense kernels, the splits sector by sector; bmin = 64: both kinds within
+    one sweep (bonds of 8 and more on the block kernels)."""
     import paper_1912_06127_amd as pkg
     N = 12
     W, Ws, bits = setup(ctx, N, 3)
