@@ -522,6 +522,33 @@ __global__ void splitk_reduce_kernel(const void* part, int ks, int M, int N, int
     else reinterpret_cast<float2*>(C)[o] = make_float2((float)re, (float)im);
 }
 
+// Chunk-split block products: problem q's g-th part wrote its [M][N] sum to
+// part + poff + g * M * N (accumulation type); C = the parts summed in order.
+struct BRed {
+    void* C;
+    int64_t ldc, poff;
+    int M, N, parts, c128C;
+};
+
+template <typename T>
+__global__ void block_reduce_kernel(const BRed* __restrict__ tab, const void* __restrict__ part) {
+    using C2 = typename std::conditional<sizeof(T) == 4, float2, double2>::type;
+    const BRed r = tab[blockIdx.x];
+    const int64_t mn = (int64_t)r.M * r.N;
+    const C2* P = reinterpret_cast<const C2*>(part) + r.poff;
+    for (int64_t i = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; i < mn; i += (int64_t)gridDim.y * blockDim.x) {
+        T re = 0, im = 0;
+        for (int g = 0; g < r.parts; ++g) {
+            const C2 v = P[g * mn + i];
+            re += v.x;
+            im += v.y;
+        }
+        const int64_t o = (i / r.N) * r.ldc + i % r.N;
+        if (r.c128C) reinterpret_cast<double2*>(r.C)[o] = make_double2((double)re, (double)im);
+        else reinterpret_cast<float2*>(r.C)[o] = make_float2((float)re, (float)im);
+    }
+}
+
 KOperand to_k(const GemmOperand& o) {
     KOperand k;
     k.p = o.p;
@@ -1109,6 +1136,80 @@ void block_gemm(tdvp_ctx ctx, const std::vector<BlockGemm>& probs, const std::ve
     for (size_t c = 0; c < chunks.size(); ++c)
         hc[c] = BChunkDev{chunks[c].offA, chunks[c].offB, chunks[c].strideA, chunks[c].strideB, chunks[c].K,
                           chunks[c].count};
+    // Too few tiles to fill the CUs (each walking a long chunk list): the
+    // chunk list of every unbatched problem is cut into up to `parts`
+    // consecutive pieces of about equal K (a chunk of count c is c unit
+    // products), each piece a problem of its own that writes an [M][N]
+    // partial sum; a reduction adds the pieces in order (deterministic).
+    std::vector<BRed> red;
+    int64_t part_elems = 0;
+    char* part = nullptr;
+    const int parts = total >= 512 ? 1 : (int)std::min<int64_t>(8, (512 + total - 1) / std::max<int64_t>(1, total));
+    if (parts > 1) {
+        std::vector<BProblem> out;
+        std::vector<BChunkDev> oc;
+        std::vector<int64_t> part_off;  // per problem of `out`: offset of its partial, or -1
+        int64_t t2 = 0;
+        for (const auto& b : hp) {
+            int units = 0;
+            for (int c = b.chunk0; c < b.chunk0 + b.nchunk; ++c) units += hc[c].count;
+            const int np = std::min(parts, units);
+            if (b.batch != 1 || b.nchunk == 0 || np < 2) {
+                BProblem x = b;
+                const int c0 = (int)oc.size();
+                for (int c = b.chunk0; c < b.chunk0 + b.nchunk; ++c) oc.push_back(hc[c]);
+                x.chunk0 = c0;
+                x.tile_begin = t2;
+                t2 += (int64_t)x.p.tiles_m * x.p.tiles_n * x.batch;
+                out.push_back(x);
+                part_off.push_back(-1);
+                continue;
+            }
+            const int64_t mn = (int64_t)b.p.M * b.p.N;
+            red.push_back(BRed{b.p.C, b.p.ldc, part_elems, b.p.M, b.p.N, np, b.p.c128C ? 1 : 0});
+            // unit u of the problem = (chunk c, product i); piece g takes units [g*units/np, (g+1)*units/np)
+            int c = b.chunk0, i = 0;
+            for (int g = 0; g < np; ++g) {
+                const int take = (int)((int64_t)(g + 1) * units / np - (int64_t)g * units / np);
+                BProblem x = b;
+                x.chunk0 = (int)oc.size();
+                for (int left = take; left > 0;) {
+                    const BChunkDev& src = hc[c];
+                    const int n = std::min(left, src.count - i);
+                    BChunkDev piece = src;
+                    piece.offA = src.offA + (int64_t)i * src.strideA;
+                    piece.offB = src.offB + (int64_t)i * src.strideB;
+                    piece.count = n;
+                    oc.push_back(piece);
+                    left -= n;
+                    i += n;
+                    if (i == src.count) {
+                        ++c;
+                        i = 0;
+                    }
+                }
+                x.nchunk = (int)oc.size() - x.chunk0;
+                x.p.c128C = fp64;
+                x.p.ldc = b.p.N;
+                x.p.strideC = mn;
+                x.tile_begin = t2;
+                t2 += (int64_t)x.p.tiles_m * x.p.tiles_n;
+                out.push_back(x);
+                part_off.push_back(part_elems + g * mn);
+            }
+            part_elems += np * mn;
+        }
+        if (!red.empty()) {
+            const size_t pesz = fp64 ? sizeof(double2) : sizeof(float2);
+            part = static_cast<char*>(ctx->workspace(std::string("blk_") + tag + "_part", pesz * part_elems));
+            for (size_t q = 0; q < out.size(); ++q)
+                if (part_off[q] >= 0) out[q].p.C = part + part_off[q] * (int64_t)pesz;
+            hp.swap(out);
+            hc.swap(oc);
+            total = t2;
+            TDVP_REQUIRE(total <= 0x7fffffff, TDVP_E_SHAPE, "block gemm: too many tiles");
+        }
+    }
     const std::string key = std::string("blk_") + tag;
     auto* dp = static_cast<BProblem*>(ctx->workspace(key + "_p", sizeof(BProblem) * hp.size()));
     auto* dc = static_cast<BChunkDev*>(ctx->workspace(key + "_c", sizeof(BChunkDev) * std::max<size_t>(1, hc.size())));
@@ -1124,6 +1225,23 @@ void block_gemm(tdvp_ctx ctx, const std::vector<BlockGemm>& probs, const std::ve
     } else {
         if (small) launch_blocks<float, 32, 64, 16, 1, 2, false>(ctx, dp, n, dc, total, ak, bkc, flops, tag);
         else launch_blocks<float, 64, 64, 16, 2, 2, false>(ctx, dp, n, dc, total, ak, bkc, flops, tag);
+    }
+    if (!red.empty()) {
+        const std::string key2 = std::string("blk_") + tag + "_red";
+        auto* dr = static_cast<BRed*>(ctx->workspace(key2, sizeof(BRed) * red.size()));
+        ctx->upload(dr, red.data(), sizeof(BRed) * red.size());
+        ProfScope prof(ctx, fp64 ? "block_reduce_f64" : "block_reduce_f32", 0.0, 0.0);
+        // problems x slices of each problem's elements: about 2048 blocks in all
+        int64_t maxmn = 1;
+        for (const auto& r : red) maxmn = std::max<int64_t>(maxmn, (int64_t)r.M * r.N);
+        const unsigned ys = (unsigned)std::max<int64_t>(
+            1, std::min<int64_t>((maxmn + 255) / 256, (2048 + (int64_t)red.size() - 1) / (int64_t)red.size()));
+        const dim3 grid((unsigned)red.size(), ys);
+        if (fp64)
+            hipLaunchKernelGGL(block_reduce_kernel<double>, grid, dim3(256), 0, ctx->stream, dr, part);
+        else
+            hipLaunchKernelGGL(block_reduce_kernel<float>, grid, dim3(256), 0, ctx->stream, dr, part);
+        TDVP_CHECK_HIP(hipGetLastError());
     }
 }
 

@@ -115,19 +115,31 @@ void stage_a(tdvp_ctx ctx, Dt dt, bool fp64, int form, const std::vector<Sector>
 }
 
 // The sparse MPO stage on the (p-sector, q-sector) rectangles whose charge
-// difference q - p is in `deltas`; strides as in WStageDesc.
+// difference q - p is in `deltas`; strides as in WStageDesc.  Neighbouring
+// q-sectors that both qualify are one rectangle (their indices are
+// contiguous): a block of the MPO stage covers a few hundred q points, and
+// single sectors of a few dozen would leave most of it idle.
 void mpo_stage(tdvp_ctx ctx, const WStageDesc& base, const std::vector<Sector>& SP, const std::vector<Sector>& SQ,
                const std::vector<int>& deltas, size_t esz_in, size_t esz_out) {
     std::vector<WStageDesc> ds;
+    auto wanted = [&](const Sector& p, const Sector& q) {
+        return std::find(deltas.begin(), deltas.end(), q.q - p.q) != deltas.end();
+    };
     for (const Sector& p : SP)
-        for (const Sector& q : SQ) {
-            if (std::find(deltas.begin(), deltas.end(), q.q - p.q) == deltas.end()) continue;
+        for (size_t i = 0; i < SQ.size();) {
+            if (!wanted(p, SQ[i])) {
+                ++i;
+                continue;
+            }
+            size_t e = i + 1;
+            while (e < SQ.size() && wanted(p, SQ[e])) ++e;
             WStageDesc w = base;
-            w.in = at(base.in, (int64_t)p.off * base.ip + q.off, esz_in);
-            w.out = at(base.out, (int64_t)p.off * base.op + q.off, esz_out);
+            w.in = at(base.in, (int64_t)p.off * base.ip + SQ[i].off, esz_in);
+            w.out = at(base.out, (int64_t)p.off * base.op + SQ[i].off, esz_out);
             w.P = p.n;
-            w.Q = q.n;
+            w.Q = SQ[e - 1].off + SQ[e - 1].n - SQ[i].off;
             ds.push_back(w);
+            i = e;
         }
     if (ds.empty()) return;
     GroupedWStage g;
