@@ -368,6 +368,65 @@ def sweep_u1_timing(pkg, ctx, steps=40):
     return res
 
 
+def sweep_u1_large_timing(pkg, ctx, chi=256, steps=3):
+    """The N = 64 XXX quench (sigma+- MPO, K = 6, w = 20) carried on in U(1)
+    mode with dt = 0.1 until every central bond reaches chi (chi_max = chi,
+    w_max = 1e-10); from that state, `steps` 2TDVP steps (dt = 0.05, complex64)
+    dense and in U(1) mode, each after one untimed step from the same state
+    (GEMM autotuning).  The spin profiles after the timed steps are compared."""
+    import numpy as np
+    N, K = 64, 6
+    c, lam, _ = pkg.fit.fit_power_law(2.0, K, N - 1)
+    sp = np.array([[0, 1], [0, 0]], dtype=np.complex128)
+    sm = sp.T.copy()
+    sz = np.array(pkg.PAULI_Z, dtype=np.complex128)
+    mpo = pkg.MPO.longrange(ctx, N, [(0.5, sp, sm), (0.5, sm, sp), (0.25, sz, sz)], c=c, lam=lam)
+    charges = [[0]] + [[0] + [1] * K + [-1] * K + [0] * K + [0]] * (N - 1) + [[0]]
+    mpo.set_charges(charges)
+    bits = [j % 2 for j in range(N)]
+    bits[31] ^= 1
+    up = np.cumsum([0] + [1 - b for b in bits])
+    grow = pkg.TDVPOptions(compute="c64", chi_max=chi, w_max=1e-10, eps_rel=1e-12, krylov_max=40, krylov_tol=1e-10)
+    m = pkg.MPS.init(ctx, N, 2, [1] * (N + 1), basis_state=bits)
+    m.set_charges([1, 0], [[int(u)] for u in up])
+    t_grow = 0.0
+    for k in range(200):
+        st = pkg.tdvp2_step(ctx, m, mpo, 0.1, grow)
+        t_grow += st["seconds"]
+        if (k + 1) % 5 == 0:
+            progress(f"U(1) quench growth: step {k + 1}, chi {max(m.chi)}, {st['seconds']:.3f} s")
+        if min(m.chi[24:41]) >= chi:
+            break
+    T, (qp, labels), chi_reached = m.tensors(), m.charges(), max(m.chi)
+    m.close()
+    opts = pkg.TDVPOptions(compute="c64", chi_max=chi, w_max=1e-10, eps_rel=1e-12, krylov_max=40, krylov_tol=1e-10)
+    res, prof = {"growth_steps": k + 1, "growth_seconds": round(t_grow, 1), "chi": chi_reached,
+                 "sectors_at_centre": len(set(labels[N // 2]))}, {}
+    for mode in ("dense", "u1"):
+        mpo.set_charges(charges if mode == "u1" else None)
+        times = []
+        for timed in (False, True):
+            x = pkg.MPS.from_tensors(ctx, T)
+            if mode == "u1":
+                x.set_charges(qp, labels)
+            for _ in range(steps if timed else 1):
+                st = pkg.tdvp2_step(ctx, x, mpo, 0.05, opts)
+                if timed:
+                    times.append(st["seconds"])
+            progress(f"chi={chi} sweep {mode} {'timed' if timed else 'tuning'} pass done")
+            if timed:
+                prof[mode] = 0.25 * pkg.expect(ctx, x, list(range(N)), sz).real
+                res[mode] = {"s_per_step": round(float(np.mean(times)), 3), "matvecs_last_step": st["matvecs"]}
+            x.close()
+    mpo.close()
+    res["speedup_u1_vs_dense"] = round(res["dense"]["s_per_step"] / res["u1"]["s_per_step"], 2)
+    res["max_abs_obs_diff_u1_vs_dense"] = float(np.max(np.abs(prof["u1"] - prof["dense"])))
+    res["workload"] = (f"2TDVP, N=64 XXX 1/r^2 sigma+- (K=6, w=20), state from the Neel + flip quench grown in "
+                       f"U(1) mode to chi={chi}; {steps} steps dt=0.05, complex64, dense vs U(1) "
+                       f"(block kernels from chi_l*chi_r >= 256^2)")
+    return res
+
+
 def segments_timing(pkg, ctx, np, graph=True, extras=True):
     """Segment-parallel 2TDVP, N=201 long-range XY (alpha 1.5, K = 6, w = 14),
     32 segments (11 | 6 x 30 | 10), uneven bond profile (one seeded draw in
@@ -605,6 +664,9 @@ def main():
     ap.add_argument("--only-u1", action="store_true", help="run only the U(1) block-sparse H_eff timing")
     ap.add_argument("--only-sweep-u1", action="store_true",
                     help="run only the N=64 quench sweep dense against U(1) blocks and print its timings")
+    ap.add_argument("--only-sweep-u1-large", type=int, default=0,
+                    help="run only the N=64 quench grown to this bond dimension in U(1) mode, then dense against "
+                         "U(1) steps from that state")
     ap.add_argument("--only-D", type=int, default=0,
                     help="run only the two-site H_eff timing at this bond dimension (both precisions; for profiling)")
     ap.add_argument("--only-grad", action="store_true",
@@ -633,6 +695,12 @@ def main():
     if args.only_u1:
         ctx = pkg.Context(0)
         print(json.dumps({"u1": {str(chi): u1_timing(pkg, ctx, torch, np, chi=chi) for chi in (64, 128, 256, 512)}}))
+        ctx.close()
+        return
+
+    if args.only_sweep_u1_large:
+        ctx = pkg.Context(0)
+        print(json.dumps({"sweep_u1_large": sweep_u1_large_timing(pkg, ctx, args.only_sweep_u1_large)}))
         ctx.close()
         return
 

@@ -339,12 +339,14 @@ struct Stepper {
     // truncated together by the rule of the dense split (Eq. discweight), and
     // the kept ones, ordered by charge (then by position in the sector),
     // label the new bond.  Sectors go the way the dense split goes: with the
-    // density-matrix rule a sector of order <= kJacobiMaxOrder takes the
-    // one-workgroup Jacobi eigen-decomposition of its reduced density matrix
-    // (queued without a read-back; one read-back of all sectors' values),
-    // any other sector an SVD.  Uall [rows][ktot] and Vall [ktot][cols]
-    // collect every sector's factors with the singular values already on the
-    // side that keeps them (site j + 1 unless centre_left).
+    // density-matrix rule every sector is decomposed through the eigenvectors
+    // of its reduced density matrix (orders <= kJacobiMaxOrder by the
+    // one-workgroup Jacobi, larger ones by the solver's divide and conquer),
+    // sigma taken as the norm of the projection; all of it is queued and read
+    // back once.  Otherwise each sector takes an SVD.
+    // Uall [rows][ktot] and Vall [ktot][cols] collect every sector's factors
+    // with the singular values already on the side that keeps them (site
+    // j + 1 unless centre_left).
     void split_u1(int j, double2* th, bool centre_left) {
         TxRange tx("split_u1");
         const int d = m->d, chil = m->chi[j], chir = m->chi[j + 2];
@@ -359,35 +361,45 @@ struct Stepper {
             for (int s1 = 0; s1 < d; ++s1) rsec[qa[a] + qs[s1]].push_back(a * d + s1);
         for (int s2 = 0; s2 < d; ++s2)
             for (int b = 0; b < chir; ++b) csec[qb[b] - qs[s2]].push_back(s2 * chir + b);
+        enum Path { JACOBI, SOLVER, SVD };
         struct Sec {
             int Q;
             const std::vector<int>* r;
             const std::vector<int>* c;
             int k, off;
-            bool jac;        // density-matrix Jacobi path
+            Path path;
+            int slot;        // SOLVER: slot in the solver's buffer
             int64_t ri, ci;  // offsets of the index lists in the device table
-            int64_t blk, G, vecs, P, T;  // arena offsets (complex elements), Jacobi path
+            int64_t blk, G, vecs, P, T;  // arena offsets (complex elements), density-matrix paths
             std::vector<double> s;
         };
         std::vector<Sec> secs;
         std::vector<int> idx;  // row lists, then column lists
-        int ktot = 0;
+        int ktot = 0, nb = 0, nmax = 0;
         int64_t arena = 0;
         for (const auto& kv : rsec) {
             auto it = csec.find(kv.first);
             if (it == csec.end()) continue;
             const int nr = (int)kv.second.size(), nc = (int)it->second.size();
-            Sec sc{kv.first, &kv.second, &it->second, 0, ktot, false, 0, 0, 0, 0, 0, 0, 0, {}};
+            Sec sc{kv.first, &kv.second, &it->second, 0, ktot, SVD, -1, 0, 0, 0, 0, 0, 0, 0, {}};
             const int n = left ? nr : nc;
-            sc.jac = gram && n <= kJacobiMaxOrder;
-            sc.k = sc.jac ? n : std::min(nr, nc);
-            if (sc.jac) {
+            if (gram) {
+                sc.path = n <= kJacobiMaxOrder ? JACOBI : SOLVER;
+                sc.k = n;
                 const int len = left ? nc : nr;
                 sc.blk = arena; arena += (int64_t)nr * nc;
-                sc.G = arena; arena += (int64_t)n * n;
+                if (sc.path == JACOBI) {
+                    sc.G = arena;
+                    arena += (int64_t)n * n;
+                } else {
+                    sc.slot = nb++;
+                    nmax = std::max(nmax, n);
+                }
                 sc.vecs = arena; arena += (int64_t)n * n;
                 sc.P = arena; arena += (int64_t)n * len;
                 sc.T = arena; arena += left ? (int64_t)nr * n : 0;
+            } else {
+                sc.k = std::min(nr, nc);
             }
             sc.ri = (int64_t)idx.size();
             idx.insert(idx.end(), kv.second.begin(), kv.second.end());
@@ -403,6 +415,9 @@ struct Stepper {
         double2* Vall = static_cast<double2*>(ctx->workspace("u1s_Vall", sizeof(double2) * (size_t)ktot * cols));
         double2* ar = static_cast<double2*>(ctx->workspace("u1s_arena", sizeof(double2) * (size_t)std::max<int64_t>(1, arena)));
         double* s2 = static_cast<double*>(ctx->workspace("u1s_s2", sizeof(double) * (size_t)ktot));
+        const int64_t slot_elems = (int64_t)nmax * nmax;
+        double2* Gb = nb ? static_cast<double2*>(ctx->workspace("u1s_geig", sizeof(double2) * (size_t)(nb * slot_elems)))
+                         : nullptr;
         TDVP_CHECK_HIP(hipMemcpyAsync(didx, idx.data(), sizeof(int) * nidx, hipMemcpyHostToDevice, ctx->stream));
         TDVP_CHECK_HIP(hipMemsetAsync(Uall, 0, sizeof(double2) * (size_t)rows * ktot, ctx->stream));
         TDVP_CHECK_HIP(hipMemsetAsync(Vall, 0, sizeof(double2) * (size_t)ktot * cols, ctx->stream));
@@ -411,43 +426,24 @@ struct Stepper {
             g.p = p; g.dt = Dt::C128; g.ld = ld; g.kcontig = kcontig; g.conj = conj;
             return g;
         };
+        // blocks and reduced density matrices; the small ones decomposed at once
         for (auto& sc : secs) {
             const int nr = (int)sc.r->size(), nc = (int)sc.c->size();
-            if (sc.jac) {
-                const int n = sc.k, len = left ? nc : nr;
-                double2 *blk = ar + sc.blk, *G = ar + sc.G, *V = ar + sc.vecs, *P = ar + sc.P;
+            if (sc.path != SVD) {
+                const int n = sc.k;
+                double2* blk = ar + sc.blk;
+                double2* G = sc.path == JACOBI ? ar + sc.G : Gb + sc.slot * slot_elems;
                 copy_idx(blk, nc, nullptr, nullptr, th, cols, didx + sc.ri, didx + sc.ci, nr, nc, ctx->stream);
-                GemmDesc g;  // reduced density matrix of the orthonormal side
-                g.M = n; g.N = n; g.cdt = Dt::C128; g.ldc = n; g.C = G;
+                GemmDesc g;
+                g.M = n; g.N = n; g.cdt = Dt::C128; g.ldc = sc.path == JACOBI ? n : nmax; g.C = G;
                 if (left) {  // G = B B^dag
                     g.K = nc; g.A = operand(blk, nc, true, false); g.B = operand(blk, nc, true, true);
                 } else {     // G = B^dag B
                     g.K = nr; g.A = operand(blk, nc, false, true); g.B = operand(blk, nc, false, false);
                 }
                 cgemm(ctx, g, true, 4);
-                jacobi_eigh_small(G, n, s2 + sc.off, V, nullptr, ctx->stream);  // row c of V = conj(vector c)
-                GemmDesc pg;  // the other side: U^dag B (left) or B V (right); its norms are the singular values
-                pg.cdt = Dt::C128; pg.C = P;
-                if (left) {
-                    pg.M = n; pg.N = nc; pg.K = nr; pg.ldc = nc;
-                    pg.A = operand(V, n, true, false); pg.B = operand(blk, nc, false, false);
-                } else {
-                    pg.M = nr; pg.N = n; pg.K = nc; pg.ldc = n;
-                    pg.A = operand(blk, nc, true, false); pg.B = operand(V, n, true, true);
-                }
-                cgemm(ctx, pg, true, 4);
-                vec_norms2(P, left ? nc : n, n, len, left, s2 + sc.off, ctx->stream);
-                if (left) {
-                    double2* T = ar + sc.T;  // T[i][c] = u_c[i]
-                    conj_transpose(T, n, V, n, n, nr, ctx->stream);
-                    copy_idx(Uall + sc.off, ktot, didx + sc.ri, nullptr, T, n, nullptr, nullptr, nr, n, ctx->stream);
-                    copy_idx(Vall + (int64_t)sc.off * cols, cols, nullptr, didx + sc.ci, P, nc, nullptr, nullptr, n, nc,
-                             ctx->stream);
-                } else {
-                    copy_idx(Vall + (int64_t)sc.off * cols, cols, nullptr, didx + sc.ci, V, n, nullptr, nullptr, n, nc,
-                             ctx->stream);
-                    copy_idx(Uall + sc.off, ktot, didx + sc.ri, nullptr, P, n, nullptr, nullptr, nr, n, ctx->stream);
-                }
+                if (sc.path == JACOBI)
+                    jacobi_eigh_small(G, n, s2 + sc.off, ar + sc.vecs, nullptr, ctx->stream);  // row c = conj(vector c)
                 continue;
             }
             double2* blk = static_cast<double2*>(ctx->workspace("u1s_blk", sizeof(double2) * (size_t)nr * nc));
@@ -462,12 +458,59 @@ struct Stepper {
                      ctx->stream);
             sc.s = r.S;
         }
-        // the Jacobi sectors' squared singular values, in one read-back
-        std::vector<double> hs2(ktot, 0.0);
-        if (std::any_of(secs.begin(), secs.end(), [](const Sec& x) { return x.jac; }))
-            ctx->read_back({{hs2.data(), s2, sizeof(double) * (size_t)ktot}});
+        // the larger ones by the solver; rows in ascending order, so the c-th
+        // largest of a sector of order n is row n - 1 - c of its slot
+        std::vector<int> orders;
+        for (const auto& sc : secs)
+            if (sc.path == SOLVER) orders.push_back(sc.k);
+        const int* info = nb ? heevd_slots(ctx, Gb, nmax, orders) : nullptr;
+        for (auto& sc : secs)
+            if (sc.path == SOLVER)
+                copy2d(ar + sc.vecs, sc.k, Gb + sc.slot * slot_elems + (int64_t)(sc.k - 1) * nmax, -(int64_t)nmax, sc.k,
+                       sc.k, 0, ctx->stream);
+        // the other side, U^dag B (left) or B V (right): its norms are the singular values
         for (auto& sc : secs) {
-            if (!sc.jac) continue;
+            if (sc.path == SVD) continue;
+            const int nr = (int)sc.r->size(), nc = (int)sc.c->size();
+            const int n = sc.k, len = left ? nc : nr;
+            double2 *blk = ar + sc.blk, *V = ar + sc.vecs, *P = ar + sc.P;
+            GemmDesc pg;
+            pg.cdt = Dt::C128; pg.C = P;
+            if (left) {
+                pg.M = n; pg.N = nc; pg.K = nr; pg.ldc = nc;
+                pg.A = operand(V, n, true, false); pg.B = operand(blk, nc, false, false);
+            } else {
+                pg.M = nr; pg.N = n; pg.K = nc; pg.ldc = n;
+                pg.A = operand(blk, nc, true, false); pg.B = operand(V, n, true, true);
+            }
+            cgemm(ctx, pg, true, 4);
+            vec_norms2(P, left ? nc : n, n, len, left, s2 + sc.off, ctx->stream);
+            if (left) {
+                double2* T = ar + sc.T;  // T[i][c] = u_c[i]
+                conj_transpose(T, n, V, n, n, nr, ctx->stream);
+                copy_idx(Uall + sc.off, ktot, didx + sc.ri, nullptr, T, n, nullptr, nullptr, nr, n, ctx->stream);
+                copy_idx(Vall + (int64_t)sc.off * cols, cols, nullptr, didx + sc.ci, P, nc, nullptr, nullptr, n, nc,
+                         ctx->stream);
+            } else {
+                copy_idx(Vall + (int64_t)sc.off * cols, cols, nullptr, didx + sc.ci, V, n, nullptr, nullptr, n, nc,
+                         ctx->stream);
+                copy_idx(Uall + sc.off, ktot, didx + sc.ri, nullptr, P, n, nullptr, nullptr, nr, n, ctx->stream);
+            }
+        }
+        // the density-matrix sectors' squared singular values (and the solver's codes) in one read-back
+        std::vector<double> hs2(ktot, 0.0);
+        std::vector<int> hinfo(nb, 0);
+        if (gram) {
+            if (nb)
+                ctx->read_back({{hs2.data(), s2, sizeof(double) * (size_t)ktot}, {hinfo.data(), info, sizeof(int) * (size_t)nb}});
+            else
+                ctx->read_back({{hs2.data(), s2, sizeof(double) * (size_t)ktot}});
+        }
+        for (int b = 0; b < nb; ++b)
+            TDVP_REQUIRE(hinfo[b] == 0, TDVP_E_SOLVER, "U(1) split: zheevd did not converge (info = " +
+                                                           std::to_string(hinfo[b]) + ")");
+        for (auto& sc : secs) {
+            if (sc.path == SVD) continue;
             sc.s.resize(sc.k);
             for (int c = 0; c < sc.k; ++c) {
                 const double v = hs2[sc.off + c];

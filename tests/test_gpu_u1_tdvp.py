@@ -95,6 +95,46 @@ def test_u1_two_site_quench_matches_dense_oracle(ctx, dt_, bmin):
     assert m.charges()[1][N] == [int(np.sum(1 - np.asarray(bits)))]
 
 
+def test_u1_large_sectors_match_dense_library_path(ctx):
+    """Sectors above the one-workgroup Jacobi order (their reduced density
+    matrices go through the solver's divide and conquer): a U(1)
+    state grown on the quench to chi ~ 170 at N = 16, then two steps dense and
+    two steps in U(1) mode (block kernels throughout) from that state; the
+    dense library path is the one the oracle pins elsewhere."""
+    import paper_1912_06127_amd as pkg
+    N = 16
+    W, _, bits = setup(ctx, N, 3)
+    m = pkg.MPS.init(ctx, N, 2, [1] * (N + 1), basis_state=bits)
+    m.set_charges(Q_SPIN, product_labels(bits))
+    grow = pkg.TDVPOptions(compute="c128", chi_max=192, w_max=1e-10, eps_rel=1e-12)
+    for s in range(60):
+        pkg.tdvp2_step(ctx, m, W, 0.2, grow)
+        if max(m.chi) >= 170:
+            break
+    print(f"grown in {s + 1} steps, chi {m.chi}", flush=True)
+    T, (qp, labels) = m.tensors(), m.charges()
+    m.close()
+    # a sector of some split has more than 64 rows or columns
+    big = max(max(np.unique(np.add.outer(labels[j], qp).ravel(), return_counts=True)[1]) for j in range(N))
+    assert big > 64, big
+    opts = pkg.TDVPOptions(compute="c128", chi_max=192, w_max=1e-10, eps_rel=1e-12, u1_block_min=1)
+    a = pkg.MPS.from_tensors(ctx, T)
+    b = pkg.MPS.from_tensors(ctx, T)
+    b.set_charges(qp, labels)
+    W.set_charges(None)
+    ia = [pkg.tdvp2_step(ctx, a, W, 0.05, opts) for _ in range(2)]
+    W.set_charges([[0]] + [[0] + [q for q in OP_CHARGE for _ in range(3)] + [0]] * (N - 1) + [[0]])
+    ib = [pkg.tdvp2_step(ctx, b, W, 0.05, opts) for _ in range(2)]
+    assert a.chi == b.chi
+    za = pkg.expect(ctx, a, list(range(N)), spin.SZ).real
+    zb = pkg.expect(ctx, b, list(range(N)), spin.SZ).real
+    assert np.max(np.abs(za - zb)) <= 1e-10, np.max(np.abs(za - zb))
+    assert abs(ia[-1]["w_total"] - ib[-1]["w_total"]) <= 1e-12 + 1e-8 * ia[-1]["w_total"]
+    check_charge_rule(b)
+    a.close()
+    b.close()
+
+
 def test_u1_dmrg_and_one_site_refusal(ctx):
     """Two-site DMRG in U(1) mode reaches the dense oracle's ground energy
     in the labelled sector; a one-site step refuses U(1) mode (its dense QR /
