@@ -134,6 +134,21 @@ def cpu_model() -> str:
     return "unknown"
 
 
+def gpu_state() -> dict | None:
+    """Clocks, power and temperature of GPU 0 as rocm-smi reports them (the
+    fields whose names mention a clock, power or temperature), or None."""
+    import subprocess
+    try:
+        r = subprocess.run(["rocm-smi", "-d", "0", "--showclocks", "--showpower", "--showtemp", "--json"],
+                           capture_output=True, text=True, timeout=30)
+        data = json.loads(r.stdout)
+    except (OSError, ValueError, subprocess.SubprocessError):
+        return None
+    card = next(iter(data.values()), {}) if isinstance(data, dict) else {}
+    keep = ("clk", "power", "temperature")
+    return {k: v for k, v in card.items() if any(t in k.lower() for t in keep)} or None
+
+
 def oracle_timings(wl, W, budget_s=20.0):
     """The FP64 oracle (numpy/scipy, complex128) timed on the host cores beside
     each GPU workload, on bounded samples of the same inputs.  Test
@@ -649,6 +664,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="headline kernel only (for profiling)")
+    ap.add_argument("--no-gpu-state", action="store_true",
+                    help="do not run rocm-smi for the clocks around the timed region (for runs under a profiler)")
     ap.add_argument("--sweep-steps", type=int, default=40)
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-segments", action="store_true", help="skip the segment-parallel N=201 step")
@@ -744,7 +761,9 @@ def main():
 
     progress("inputs ready; timing complex64 D=1024")
     x64 = device_inputs(torch, wl, W, D, w, torch.complex64)
+    state_before = None if args.no_gpu_state else gpu_state()
     ms64, prof64, _ = time_heff(pkg, ctx, torch, x64, args.steps, args.warmup, profile=True)
+    state_after = None if args.no_gpu_state else gpu_state()
     value = F / (ms64 * 1e-3) * 1e-9
     del x64
 
@@ -785,6 +804,7 @@ def main():
                                "complex64 on FP32 MFMA (3M)",
                    "D": D, "d": 2, "w": w, "parallelism": "single GPU"},
         "roofline": roofline,
+        "gpu_state": {"before_timed_region": state_before, "after_timed_region": state_after},
     }
 
     if not args.no_extras:
