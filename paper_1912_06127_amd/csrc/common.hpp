@@ -108,6 +108,7 @@ struct tdvp_ctx_s {
     size_t pinned_bytes = 0;
     void* pinned_rd = nullptr;                  // page-locked landing area of read_back
     size_t pinned_rd_bytes = 0;
+    std::shared_ptr<void> solver_lanes;         // worker lanes of the U(1) split's eigensolvers (tdvp.cpp)
     std::vector<tdvp_prof_rec> prof_pending;
     std::map<std::string, tdvp_prof_total> prof_total;
 

@@ -136,15 +136,14 @@ struct GramResult {
     int n;
 };
 GramResult gram_eigen(tdvp_ctx ctx, const double2* M, int rows, int cols, bool left);
-// Eigen-decompositions of several Hermitian matrices, queued one solver call
-// after another with nothing read back: slot b of G holds a row-major matrix
-// of order n[b] with leading dimension ld (slot stride ld * ld).  On return
-// row c of slot b is the conjugate of the eigenvector of its c-th smallest
-// eigenvalue.  Returns the device array of the solver info codes (0 =
-// converged).  (rocSOLVER's strided-batched divide and conquer was not used:
-// it returned non-finite eigenvectors for matrices zero-padded to a common
-// order, whose tridiagonal form splits.)
-const int* heevd_slots(tdvp_ctx ctx, double2* G, int ld, const std::vector<int>& n);
+// Eigen-decomposition of the Hermitian matrix of order n at G (row-major,
+// leading dimension ld) on the given handle (its stream), nothing read back:
+// on return row c is the conjugate of the eigenvector of the c-th smallest
+// eigenvalue; eigenvalues to ev, n-element scratch E, solver code to info
+// (0 = converged).  (rocSOLVER's strided-batched divide and conquer was not
+// used for several such matrices: it returned non-finite eigenvectors for
+// matrices zero-padded to a common order, whose tridiagonal form splits.)
+void heevd_slot(rocblas_handle h, double2* G, int ld, int n, double* ev, double* E, int* info);
 // Largest dense problems a context's solver calls will see: reserves the
 // device memory rocSOLVER needs for them (rocBLAS's device-memory size query)
 // and the named workspaces of the calls above, and installs that memory as

@@ -138,6 +138,7 @@ void tdvp_ctx_s::read_back(std::initializer_list<ReadSpan> spans) {
 }
 
 void tdvp_ctx_s::release_all() {
+    solver_lanes.reset();  // joins nothing: the lanes only run inside a split
     for (auto& sl : up_slot) {
         if (sl.ev) {
             if (sl.pending) (void)hipEventSynchronize(sl.ev);

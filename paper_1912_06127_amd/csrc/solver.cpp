@@ -173,18 +173,10 @@ GramResult gram_eigen(tdvp_ctx ctx, const double2* M, int rows, int cols, bool l
     return r;
 }
 
-const int* heevd_slots(tdvp_ctx ctx, double2* G, int ld, const std::vector<int>& n) {
-    const int count = (int)n.size();
-    double* ev = static_cast<double*>(ctx->workspace("heevds_ev", sizeof(double) * (size_t)ld * count));
-    double* E = static_cast<double*>(ctx->workspace("heevds_E", sizeof(double) * (size_t)ld * count));
-    int* info = static_cast<int*>(ctx->workspace("heevds_info", sizeof(int) * (size_t)count));
+void heevd_slot(rocblas_handle h, double2* G, int ld, int n, double* ev, double* E, int* info) {
     // row-major G is the column-major conj(G): the eigenvectors it returns in
     // columns are the conjugated eigenvectors of G, i.e. rows of the row-major view
-    for (int b = 0; b < count; ++b)
-        check_rs(rocsolver_zheevd(ctx->blas, rocblas_evect_original, rocblas_fill_upper, n[b],
-                                  rz(G + (size_t)b * ld * ld), ld, ev + (size_t)b * ld, E + (size_t)b * ld, info + b),
-                 "zheevd");
-    return info;
+    check_rs(rocsolver_zheevd(h, rocblas_evect_original, rocblas_fill_upper, n, rz(G), ld, ev, E, info), "zheevd");
 }
 
 }  // namespace tdvp

@@ -7,8 +7,12 @@
 #include <algorithm>
 #include <map>
 
+#include <atomic>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
+#include <exception>
+#include <thread>
 
 using namespace tdvp;
 
@@ -52,6 +56,106 @@ void env_u1(tdvp_ctx ctx, int dir, Dt dt, int chil, int chir, int d, int wl, int
 }  // namespace tdvp
 
 namespace {
+
+// Worker lanes for the per-sector eigensolvers of the U(1) split.  The
+// solver's divide and conquer is bound by its many small launches issued
+// from the host, so sectors decomposed from several host threads, each with
+// its own stream and rocBLAS handle, overlap on the GPU.  A lane owns only
+// its stream, handle and solver workspace (hipMalloc: the lanes never call
+// the context's allocator callback); the matrices, eigenvalues and codes it
+// writes are slots of buffers the owning thread allocated.
+struct SolverLane {
+    tdvp_ctx_s c;
+    hipEvent_t done = nullptr;
+    ~SolverLane() {
+        if (c.stream) (void)hipStreamSynchronize(c.stream);
+        c.release_all();
+        if (c.blas) rocblas_destroy_handle(c.blas);
+        if (c.stream) (void)hipStreamDestroy(c.stream);
+        if (done) (void)hipEventDestroy(done);
+    }
+};
+
+struct SolverLanes {
+    std::vector<std::unique_ptr<SolverLane>> lanes;
+    hipEvent_t ready = nullptr;
+    ~SolverLanes() {
+        lanes.clear();
+        if (ready) (void)hipEventDestroy(ready);
+    }
+};
+
+int solver_lane_count() {
+    const char* e = getenv("TDVP_U1_LANES");
+    const int n = e ? atoi(e) : 4;
+    return std::max(1, std::min(n, 16));
+}
+
+SolverLanes& solver_lanes(tdvp_ctx ctx, int n) {
+    if (!ctx->solver_lanes) ctx->solver_lanes = std::make_shared<SolverLanes>();
+    auto& P = *static_cast<SolverLanes*>(ctx->solver_lanes.get());
+    if (!P.ready) TDVP_CHECK_HIP(hipEventCreateWithFlags(&P.ready, hipEventDisableTiming));
+    while ((int)P.lanes.size() < n) {
+        auto L = std::make_unique<SolverLane>();
+        L->c.device = ctx->device;
+        L->c.alloc_fn = nullptr;
+        L->c.free_fn = nullptr;
+        L->c.user = nullptr;
+        TDVP_CHECK_HIP(hipStreamCreateWithFlags(&L->c.stream, hipStreamNonBlocking));
+        TDVP_REQUIRE(rocblas_create_handle(&L->c.blas) == rocblas_status_success, TDVP_E_HIP,
+                     "rocblas_create_handle failed");
+        rocblas_set_stream(L->c.blas, L->c.stream);
+        TDVP_CHECK_HIP(hipEventCreateWithFlags(&L->done, hipEventDisableTiming));
+        P.lanes.push_back(std::move(L));
+    }
+    return P;
+}
+
+// Eigen-decompositions of the slots of G (orders n[b], leading dimension ld)
+// after the work queued so far on the context stream; the context stream
+// waits for all of them.  ev, E: ld doubles per slot; info: one int per slot.
+void heevd_on_lanes(tdvp_ctx ctx, double2* G, int ld, const std::vector<int>& n, double* ev, double* E, int* info) {
+    const int count = (int)n.size();
+    const int nl = std::min(solver_lane_count(), count);
+    if (nl <= 1) {
+        for (int b = 0; b < count; ++b)
+            heevd_slot(ctx->blas, G + (size_t)b * ld * ld, ld, n[b], ev + (size_t)b * ld, E + (size_t)b * ld, info + b);
+        return;
+    }
+    SolverLanes& P = solver_lanes(ctx, nl);
+    SolverSizes ss;
+    ss.eig_n = *std::max_element(n.begin(), n.end());
+    for (int l = 0; l < nl; ++l) reserve_solver_workspace(&P.lanes[l]->c, ss);
+    std::vector<int> order(count);
+    for (int b = 0; b < count; ++b) order[b] = b;
+    std::sort(order.begin(), order.end(), [&](int a, int b) { return n[a] > n[b]; });  // largest first
+    TDVP_CHECK_HIP(hipEventRecord(P.ready, ctx->stream));
+    std::atomic<int> next{0};
+    std::vector<std::exception_ptr> errs(nl);
+    std::vector<std::thread> pool;
+    for (int l = 0; l < nl; ++l) {
+        pool.emplace_back([&, l] {
+            try {
+                SolverLane& L = *P.lanes[l];
+                TDVP_CHECK_HIP(hipSetDevice(L.c.device));
+                TDVP_CHECK_HIP(hipStreamWaitEvent(L.c.stream, P.ready, 0));
+                for (int t = next++; t < count; t = next++) {
+                    const int b = order[t];
+                    heevd_slot(L.c.blas, G + (size_t)b * ld * ld, ld, n[b], ev + (size_t)b * ld, E + (size_t)b * ld,
+                               info + b);
+                }
+                TDVP_CHECK_HIP(hipEventRecord(L.done, L.c.stream));
+            } catch (...) {
+                errs[l] = std::current_exception();
+            }
+        });
+    }
+    for (auto& t : pool) t.join();
+    for (int l = 0; l < nl; ++l)
+        if (!errs[l]) TDVP_CHECK_HIP(hipStreamWaitEvent(ctx->stream, P.lanes[l]->done, 0));
+    for (auto& e : errs)
+        if (e) std::rethrow_exception(e);
+}
 
 struct Stepper {
     tdvp_ctx ctx;
@@ -341,9 +445,9 @@ struct Stepper {
     // label the new bond.  Sectors go the way the dense split goes: with the
     // density-matrix rule every sector is decomposed through the eigenvectors
     // of its reduced density matrix (orders <= kJacobiMaxOrder by the
-    // one-workgroup Jacobi, larger ones by the solver's divide and conquer),
-    // sigma taken as the norm of the projection; all of it is queued and read
-    // back once.  Otherwise each sector takes an SVD.
+    // one-workgroup Jacobi, larger ones by the solver's divide and conquer,
+    // spread over worker lanes), sigma taken as the norm of the projection;
+    // all of it is queued and read back once.  Otherwise each sector takes an SVD.
     // Uall [rows][ktot] and Vall [ktot][cols] collect every sector's factors
     // with the singular values already on the side that keeps them (site
     // j + 1 unless centre_left).
@@ -463,7 +567,14 @@ struct Stepper {
         std::vector<int> orders;
         for (const auto& sc : secs)
             if (sc.path == SOLVER) orders.push_back(sc.k);
-        const int* info = nb ? heevd_slots(ctx, Gb, nmax, orders) : nullptr;
+        const int* info = nullptr;
+        if (nb) {
+            double* ev = static_cast<double*>(ctx->workspace("heevds_ev", sizeof(double) * (size_t)nmax * nb));
+            double* E = static_cast<double*>(ctx->workspace("heevds_E", sizeof(double) * (size_t)nmax * nb));
+            int* dinfo = static_cast<int*>(ctx->workspace("heevds_info", sizeof(int) * (size_t)nb));
+            heevd_on_lanes(ctx, Gb, nmax, orders, ev, E, dinfo);
+            info = dinfo;
+        }
         for (auto& sc : secs)
             if (sc.path == SOLVER)
                 copy2d(ar + sc.vecs, sc.k, Gb + sc.slot * slot_elems + (int64_t)(sc.k - 1) * nmax, -(int64_t)nmax, sc.k,
