@@ -508,6 +508,45 @@ def segments_timing(pkg, ctx, np, graph=True, extras=True):
     return res
 
 
+def segments_fp64_timing(pkg, ctx, np):
+    """The segment-parallel step of segments_timing with every contraction in
+    FP64 (complex128 environments and matvecs on the FP64 MFMA path): one
+    untimed step (tile tuning), then one timed eager step, for the FP32 / FP64
+    comparison at equal schedule and state."""
+    import workloads as wl
+    p = wl.XY_N201
+    N, sizes = p["N"], p["segments"]
+    chi = wl.segment_bond_profile(sizes, 2, p["chi_lo"], p["chi_hi"], p["seed_chi"])
+    T = wl.random_site_tensors(p["seed_state"], chi, 2)
+    c, lam, err = pkg.fit.fit_power_law(p["alpha"], p["K"], N - 1)
+    sx, sy = (np.array(q, dtype=np.complex128) for q in (pkg.PAULI_X, pkg.PAULI_Y))
+    mpo = pkg.MPO.longrange(ctx, N, [(0.5, sx, sx), (0.5, sy, sy)], c=c, lam=lam)
+    progress("segments FP64: building the inverse canonical state")
+    sg = pkg.Segments.init(ctx, mpo, T, sizes, compute="c128")
+    del T
+    eager = pkg.SegmentOptions(compute="c128")
+    progress("segments FP64: warm-up step (tile tuning)")
+    sg.step(mpo, p["dt"], eager)
+    progress("segments FP64: timed eager step")
+    ctx.profile(True)
+    st = sg.step(mpo, p["dt"], eager)
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    g = {k: v for k, v in prof.items() if k.startswith("cgemm2g")}
+    gms = sum(v["ms"] for v in g.values())
+    gfl = sum(v["flops"] for v in g.values())
+    res = {"s_per_step_eager": round(st["seconds"], 3), "step_tflops": round(st["flops"] / st["seconds"] * 1e-12, 2),
+           "grouped_gemm_tflops": round(gfl / (gms * 1e-3) * 1e-12, 2),
+           "grouped_gemm_frac_of_fp64_peak": round(gfl / (gms * 1e-3) * 1e-12 / PEAK_FP64_MFMA_TFLOPS, 4),
+           "batched_expm_s": round(prof.get("seg_batched_expm", {}).get("ms", 0.0) * 1e-3, 3),
+           "splits_s": round(prof.get("seg_splits", {}).get("ms", 0.0) * 1e-3, 3),
+           "w_total": sg.w_total,
+           "workload": "the segment-parallel N=201 step above with complex128 environments and matvecs (FP64 MFMA)"}
+    sg.close()
+    mpo.close()
+    return res
+
+
 def one_site_and_repair(pkg, ctx, sg, mpo, p, chi, res):
     """Norm drift, the serial repair and the one-site schedule on the state
     the two-site steps left."""
@@ -672,6 +711,8 @@ def main():
     ap.add_argument("--only-segments", action="store_true",
                     help="run only the segment-parallel N=201 workload and print its timings (for profiling)")
     ap.add_argument("--segments-no-graph", action="store_true", help="segment workload: eager steps only")
+    ap.add_argument("--only-segments-fp64", action="store_true",
+                    help="run only the segment-parallel N=201 step with FP64 contractions and print its timings")
     ap.add_argument("--segments-no-extras", action="store_true",
                     help="segment workload: skip the repair and the one-site schedule")
     ap.add_argument("--sweep-no-taylor", action="store_true", help="sweep workload: skip the Taylor-exponential pass")
@@ -743,6 +784,12 @@ def main():
             r[name] = {"gflops": round(heff2_flops(args.only_D, 10) / (msx * 1e-3) * 1e-9, 1), "ms": round(msx, 5)}
             del xs
         print(json.dumps({"heff_D": args.only_D, **r}))
+        ctx.close()
+        return
+
+    if args.only_segments_fp64:
+        ctx = pkg.Context(0)
+        print(json.dumps({"segments_fp64": segments_fp64_timing(pkg, ctx, np)}))
         ctx.close()
         return
 
