@@ -358,6 +358,15 @@ void small_normalize(const double2* x, double2* v, int64_t n, double* nn, hipStr
 // null).  All device pointers.
 constexpr int kJacobiMaxOrder = 64;
 void jacobi_eigh_small(const double2* G, int n, double* evals, double2* vecs, int* sweeps, hipStream_t s);
+// Thin QR of an m x n matrix (m >= n, n <= kQrMaxCols, m n <= kQrMaxElems) in one
+// workgroup (Householder reflectors in LDS, LAPACK's zgeqr2 / zung2r conventions).
+// herm = false: M row-major [m][n] = Q [m][n] R [n][n] (R upper); herm = true: M
+// row-major [n][m] = L [n][n] Q [n][m] (the LQ; L lower, rows of Q orthonormal),
+// written to RL and Q.  All device pointers; every output element is written.
+constexpr int kQrMaxCols = 64;
+constexpr int kQrMaxElems = 4096;
+bool qr_small_fits(int m, int n);
+void qr_small(const double2* M, int m, int n, bool herm, double2* Q, double2* RL, hipStream_t s);
 // w -= sum_j coef[j] V[j]   (coef device complex[nv])
 void axpy_multi(const double2* V, int64_t vstride, int nv, const double2* coef, double2* w,
                 int64_t n, hipStream_t s);

@@ -538,6 +538,135 @@ __global__ void __launch_bounds__(kSmallThreads) small_normalize_kernel(const do
 // stop when the off-diagonal mass is below 1e-30 of the diagonal mass, or
 // after 40 sweeps.  Outputs: eigenvalues in descending order and
 // the eigenvectors as conjugated rows (row c = conj of the c-th eigenvector).
+// ------------------------------------------------ small QR in one workgroup
+// Thin Householder QR of an m x n complex matrix B (m >= n) held in LDS, in
+// the reflector convention of LAPACK's zgeqr2 / zung2r: reflector k is
+// H_k = I - tau_k v v^H with v_k = 1, built so that H_k^H maps column k below
+// the diagonal onto beta_k e_k with real beta_k; B = Q R with Q = H_0 ... H_{n-1}
+// (first n columns) and R upper triangular.  One wave per column for the
+// reflector applications (lanes over rows, shuffle reductions).
+// herm = 0: B = M (row-major [m][n]); outputs Q [m][n] and R [n][n] (upper),
+// both row-major with leading dimension n.
+// herm = 1: B = M^H with M row-major [n][m] (the LQ of M = R^H Q^H); outputs
+// L = R^H [n][n] (lower, ld n) to RL and Q^H [n][m] (ld m) to Qout.
+constexpr int kQrThreads = 256;
+constexpr int kQrWaves = kQrThreads / 64;
+
+__device__ inline double2 qr_cmul(double2 a, double2 b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+__device__ inline double2 qr_cjmul(double2 a, double2 b) {  // conj(a) * b
+    return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+__device__ inline double2 qr_wave_sum(double2 v) {
+    for (int o = 32; o > 0; o >>= 1) {
+        v.x += __shfl_xor(v.x, o, 64);
+        v.y += __shfl_xor(v.y, o, 64);
+    }
+    return v;
+}
+
+__global__ void __launch_bounds__(kQrThreads) qr_small_kernel(const double2* __restrict__ M, int m, int n, int herm,
+                                                              double2* __restrict__ Qout, double2* __restrict__ RL) {
+    __shared__ double2 A[kQrMaxElems];
+    __shared__ double2 Q[kQrMaxElems];
+    __shared__ double2 tau[kQrMaxCols];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int e = tid; e < m * n; e += kQrThreads) {
+        const int i = e / n, j = e % n;
+        if (herm) {
+            const double2 x = M[(int64_t)j * m + i];
+            A[e] = make_double2(x.x, -x.y);
+        } else {
+            A[e] = M[(int64_t)i * n + j];
+        }
+        Q[e] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+    }
+    __syncthreads();
+    for (int k = 0; k < n; ++k) {
+        if (wave == 0) {
+            double xn = 0.0;  // squared norm of column k below the diagonal
+            for (int i = k + 1 + lane; i < m; i += 64) xn += A[i * n + k].x * A[i * n + k].x + A[i * n + k].y * A[i * n + k].y;
+            for (int o = 32; o > 0; o >>= 1) xn += __shfl_xor(xn, o, 64);
+            const double2 alpha = A[k * n + k];
+            double2 t = make_double2(0.0, 0.0), sc = make_double2(0.0, 0.0);
+            double beta = alpha.x;
+            const bool reflect = !(xn == 0.0 && alpha.y == 0.0);
+            if (reflect) {
+                beta = -copysign(sqrt(alpha.x * alpha.x + alpha.y * alpha.y + xn), alpha.x);
+                t = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+                // sc = 1 / (alpha - beta)
+                const double dr = alpha.x - beta, di = alpha.y, dd = dr * dr + di * di;
+                sc = make_double2(dr / dd, -di / dd);
+            }
+            for (int i = k + 1 + lane; i < m; i += 64) A[i * n + k] = reflect ? qr_cmul(A[i * n + k], sc) : A[i * n + k];
+            if (lane == 0) {
+                tau[k] = t;
+                if (reflect) A[k * n + k] = make_double2(beta, 0.0);
+            }
+        }
+        __syncthreads();
+        // columns j > k: A(k:m, j) -= conj(tau) v (v^H A(k:m, j))
+        const double2 tk = tau[k];
+        for (int j = k + 1 + wave; j < n; j += kQrWaves) {
+            double2 w = make_double2(0.0, 0.0);
+            for (int i = k + lane; i < m; i += 64) {
+                const double2 v = i == k ? make_double2(1.0, 0.0) : A[i * n + k];
+                const double2 p = qr_cjmul(v, A[i * n + j]);
+                w.x += p.x;
+                w.y += p.y;
+            }
+            w = qr_wave_sum(w);
+            const double2 f = qr_cjmul(tk, w);  // conj(tau) w
+            for (int i = k + lane; i < m; i += 64) {
+                const double2 v = i == k ? make_double2(1.0, 0.0) : A[i * n + k];
+                const double2 d = qr_cmul(v, f);
+                A[i * n + j].x -= d.x;
+                A[i * n + j].y -= d.y;
+            }
+        }
+        __syncthreads();
+    }
+    // Q = H_0 ... H_{n-1} I: reflectors applied from the last, columns j >= k
+    for (int k = n - 1; k >= 0; --k) {
+        const double2 tk = tau[k];
+        for (int j = k + wave; j < n; j += kQrWaves) {
+            double2 w = make_double2(0.0, 0.0);
+            for (int i = k + lane; i < m; i += 64) {
+                const double2 v = i == k ? make_double2(1.0, 0.0) : A[i * n + k];
+                const double2 p = qr_cjmul(v, Q[i * n + j]);
+                w.x += p.x;
+                w.y += p.y;
+            }
+            w = qr_wave_sum(w);
+            const double2 f = qr_cmul(tk, w);  // tau w
+            for (int i = k + lane; i < m; i += 64) {
+                const double2 v = i == k ? make_double2(1.0, 0.0) : A[i * n + k];
+                const double2 d = qr_cmul(v, f);
+                Q[i * n + j].x -= d.x;
+                Q[i * n + j].y -= d.y;
+            }
+        }
+        __syncthreads();
+    }
+    if (!herm) {
+        for (int e = tid; e < m * n; e += kQrThreads) Qout[e] = Q[e];
+        for (int e = tid; e < n * n; e += kQrThreads) {
+            const int r = e / n, c = e % n;
+            RL[e] = c >= r ? A[r * n + c] : make_double2(0.0, 0.0);
+        }
+    } else {
+        for (int e = tid; e < m * n; e += kQrThreads) {  // Q^H [n][m]
+            const int c = e / m, j = e % m;
+            const double2 q = Q[j * n + c];
+            Qout[e] = make_double2(q.x, -q.y);
+        }
+        for (int e = tid; e < n * n; e += kQrThreads) {  // L = R^H, lower
+            const int a = e / n, c = e % n;
+            const double2 r = A[c * n + a];
+            RL[e] = c <= a ? make_double2(r.x, -r.y) : make_double2(0.0, 0.0);
+        }
+    }
+}
+
 constexpr int kJacobiMax = kJacobiMaxOrder;
 constexpr int kJacobiThreads = 256;
 
@@ -1312,6 +1441,14 @@ void lanczos_small_step(double2* V, int64_t n, int k, double2* w, double beta_pr
 void small_normalize(const double2* x, double2* v, int64_t n, double* nn, hipStream_t s) {
     TDVP_REQUIRE(n <= kSmallLanczos, TDVP_E_ARG, "small_normalize: vector too long");
     hipLaunchKernelGGL(small_normalize_kernel, dim3(1), dim3(kSmallThreads), 0, s, x, v, n, nn);
+    TDVP_CHECK_HIP(hipGetLastError());
+}
+
+bool qr_small_fits(int m, int n) { return n >= 1 && m >= n && n <= kQrMaxCols && (int64_t)m * n <= kQrMaxElems; }
+
+void qr_small(const double2* M, int m, int n, bool herm, double2* Q, double2* RL, hipStream_t s) {
+    TDVP_REQUIRE(qr_small_fits(m, n), TDVP_E_SHAPE, "qr_small: matrix does not fit one workgroup");
+    hipLaunchKernelGGL(qr_small_kernel, dim3(1), dim3(kQrThreads), 0, s, M, m, n, herm ? 1 : 0, Q, RL);
     TDVP_CHECK_HIP(hipGetLastError());
 }
 

@@ -26,6 +26,10 @@ rocblas_double_complex* rz(double2* p) { return reinterpret_cast<rocblas_double_
 }  // namespace
 
 void qr_rowmajor(tdvp_ctx ctx, const double2* M, int rows, int cols, double2* Q, double2* R) {
+    if (qr_small_fits(rows, cols)) {  // rows >= cols: Q [rows][cols], R [cols][cols]
+        qr_small(M, rows, cols, false, Q, R, ctx->stream);
+        return;
+    }
     const int k = std::min(rows, cols);
     double2* work = static_cast<double2*>(ctx->workspace("qr_work", sizeof(double2) * (size_t)rows * cols));
     double2* tau = static_cast<double2*>(ctx->workspace("qr_tau", sizeof(double2) * (size_t)k));
@@ -40,6 +44,10 @@ void qr_rowmajor(tdvp_ctx ctx, const double2* M, int rows, int cols, double2* Q,
 }
 
 void lq_rowmajor(tdvp_ctx ctx, const double2* M, int rows, int cols, double2* L, double2* Q) {
+    if (qr_small_fits(cols, rows)) {  // rows <= cols: L [rows][rows], Q [rows][cols]
+        qr_small(M, cols, rows, true, Q, L, ctx->stream);
+        return;
+    }
     const int k = std::min(rows, cols);
     double2* work = static_cast<double2*>(ctx->workspace("qr_work", sizeof(double2) * (size_t)rows * cols));
     double2* tau = static_cast<double2*>(ctx->workspace("qr_tau", sizeof(double2) * (size_t)k));
