@@ -358,6 +358,15 @@ void small_normalize(const double2* x, double2* v, int64_t n, double* nn, hipStr
 // null).  All device pointers.
 constexpr int kJacobiMaxOrder = 64;
 void jacobi_eigh_small(const double2* G, int n, double* evals, double2* vecs, int* sweeps, hipStream_t s);
+// The same for several matrices in one launch, one workgroup each (the table
+// is uploaded without waiting, tdvp_ctx_s::upload).
+struct JacobiProb {
+    const double2* G;
+    double* evals;
+    double2* vecs;
+    int n, pad;
+};
+void jacobi_eigh_batched(tdvp_ctx ctx, const std::vector<JacobiProb>& probs);
 // Thin QR of an m x n matrix (m >= n, n <= kQrMaxCols, m n <= kQrMaxElems) in one
 // workgroup (Householder reflectors in LDS, LAPACK's zgeqr2 / zung2r conventions).
 // herm = false: M row-major [m][n] = Q [m][n] R [n][n] (R upper); herm = true: M

@@ -670,8 +670,8 @@ __global__ void __launch_bounds__(kQrThreads) qr_small_kernel(const double2* __r
 constexpr int kJacobiMax = kJacobiMaxOrder;
 constexpr int kJacobiThreads = 256;
 
-__global__ void __launch_bounds__(kJacobiThreads) jacobi_eigh_kernel(const double2* G, int n, double* evals,
-                                                                       double2* vecs, int* sweeps_out) {
+__device__ __forceinline__ void jacobi_eigh_body(const double2* G, int n, double* evals, double2* vecs,
+                                                 int* sweeps_out) {
     __shared__ double2 A[kJacobiMax * kJacobiMax];
     __shared__ double2 V[kJacobiMax * kJacobiMax];
     __shared__ double rc[kJacobiMax / 2], rs[kJacobiMax / 2], rpr[kJacobiMax / 2], rpi[kJacobiMax / 2];
@@ -786,6 +786,17 @@ __global__ void __launch_bounds__(kJacobiThreads) jacobi_eigh_kernel(const doubl
         }
     }
     if (tid == 0 && sweeps_out) *sweeps_out = sweep;
+}
+
+__global__ void __launch_bounds__(kJacobiThreads) jacobi_eigh_kernel(const double2* G, int n, double* evals,
+                                                                       double2* vecs, int* sweeps_out) {
+    jacobi_eigh_body(G, n, evals, vecs, sweeps_out);
+}
+
+// One workgroup per matrix of the table.
+__global__ void __launch_bounds__(kJacobiThreads) jacobi_eigh_batched_kernel(const JacobiProb* __restrict__ tab) {
+    const JacobiProb p = tab[blockIdx.x];
+    jacobi_eigh_body(p.G, p.n, p.evals, p.vecs, nullptr);
 }
 
 // ------------------------------------------------------------ FP64 vectors
@@ -1449,6 +1460,18 @@ bool qr_small_fits(int m, int n) { return n >= 1 && m >= n && n <= kQrMaxCols &&
 void qr_small(const double2* M, int m, int n, bool herm, double2* Q, double2* RL, hipStream_t s) {
     TDVP_REQUIRE(qr_small_fits(m, n), TDVP_E_SHAPE, "qr_small: matrix does not fit one workgroup");
     hipLaunchKernelGGL(qr_small_kernel, dim3(1), dim3(kQrThreads), 0, s, M, m, n, herm ? 1 : 0, Q, RL);
+    TDVP_CHECK_HIP(hipGetLastError());
+}
+
+void jacobi_eigh_batched(tdvp_ctx ctx, const std::vector<JacobiProb>& probs) {
+    if (probs.empty()) return;
+    for (const auto& p : probs)
+        TDVP_REQUIRE(p.n >= 1 && p.n <= kJacobiMax && p.G && p.evals && p.vecs, TDVP_E_ARG,
+                     "jacobi_eigh_batched: order out of range or null pointer");
+    auto* tab = static_cast<JacobiProb*>(ctx->workspace("jacobi_tab", sizeof(JacobiProb) * probs.size()));
+    ctx->upload(tab, probs.data(), sizeof(JacobiProb) * probs.size());
+    hipLaunchKernelGGL(jacobi_eigh_batched_kernel, dim3((unsigned)probs.size()), dim3(kJacobiThreads), 0, ctx->stream,
+                       tab);
     TDVP_CHECK_HIP(hipGetLastError());
 }
 

@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <exception>
+#include <functional>
 #include <thread>
 
 using namespace tdvp;
@@ -114,10 +115,14 @@ SolverLanes& solver_lanes(tdvp_ctx ctx, int n) {
 // Eigen-decompositions of the slots of G (orders n[b], leading dimension ld)
 // after the work queued so far on the context stream; the context stream
 // waits for all of them.  ev, E: ld doubles per slot; info: one int per slot.
-void heevd_on_lanes(tdvp_ctx ctx, double2* G, int ld, const std::vector<int>& n, double* ev, double* E, int* info) {
+// `meanwhile` runs on the calling thread while the lanes work (it may queue
+// independent work on the context stream).
+void heevd_on_lanes(tdvp_ctx ctx, double2* G, int ld, const std::vector<int>& n, double* ev, double* E, int* info,
+                    const std::function<void()>& meanwhile) {
     const int count = (int)n.size();
     const int nl = std::min(solver_lane_count(), count);
     if (nl <= 1) {
+        meanwhile();
         for (int b = 0; b < count; ++b)
             heevd_slot(ctx->blas, G + (size_t)b * ld * ld, ld, n[b], ev + (size_t)b * ld, E + (size_t)b * ld, info + b);
         return;
@@ -150,9 +155,16 @@ void heevd_on_lanes(tdvp_ctx ctx, double2* G, int ld, const std::vector<int>& n,
             }
         });
     }
+    std::exception_ptr own;
+    try {
+        meanwhile();
+    } catch (...) {
+        own = std::current_exception();
+    }
     for (auto& t : pool) t.join();
     for (int l = 0; l < nl; ++l)
         if (!errs[l]) TDVP_CHECK_HIP(hipStreamWaitEvent(ctx->stream, P.lanes[l]->done, 0));
+    if (own) std::rethrow_exception(own);
     for (auto& e : errs)
         if (e) std::rethrow_exception(e);
 }
@@ -530,7 +542,9 @@ struct Stepper {
             g.p = p; g.dt = Dt::C128; g.ld = ld; g.kcontig = kcontig; g.conj = conj;
             return g;
         };
-        // blocks and reduced density matrices; the small ones decomposed at once
+        // blocks and reduced density matrices (the small ones are decomposed
+        // together in one launch below, while the solver lanes work)
+        std::vector<JacobiProb> jprobs;
         for (auto& sc : secs) {
             const int nr = (int)sc.r->size(), nc = (int)sc.c->size();
             if (sc.path != SVD) {
@@ -546,8 +560,8 @@ struct Stepper {
                     g.K = nr; g.A = operand(blk, nc, false, true); g.B = operand(blk, nc, false, false);
                 }
                 cgemm(ctx, g, true, 4);
-                if (sc.path == JACOBI)
-                    jacobi_eigh_small(G, n, s2 + sc.off, ar + sc.vecs, nullptr, ctx->stream);  // row c = conj(vector c)
+                if (sc.path == JACOBI)  // row c of the vectors = conj(eigenvector c)
+                    jprobs.push_back(JacobiProb{G, s2 + sc.off, ar + sc.vecs, n, 0});
                 continue;
             }
             double2* blk = static_cast<double2*>(ctx->workspace("u1s_blk", sizeof(double2) * (size_t)nr * nc));
@@ -572,8 +586,10 @@ struct Stepper {
             double* ev = static_cast<double*>(ctx->workspace("heevds_ev", sizeof(double) * (size_t)nmax * nb));
             double* E = static_cast<double*>(ctx->workspace("heevds_E", sizeof(double) * (size_t)nmax * nb));
             int* dinfo = static_cast<int*>(ctx->workspace("heevds_info", sizeof(int) * (size_t)nb));
-            heevd_on_lanes(ctx, Gb, nmax, orders, ev, E, dinfo);
+            heevd_on_lanes(ctx, Gb, nmax, orders, ev, E, dinfo, [&] { jacobi_eigh_batched(ctx, jprobs); });
             info = dinfo;
+        } else {
+            jacobi_eigh_batched(ctx, jprobs);
         }
         for (auto& sc : secs)
             if (sc.path == SOLVER)
