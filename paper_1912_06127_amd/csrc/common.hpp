@@ -102,6 +102,7 @@ struct tdvp_ctx_s {
     uint64_t ws_gen = 0;                        // bumped whenever a workspace moves
     bool prof_on = false;                       // HIP event pair around every launch
     bool autotune = true;                       // time GEMM tiles per shape bucket
+    bool splitk = true;                         // GEMMs may split K (partial sums in a workspace)
     int gemm_form = 0;                          // raw-pointer calls: 0 default, 3 or 4
     std::map<int64_t, int> krylov_hint;         // Lanczos iterations last used per vector length
     void* pinned = nullptr;                     // page-locked host staging (pinned_host)

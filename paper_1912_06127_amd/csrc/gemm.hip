@@ -912,10 +912,11 @@ void cgemm(tdvp_ctx ctx, const GemmDesc& g, bool fp64, int form) {
         launch_cfg(ctx, kp, g.batch, fp64, m3, heuristic_cfg(g, fp64).cfg, 1);
         return;
     }
-    const Choice ch = choose_cfg(ctx, g, kp, fp64, m3);
+    Choice ch = choose_cfg(ctx, g, kp, fp64, m3);
+    if (!ctx->splitk) ch.ks = 1;
     if (!launch_cfg(ctx, kp, g.batch, fp64, m3, ch.cfg, ch.ks)) {
         const Choice h = heuristic_cfg(g, fp64);
-        launch_cfg(ctx, kp, g.batch, fp64, m3, h.cfg, h.ks);
+        launch_cfg(ctx, kp, g.batch, fp64, m3, h.cfg, ctx->splitk ? h.ks : 1);
     }
 }
 

@@ -495,6 +495,45 @@ struct SegRun {
         if (op.refresh & 1) env_buf(sg->beta[j + 1], (size_t)W->w[j + 1] * c * c);
         if (op.refresh & 2) env_buf(sg->gamma[j], (size_t)W->w[j + 1] * c * c);
     }
+    // The named workspaces a split on a lane asks for (its own, the
+    // environment refresh's and the small density-matrix path's), at their
+    // largest size over the phase, grown on the owning thread: a split on a
+    // lane then allocates nothing.  The solver's own buffers are reserved by
+    // reserve_solver_workspace.
+    void presize_lane_split(tdvp_ctx_s& c, const SPhase& ph) {
+        const int d = sg->d;
+        const size_t esz = elem_bytes(sg->edt);
+        size_t u = 1, sv = 1, k1 = 1, env = 1, gn = 0, gp = 1;
+        for (const auto& op : ph) {
+            const int j = op.j;
+            const size_t rows = (size_t)sg->chi[j] * d, cols = (size_t)d * sg->chi[j + 2], k = (size_t)split_cap(j);
+            const size_t wmax = (size_t)std::max({W->w[j], W->w[j + 1], W->w[j + 2]});
+            u = std::max(u, rows * k);
+            sv = std::max(sv, k * cols);
+            k1 = std::max(k1, k);
+            env = std::max(env, esz * wmax * std::max(rows, cols) * k);
+            const size_t n = std::min(rows, cols);
+            if (n <= (size_t)kJacobiMaxOrder) {
+                gn = std::max(gn, n);
+                gp = std::max(gp, n * std::max(rows, cols));
+            }
+        }
+        c.workspace("seg_U", sizeof(double2) * u);
+        c.workspace("seg_US", sizeof(double2) * u);
+        c.workspace("seg_SV", sizeof(double2) * sv);
+        c.workspace("seg_B", sizeof(double2) * sv);
+        c.workspace("seg_scal", sizeof(double) * k1);
+        c.workspace("env_X", env);
+        c.workspace("env_Y", env);
+        if (gn) {
+            c.workspace("gram_G", sizeof(double2) * gn * gn);
+            c.workspace("gram_vecs", sizeof(double2) * gn * gn);
+            c.workspace("gram_ev", sizeof(double) * gn);
+            c.workspace("gram_E", sizeof(double) * gn);
+            c.workspace("gram_info", sizeof(int));
+            c.workspace("gram_P", sizeof(double2) * gp);
+        }
+    }
     void presize_bond(const SOp& op) {
         const int j = op.j, c = sg->chi[j + 1];
         if (op.refresh == 1) env_buf(sg->beta[j + 1], (size_t)W->w[j + 1] * c * c);
@@ -710,7 +749,10 @@ struct SegRun {
             L->c.alloc_fn = nullptr;
             L->c.free_fn = nullptr;
             L->c.user = nullptr;
-            L->c.autotune = ctx->autotune;
+            // no tile timing and no K splits on a lane: both would allocate
+            // (candidate runs, split-K partials) from the worker thread
+            L->c.autotune = false;
+            L->c.splitk = false;
             TDVP_CHECK_HIP(hipStreamCreateWithFlags(&L->c.stream, hipStreamNonBlocking));
             TDVP_REQUIRE(rocblas_create_handle(&L->c.blas) == rocblas_status_success, TDVP_E_HIP,
                          "rocblas_create_handle failed");
@@ -783,7 +825,10 @@ struct SegRun {
             }
         }
         ensure_lanes(nl);
-        for (int l = 0; l < nl; ++l) reserve_solver_workspace(&sg->lanes[l]->c, ss);
+        for (int l = 0; l < nl; ++l) {
+            reserve_solver_workspace(&sg->lanes[l]->c, ss);
+            presize_lane_split(sg->lanes[l]->c, ph);
+        }
         std::vector<int> order(n);
         for (int i = 0; i < n; ++i) order[i] = i;
         std::sort(order.begin(), order.end(),
