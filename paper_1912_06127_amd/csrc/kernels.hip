@@ -744,29 +744,45 @@ __device__ __forceinline__ void jacobi_eigh_body(const double2* G, int n, double
                 rpi[tid] = ei;
             }
             __syncthreads();
-            // columns: col_p' = c col_p - s e^{-i phi} col_q, col_q' = s col_p + c e^{-i phi} col_q
-            for (int i = tid; i < half * m; i += kJacobiThreads) {
-                const int k = i / m, r = i % m;
-                const int p = rp[k], q = rq[k];
-                const double c = rc[k], sn = rs[k], er = rpr[k], ei = -rpi[k];  // e^{-i phi}
-                for (int which = 0; which < 2; ++which) {
-                    double2* M = which ? V : A;
-                    const double2 xp = M[r * m + p], xq = M[r * m + q];
+            // Column rotation of pair k (V and A): col_p' = c col_p - s e^{-i phi} col_q,
+            // col_q' = s col_p + c e^{-i phi} col_q; row rotation (A): row_p' = c row_p -
+            // s e^{i phi} row_q, row_q' = s row_p + c e^{i phi} row_q.  The pairs
+            // partition the indices, so A is updated block by block: the 2 x 2 block
+            // of pairs (P, Q) takes the column rotation of Q and then the row rotation
+            // of P, the same operations in the same order as a full column pass
+            // followed by a full row pass, with A read and written once.
+            for (int i = tid; i < half * half + half * m; i += kJacobiThreads) {
+                if (i < half * half) {
+                    const int P = i / half, Q = i % half;
+                    const int p1 = rp[P], p2 = rq[P], q1 = rp[Q], q2 = rq[Q];
+                    const double cq = rc[Q], sq = rs[Q], erq = rpr[Q], eiq = -rpi[Q];  // e^{-i phi_Q}
+                    const double cp = rc[P], sp = rs[P], erp = rpr[P], eip = rpi[P];   // e^{i phi_P}
+                    double2 x[2][2];
+                    const int rows2[2] = {p1, p2};
+                    for (int a = 0; a < 2; ++a) {  // column rotation of Q on rows p1, p2
+                        const int r = rows2[a];
+                        const double2 xp = A[r * m + q1], xq = A[r * m + q2];
+                        const double2 eq = make_double2(erq * xq.x - eiq * xq.y, erq * xq.y + eiq * xq.x);
+                        x[a][0] = make_double2(cq * xp.x - sq * eq.x, cq * xp.y - sq * eq.y);
+                        x[a][1] = make_double2(sq * xp.x + cq * eq.x, sq * xp.y + cq * eq.y);
+                    }
+                    const int cols2[2] = {q1, q2};
+                    for (int b = 0; b < 2; ++b) {  // then the row rotation of P
+                        const double2 xp = x[0][b], xq = x[1][b];
+                        const double2 eq = make_double2(erp * xq.x - eip * xq.y, erp * xq.y + eip * xq.x);
+                        A[p1 * m + cols2[b]] = make_double2(cp * xp.x - sp * eq.x, cp * xp.y - sp * eq.y);
+                        A[p2 * m + cols2[b]] = make_double2(sp * xp.x + cp * eq.x, sp * xp.y + cp * eq.y);
+                    }
+                } else {
+                    const int i2 = i - half * half;
+                    const int k = i2 / m, r = i2 % m;
+                    const int p = rp[k], q = rq[k];
+                    const double c = rc[k], sn = rs[k], er = rpr[k], ei = -rpi[k];  // e^{-i phi}
+                    const double2 xp = V[r * m + p], xq = V[r * m + q];
                     const double2 eq = make_double2(er * xq.x - ei * xq.y, er * xq.y + ei * xq.x);
-                    M[r * m + p] = make_double2(c * xp.x - sn * eq.x, c * xp.y - sn * eq.y);
-                    M[r * m + q] = make_double2(sn * xp.x + c * eq.x, sn * xp.y + c * eq.y);
+                    V[r * m + p] = make_double2(c * xp.x - sn * eq.x, c * xp.y - sn * eq.y);
+                    V[r * m + q] = make_double2(sn * xp.x + c * eq.x, sn * xp.y + c * eq.y);
                 }
-            }
-            __syncthreads();
-            // rows: row_p' = c row_p - s e^{i phi} row_q, row_q' = s row_p + c e^{i phi} row_q
-            for (int i = tid; i < half * m; i += kJacobiThreads) {
-                const int k = i / m, col = i % m;
-                const int p = rp[k], q = rq[k];
-                const double c = rc[k], sn = rs[k], er = rpr[k], ei = rpi[k];
-                const double2 xp = A[p * m + col], xq = A[q * m + col];
-                const double2 eq = make_double2(er * xq.x - ei * xq.y, er * xq.y + ei * xq.x);
-                A[p * m + col] = make_double2(c * xp.x - sn * eq.x, c * xp.y - sn * eq.y);
-                A[q * m + col] = make_double2(sn * xp.x + c * eq.x, sn * xp.y + c * eq.y);
             }
             __syncthreads();
         }
